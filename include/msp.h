@@ -1,0 +1,227 @@
+/*
+ * msp.h -- C-ABI of libmsp, a gfx950 (MI355X) implementation of the hot path of
+ * Multi-level Sketched Preconditioning (Derezinski, Musco, Yang, "Faster Linear
+ * Systems and Matrix Norm Approximation via Multi-level Sketched Preconditioning").
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers unless marked [host].
+ *   - Matrices are row-major with an explicit leading dimension (in elements).
+ *   - Blocks of k vectors (right-hand sides, solutions, probes) are stored as k
+ *     contiguous vectors: vector j starts at ptr + j * ld (ld >= vector length).
+ *   - Every call enqueues its device work on `stream` (hipStream_t passed as void*);
+ *     calls that fill [host] outputs synchronise the stream before returning.
+ *   - The caller owns all device memory, including the workspaces whose sizes the
+ *     *_workspace queries return; the library never allocates device memory.
+ *   - Errors: every call returns an msp_status; no call throws or aborts.
+ *     Arguments are validated before any device work is enqueued. msp_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - Determinism: identical inputs, seeds and device give bitwise-identical results
+ *     (all reductions run in a fixed order; no floating-point atomics).
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MSP_OK = 0,
+  MSP_ERR_INVALID_ARG = 1,   /* bad size, pointer, dtype or parameter */
+  MSP_ERR_NOT_POSDEF = 2,    /* a pivot of an SPD inverse was <= 0 */
+  MSP_ERR_BREAKDOWN = 3,     /* p^T A p <= 0 in a Krylov iteration */
+  MSP_ERR_NO_CONVERGENCE = 4,/* iteration cap reached; best iterate returned */
+  MSP_ERR_NONFINITE = 5,     /* NaN/Inf in an input scalar or a residual */
+  MSP_ERR_WORKSPACE = 6,     /* workspace too small or misaligned */
+  MSP_ERR_UNSUPPORTED = 7,   /* valid request outside what this build implements */
+  MSP_ERR_HIP = 8            /* a HIP runtime call failed */
+} msp_status;
+
+typedef enum { MSP_F64 = 0, MSP_F32 = 1, MSP_BF16 = 2 } msp_dtype;
+
+typedef enum {
+  MSP_SYM_PSD = 0,  /* (A + lam I) x = b with A symmetric PSD: Algorithms 1-2 (two levels) */
+  MSP_GENERAL = 1   /* (A^T A + lam I) x = c, or A x = b via c = A^T b: Algorithms 3-5 */
+} msp_structure;
+
+/* Opaque preconditioner handle (host memory). Its device data lives in the caller's
+ * sketch output Y and nystrom workspace, which must outlive the handle. */
+typedef struct msp_precond msp_precond;
+
+/* ---------------------------------------------------------------------------------
+ * msp_sketch -- sketch generation and the sparse sketch of A.
+ *
+ * Definition 2.1 (sparse embedding matrix): S in R^{s x n}; column i of S holds
+ * +-1/sqrt(gamma) in gamma distinct rows chosen uniformly without replacement, with
+ * independent signs. Algorithm 1 line 3 (PSD) and Algorithm 3 line 4 (general) form
+ * Y = A S^T (the paper's C, resp. A-tilde), one pass over A.
+ *
+ * The index draw is counter-based SplitMix64: column key k_i = fmix(seed + (i+1)G),
+ * draw a >= 0 u = fmix(k_i + (a+1)G) with G = 0x9E3779B97F4A7C15; candidate row
+ * floor(hi32(u) s / 2^32), sign -1 iff bit 0 of u is set; the first gamma distinct
+ * candidates are kept in draw order.
+ *
+ *   A        m x n, row-major, leading dim lda >= n, dtype a_t (F64 | F32 | BF16)
+ *   s, gamma sketch rows and nonzeros per column, 1 <= gamma <= s <= n
+ *   S_rows   out, int32 [n][gamma]     S_signs  out, int8 [n][gamma] (+1 / -1)
+ *   Y        out, m x s row-major, leading dim ldy >= s, dtype y_t (F64 | F32);
+ *            F64 Y requires F64 A. Sums run in y_t precision.
+ *   ws       device workspace of at least msp_sketch_workspace(...) bytes, 256-B aligned
+ * Asynchronous: returns after enqueueing.
+ * ------------------------------------------------------------------------------ */
+msp_status msp_sketch_workspace(int64_t m, int64_t n, int64_t s, int32_t gamma, size_t* bytes /*host*/);
+msp_status msp_sketch(void* stream, const void* A, msp_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                      int64_t s, int32_t gamma, uint64_t seed,
+                      int32_t* S_rows, int8_t* S_signs, void* Y, msp_dtype y_t, int64_t ldy,
+                      void* ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------------------------
+ * msp_nystrom -- the Nystrom factor and the inner-level preconditioners.
+ *
+ * MSP_SYM_PSD (Algorithm 1 lines 3-4; Section 4): lam~ = lam + lam0, W = S C
+ *   (symmetrised), C~ = Phi C with Phi a second sparse embedding (phi rows,
+ *   phi_gamma nonzeros per column, seed phi_seed), M2 = C~^T C~ + lam~ W, and the
+ *   explicit inverse M2^{-1} that Algorithm 1 precomputes.
+ * MSP_GENERAL (Algorithm 3 lines 2-6; Section 5): A^ = Phi A~ (Phi over the m rows),
+ *   M3a = A^^T A^, M3b = M3a + lam~ I and their explicit inverses.
+ * Every inverse is of (M + mu I), mu = 1e-12 tr(M)/s, by Gauss-Jordan elimination
+ * without pivoting (valid for SPD M: each pivot is a positive Schur-complement
+ * diagonal; a pivot <= 0 returns MSP_ERR_NOT_POSDEF).
+ *
+ *   m, n, s, gamma, S_rows, S_signs, Y, y_t, ldy   as produced by msp_sketch
+ *            (MSP_SYM_PSD needs m == n)
+ *   lambda   regulariser lam >= 0 of the user's system
+ *   lambda0  lam0 >= 0 of Theorems 3.1/4.1 (the paper's value is (2/l) sum_{i>l} lambda_i;
+ *            it is an explicit input, as in the algorithms' input lists); lam + lam0 > 0
+ *   phi, phi_gamma, phi_seed   the level-2/3 embedding, 1 <= phi_gamma <= phi
+ *   ws       device workspace of msp_nystrom_workspace(...) bytes; it holds the factors
+ *            and must outlive the handle
+ *   P        [host] out: the handle; free with msp_precond_destroy
+ * Synchronises once (to report MSP_ERR_NOT_POSDEF).
+ * ------------------------------------------------------------------------------ */
+msp_status msp_nystrom_workspace(msp_structure structure, int64_t m, int64_t n, int64_t s, int64_t phi,
+                                 int32_t phi_gamma, size_t* bytes /*host*/);
+msp_status msp_nystrom(void* stream, msp_structure structure, int64_t m, int64_t n, int64_t s, int32_t gamma,
+                       const int32_t* S_rows, const int8_t* S_signs, const void* Y, msp_dtype y_t, int64_t ldy,
+                       double lambda, double lambda0, int64_t phi, int32_t phi_gamma, uint64_t phi_seed,
+                       void* ws, size_t ws_bytes, msp_precond** P /*host out*/);
+msp_status msp_precond_destroy(msp_precond* P);
+/* Copy the handle's s x s factors into caller buffers (device, s*s doubles each, any may
+ * be NULL): W = S C (PSD) and M2^{-1} (PSD) or M3a^{-1} (general), and M3b^{-1}
+ * (general). For inspection and tests; asynchronous. */
+msp_status msp_precond_factors(void* stream, const msp_precond* P, double* W, double* Minv, double* Minv2);
+/* Change lam (and hence lam~ = lam + lam0) of an existing handle. For MSP_GENERAL this
+ * refactors M3b = M3a + lam~ I (the nodes of msp_schatten); for MSP_SYM_PSD it refactors M2. */
+msp_status msp_precond_set_lambda(void* stream, msp_precond* P, double lambda);
+
+/* ---------------------------------------------------------------------------------
+ * msp_solve -- the preconditioned iteration (Algorithm 1 line 5 with Algorithm 2;
+ * Algorithm 3 line 7 with Algorithms 4-5).
+ *
+ * Level 1 is flexible PCG (Polak-Ribiere beta) on (A + lam I) (PSD) or A^T A + lam I
+ * (general); with an exact preconditioner it coincides with Algorithm 6 (Section 6).
+ * SolveM1 (Algorithms 2/4) runs a level-2 flexible PCG to relative residual inner_tol
+ * (at most max_inner steps) and returns (r - C y)/lam~; for MSP_GENERAL its
+ * preconditioner SolveM2 (Algorithm 5) runs two level-3 PCGs in the product form
+ * W^{-1}((W + lam~ I)^{-1} r), each to level3_tol.
+ * Stop: per right-hand side, |b - (A + lam I) x| <= tol |b| (PSD) or |b - A x| <= tol |b|
+ * (general, lam == 0 and `normal` == 0) or |c - (A^T A + lam I) x| <= tol |c| (general,
+ * `normal` != 0), taken on the recurrence residual and confirmed on the residual
+ * recomputed in FP64 from A_hi (restart from it if the confirmation fails).
+ *
+ * Mixed precision: A_lo (dtype lo_t) is the matrix swept inside MSP with accumulation
+ * in FP64 (lo_t F64) or FP32 (lo_t F32/BF16); A_hi (hi_t) is used for the FP64
+ * residuals. If refine != 0 and lo_t != F64, the solve runs FP64 iterative refinement:
+ * x += MSP_lo(b - (A_hi + lam I) x) with each inner MSP solve to refine_inner_tol;
+ * after two steps that fail to halve the residual it switches to Krylov refinement
+ * (flexible PCG on A_hi with MSP_lo as preconditioner). A_hi may equal A_lo.
+ *
+ *   B        k right-hand sides (PSD: n each, general: m each), ld ldb, FP64
+ *   X        out, k solutions of length n, ld ldx, FP64
+ *   info     [host] out, may be NULL
+ * Synchronises the stream before returning.
+ * ------------------------------------------------------------------------------ */
+typedef struct {
+  double tol;              /* level-1 relative residual target (default 1e-8) */
+  int32_t max_outer;       /* level-1 iteration cap (default 5000) */
+  double inner_tol;        /* level-2 relative residual target (default 1e-10) */
+  int32_t max_inner;       /* level-2 iteration cap per SolveM1 (default 200) */
+  double level3_tol;       /* level-3 relative residual target (default 1e-10) */
+  int32_t max_level3;      /* level-3 iteration cap (default 200) */
+  int32_t normal;          /* general only: solve (A^T A + lam I) x = B instead of A x = B */
+  int32_t refine;          /* FP64 iterative refinement around a low-precision sweep */
+  double refine_inner_tol; /* inner MSP target per refinement step (default 1e-6) */
+  int32_t max_refine;      /* refinement step cap (default 30) */
+} msp_solve_opts;
+
+typedef struct {
+  msp_status status;
+  int32_t outer_iters;      /* level-1 iterations (max over right-hand sides) */
+  int64_t inner_iters;      /* level-2 iterations, summed over SolveM1 calls */
+  int64_t level3_iters;     /* level-3 iterations, summed */
+  int32_t refine_steps;     /* FP64 refinement steps taken (0 without refinement) */
+  int32_t krylov_refine;    /* 1 if refinement switched to its Krylov form */
+  int32_t restarts;         /* confirmation failures that restarted level 1 */
+  double rel_residual_max;  /* max over RHS of the FP64 relative residual at exit */
+  double sweep_bytes;       /* algorithmic bytes of A read by all level-1/2 sweeps */
+  int64_t sweeps;           /* number of passes over A (per block of k RHS) */
+} msp_solve_info;
+
+void msp_solve_opts_default(msp_solve_opts* o /*host*/);
+msp_status msp_solve_workspace(const msp_precond* P, int64_t k, const msp_solve_opts* opts, size_t* bytes /*host*/);
+msp_status msp_solve(void* stream, const msp_precond* P,
+                     const void* A_hi, msp_dtype hi_t, const void* A_lo, msp_dtype lo_t, int64_t lda,
+                     const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx,
+                     const msp_solve_opts* opts, void* ws, size_t ws_bytes, msp_solve_info* info /*host*/);
+
+/* ---------------------------------------------------------------------------------
+ * msp_solve_backward -- adjoint of X = (A + lam I)^{-1} B for symmetric PSD A.
+ *
+ * Given G = dL/dX: dB = (A + lam I)^{-T} G = (A + lam I)^{-1} G (A symmetric), solved
+ * with the same handle and iteration as msp_solve; dlambda = -sum_j <dB_j, X_j>;
+ * dA = -dB X^T, written densely (n x n, ld ldda) only when dA != NULL.
+ *   dlambda  [host] out, may be NULL
+ * MSP_GENERAL handles return MSP_ERR_UNSUPPORTED.
+ * ------------------------------------------------------------------------------ */
+msp_status msp_solve_backward(void* stream, const msp_precond* P,
+                              const void* A_hi, msp_dtype hi_t, const void* A_lo, msp_dtype lo_t, int64_t lda,
+                              const double* X, int64_t ldx, const double* G, int64_t ldg, int64_t k,
+                              double* dB, int64_t lddb, double* dlambda /*host*/, double* dA, int64_t ldda,
+                              const msp_solve_opts* opts, void* ws, size_t ws_bytes, msp_solve_info* info /*host*/);
+
+/* ---------------------------------------------------------------------------------
+ * msp_schatten -- spectral sums through ridge solves (Section 3.2, Theorem 3.3).
+ *
+ * MSP_TRACE_SCHATTEN_P: ||A||_p^p = tr((A^T A)^{p/2}), 0 < p < 2, from
+ *   (sin(pi p/2)/pi) int_0^inf t^{p/2-1} tr(A^T A (A^T A + t I)^{-1}) dt with t = e^u,
+ *   trapezoid nodes u_j = u_lo + j h <= u_hi, and Hutchinson's estimator over the probe
+ *   block G: per probe and node <A g, A x>, x = (A^T A + t_j I)^{-1} g solved by the
+ *   three-level MSP of P (an MSP_GENERAL handle; lam~ = t_j + lam0 per node).
+ * MSP_TRACE_EFFDIM: d_lam = tr(A (A + lam I)^{-1}) = mean_k (g^T g - lam g^T x),
+ *   x = (A + lam I)^{-1} g by the two-level MSP of P (an MSP_SYM_PSD handle); `p` is lam.
+ *   G        N probes of length n, ld ldg, FP64
+ *   estimate, std_err  [host] out (std_err: standard error over probes)
+ * Synchronises the stream before returning.
+ * ------------------------------------------------------------------------------ */
+typedef enum { MSP_TRACE_SCHATTEN_P = 0, MSP_TRACE_EFFDIM = 1 } msp_trace_kind;
+msp_status msp_schatten_workspace(const msp_precond* P, int64_t nprobes, const msp_solve_opts* opts,
+                                  size_t* bytes /*host*/);
+msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precond* P,
+                        const void* A_hi, msp_dtype hi_t, const void* A_lo, msp_dtype lo_t, int64_t lda,
+                        double p, const double* G, int64_t ldg, int64_t nprobes,
+                        double h, double u_lo, double u_hi, const msp_solve_opts* opts,
+                        void* ws, size_t ws_bytes, double* estimate /*host*/, double* std_err /*host*/,
+                        msp_solve_info* info /*host*/);
+
+/* Thread-local description of the last failure (empty string if none). */
+const char* msp_last_error(void);
+/* Library version string. */
+const char* msp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSP_H */

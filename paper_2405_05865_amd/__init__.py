@@ -1,0 +1,291 @@
+"""MI355X (gfx950) implementation of the hot path of Multi-level Sketched
+Preconditioning (Derezinski, Musco, Yang): the sparse sketch Y = A S^T, the Nystrom
+preconditioner with its inner levels, and the multi-level preconditioned iteration.
+
+This module is argument marshalling over the C-ABI library libmsp.so
+(include/msp.h); every step of the method runs in hand-written HIP kernels. Torch
+supplies device memory and the current stream. If the library is missing, every call
+raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _binding as B
+from ._binding import MspError, SolveInfo, SolveOpts  # noqa: F401
+
+__all__ = ["sketch", "Precond", "nystrom", "solve", "solve_backward", "schatten", "effective_dimension",
+           "MSPSolve", "msp_solve", "library", "MspError", "SolveOpts"]
+
+_DT = {torch.float64: B.MSP_F64, torch.float32: B.MSP_F32, torch.bfloat16: B.MSP_BF16}
+
+
+def library():
+    """The loaded ctypes library (raises if libmsp.so has not been built)."""
+    return B.load()
+
+
+def _code(t: torch.Tensor) -> int:
+    if t.dtype not in _DT:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return _DT[t.dtype]
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _rowmajor(A: torch.Tensor, name: str):
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D row-major tensor (unit column stride)")
+    if not A.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+
+
+def _workspace(nbytes: int, dev) -> torch.Tensor:
+    ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + int(nbytes)] if nbytes else ws[off:off + 1]
+
+
+def _vectors(X: torch.Tensor, length: int, name: str):
+    """(length,) or (k, length) float64 CUDA tensor with unit inner stride -> (k, ld)."""
+    if X.dtype != torch.float64 or not X.is_cuda:
+        raise ValueError(f"{name} must be a float64 CUDA tensor")
+    if X.dim() == 1:
+        if X.shape[0] != length or X.stride(0) != 1:
+            raise ValueError(f"{name} must have length {length} and unit stride")
+        return 1, length
+    if X.dim() != 2 or X.shape[1] != length or X.stride(1) != 1:
+        raise ValueError(f"{name} must be (k, {length}) with unit inner stride")
+    return X.shape[0], X.stride(0)
+
+
+def _opts(**kw) -> SolveOpts:
+    L = library()
+    o = SolveOpts()
+    L.msp_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if v is None:
+            continue
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, int(v) if isinstance(getattr(o, k), int) else float(v))
+    return o
+
+
+# -----------------------------------------------------------------------------------
+# msp_sketch
+# -----------------------------------------------------------------------------------
+def sketch(A: torch.Tensor, s: int, gamma: int, seed: int, y_dtype: torch.dtype | None = None):
+    """S (Definition 2.1) and Y = A S^T. Returns (S_rows int32 [n, gamma],
+    S_signs int8 [n, gamma], Y [m, s])."""
+    L = library()
+    _rowmajor(A, "A")
+    m, n = A.shape
+    if y_dtype is None:
+        y_dtype = torch.float64 if A.dtype == torch.float64 else torch.float32
+    rows = torch.empty((n, gamma), dtype=torch.int32, device=A.device)
+    signs = torch.empty((n, gamma), dtype=torch.int8, device=A.device)
+    Y = torch.empty((m, s), dtype=y_dtype, device=A.device)
+    need = B.size_out()
+    B.check(L.msp_sketch_workspace(m, n, s, gamma, ctypes.byref(need)))
+    ws = _workspace(need.value, A.device)
+    B.check(L.msp_sketch(_stream(A.device), A.data_ptr(), _code(A), m, n, A.stride(0), s, gamma,
+                         ctypes.c_uint64(seed & (2 ** 64 - 1)), rows.data_ptr(), signs.data_ptr(), Y.data_ptr(),
+                         _code(Y), Y.stride(0), ws.data_ptr(), ws.numel()))
+    return rows, signs, Y
+
+
+# -----------------------------------------------------------------------------------
+# msp_nystrom
+# -----------------------------------------------------------------------------------
+class Precond:
+    """Handle of the Nystrom preconditioner and its inner levels (msp_nystrom)."""
+
+    def __init__(self, structure: str, S_rows, S_signs, Y, lam: float, lam0: float, phi: int, phi_gamma: int,
+                 phi_seed: int):
+        L = library()
+        self.structure = structure
+        code = B.MSP_SYM_PSD if structure == "psd" else B.MSP_GENERAL
+        _rowmajor(Y, "Y")
+        m, s = Y.shape
+        n, gamma = S_rows.shape
+        self.m, self.n, self.s, self.gamma = m, n, s, gamma
+        self.phi, self.phi_gamma = phi, phi_gamma
+        self.lam, self.lam0 = float(lam), float(lam0)
+        need = B.size_out()
+        B.check(L.msp_nystrom_workspace(code, m, n, s, phi, phi_gamma, ctypes.byref(need)))
+        self._ws = _workspace(need.value, Y.device)
+        self._keep = (S_rows, S_signs, Y)
+        self.device = Y.device
+        h = ctypes.c_void_p()
+        B.check(L.msp_nystrom(_stream(Y.device), code, m, n, s, gamma, S_rows.data_ptr(), S_signs.data_ptr(),
+                              Y.data_ptr(), _code(Y), Y.stride(0), float(lam), float(lam0), phi, phi_gamma,
+                              ctypes.c_uint64(phi_seed & (2 ** 64 - 1)), self._ws.data_ptr(), self._ws.numel(),
+                              ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def Y(self):
+        return self._keep[2]
+
+    def factors(self):
+        """(W or None, M2^{-1} or M3a^{-1}, M3b^{-1} or None) as s x s float64 tensors."""
+        s = self.s
+        mk = lambda: torch.empty((s, s), dtype=torch.float64, device=self.device)
+        W = mk() if self.structure == "psd" else None
+        Mi = mk()
+        M2 = mk() if self.structure != "psd" else None
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        B.check(library().msp_precond_factors(_stream(self.device), self.handle, ptr(W), ptr(Mi), ptr(M2)))
+        torch.cuda.current_stream(self.device).synchronize()
+        return W, Mi, M2
+
+    def set_lambda(self, lam: float):
+        B.check(library().msp_precond_set_lambda(_stream(self.device), self.handle, float(lam)))
+        self.lam = float(lam)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            library().msp_precond_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nystrom(structure, S_rows, S_signs, Y, lam, lam0, phi, phi_gamma, phi_seed) -> Precond:
+    return Precond(structure, S_rows, S_signs, Y, lam, lam0, phi, phi_gamma, phi_seed)
+
+
+# -----------------------------------------------------------------------------------
+# msp_solve / msp_solve_backward
+# -----------------------------------------------------------------------------------
+def solve(P: Precond, A_hi: torch.Tensor, Bv: torch.Tensor, A_lo: torch.Tensor | None = None, **opts):
+    """X solving the system of P's structure for the right-hand sides Bv ((n,) or (k, n)).
+    Returns (X, info dict)."""
+    L = library()
+    A_lo = A_hi if A_lo is None else A_lo
+    _rowmajor(A_hi, "A_hi")
+    _rowmajor(A_lo, "A_lo")
+    if A_hi.stride(0) != A_lo.stride(0):
+        raise ValueError("A_hi and A_lo must share the leading dimension")
+    o = _opts(**opts)
+    blen = P.m if (P.structure == "general" and not o.normal) else P.n
+    k, ldb = _vectors(Bv, blen, "B")
+    X = torch.empty((k, P.n) if Bv.dim() == 2 else (P.n,), dtype=torch.float64, device=Bv.device)
+    need = B.size_out()
+    B.check(L.msp_solve_workspace(P.handle, k, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, Bv.device)
+    info = SolveInfo()
+    code = L.msp_solve(_stream(Bv.device), P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(), _code(A_lo),
+                       A_hi.stride(0), Bv.data_ptr(), ldb, k, X.data_ptr(), P.n, ctypes.byref(o), ws.data_ptr(),
+                       ws.numel(), ctypes.byref(info))
+    if code not in (0, 3, 4):
+        B.check(code)
+    d = info.as_dict()
+    d["code"] = B.STATUS.get(code, code)
+    return X, d
+
+
+def solve_backward(P: Precond, A_hi, X, G, A_lo=None, want_dA: bool = False, **opts):
+    """Adjoint of X = (A + lam I)^{-1} B for PSD A. Returns (dB, dlam, dA or None, info)."""
+    L = library()
+    A_lo = A_hi if A_lo is None else A_lo
+    o = _opts(**opts)
+    k, ldx = _vectors(X, P.n, "X")
+    k2, ldg = _vectors(G, P.n, "G")
+    if k != k2:
+        raise ValueError("X and G differ in the number of vectors")
+    dB = torch.empty_like(G, memory_format=torch.contiguous_format)
+    dA = torch.empty((P.n, P.n), dtype=torch.float64, device=G.device) if want_dA else None
+    dl = ctypes.c_double(0.0)
+    need = B.size_out()
+    B.check(L.msp_solve_workspace(P.handle, k, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, G.device)
+    info = SolveInfo()
+    code = L.msp_solve_backward(_stream(G.device), P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(),
+                                _code(A_lo), A_hi.stride(0), X.data_ptr(), ldx, G.data_ptr(), ldg, k, dB.data_ptr(),
+                                P.n, ctypes.byref(dl), dA.data_ptr() if dA is not None else None, P.n,
+                                ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(info))
+    if code not in (0, 3, 4):
+        B.check(code)
+    return dB, dl.value, dA, info.as_dict()
+
+
+def schatten(P: Precond, A_hi, probes, p: float = 1.0, A_lo=None, h: float = 1.5, u_lo: float = float("nan"),
+             u_hi: float = float("nan"), kind: str = "schatten", **opts):
+    """Hutchinson + quadrature estimate of ||A||_p^p (kind "schatten", P general) or of
+    d_lam (kind "effdim", P psd; p is lam). Returns (estimate, std_err, info)."""
+    L = library()
+    A_lo = A_hi if A_lo is None else A_lo
+    o = _opts(**opts)
+    N, ldg = _vectors(probes, P.n, "probes")
+    need = B.size_out()
+    B.check(L.msp_schatten_workspace(P.handle, N, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, probes.device)
+    est, se = ctypes.c_double(), ctypes.c_double()
+    info = SolveInfo()
+    kc = B.MSP_TRACE_SCHATTEN_P if kind == "schatten" else B.MSP_TRACE_EFFDIM
+    B.check(L.msp_schatten(_stream(probes.device), kc, P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(),
+                           _code(A_lo), A_hi.stride(0), float(p), probes.data_ptr(), ldg, N, float(h), float(u_lo),
+                           float(u_hi), ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(est),
+                           ctypes.byref(se), ctypes.byref(info)))
+    return est.value, se.value, info.as_dict()
+
+
+def effective_dimension(P: Precond, A_hi, probes, lam: float, **opts):
+    return schatten(P, A_hi, probes, p=lam, kind="effdim", **opts)
+
+
+# -----------------------------------------------------------------------------------
+# convenience: the whole path in one call, and the autograd wrapper
+# -----------------------------------------------------------------------------------
+@dataclass
+class SketchParams:
+    s: int
+    gamma: int = 8
+    phi: int | None = None
+    phi_gamma: int = 8
+    seed: int = 0
+    phi_seed: int = 1
+
+
+def msp_solve(A: torch.Tensor, Bv: torch.Tensor, lam: float, lam0: float, sp: SketchParams, A_lo=None,
+              structure: str = "psd", **opts):
+    """sketch -> nystrom -> solve. Returns (X, info, precond)."""
+    A_sk = A if A_lo is None else A_lo
+    rows, signs, Y = sketch(A_sk, sp.s, sp.gamma, sp.seed)
+    P = Precond(structure, rows, signs, Y, lam, lam0, sp.phi or 4 * sp.s, sp.phi_gamma, sp.phi_seed)
+    X, info = solve(P, A, Bv, A_lo=A_lo, **opts)
+    return X, info, P
+
+
+class MSPSolve(torch.autograd.Function):
+    """X = (A + lam I)^{-1} B for symmetric PSD A through MSP, with the adjoint solve
+    (msp_solve_backward) reusing the same preconditioner."""
+
+    @staticmethod
+    def forward(ctx, A, Bv, lam, P, opts):
+        X, info = solve(P, A, Bv, **opts)
+        ctx.save_for_backward(A, X)
+        ctx.P = P
+        ctx.opts = opts
+        ctx.info = info
+        return X
+
+    @staticmethod
+    def backward(ctx, G):
+        A, X = ctx.saved_tensors
+        want_dA = ctx.needs_input_grad[0]
+        dB, dlam, dA, _ = solve_backward(ctx.P, A, X, G.contiguous(), want_dA=want_dA, **ctx.opts)
+        dl = torch.tensor(dlam, dtype=torch.float64, device=G.device) if ctx.needs_input_grad[2] else None
+        return dA, dB, dl, None, None

@@ -1,0 +1,274 @@
+// Small dense FP64 work on s x s matrices: the Gram products C~^T C~ and A^^T A^
+// (Algorithm 1 line 4, Algorithm 3 line 5), symmetric combinations, and the explicit
+// SPD inverses M2^{-1}, M3a^{-1}, M3b^{-1} the algorithms precompute.
+//
+// The inverse is computed by block Gauss-Jordan sweeps without pivoting. For SPD M
+// every pivot block is a Schur complement of M, hence SPD, so no pivoting is needed;
+// a non-positive pivot flags the matrix as not positive definite.
+#include "msp_internal.h"
+
+namespace {
+
+constexpr int TILE = 64;
+constexpr int KCH = 16;
+
+// Gram partial: G_part[z] = X[rows of split z]^T X[rows of split z], lower tiles, mirrored
+__global__ void __launch_bounds__(256) k_gram(const double* __restrict__ X, int64_t rows, int64_t s, int64_t ldx,
+                                              int64_t rows_per_split, double* __restrict__ Gp) {
+  // map blockIdx.x to a lower tile (ti >= tj)
+  int t = blockIdx.x, ti = 0;
+  while (t > ti) { t -= ti + 1; ++ti; }
+  const int tj = t;
+  const int64_t i0 = (int64_t)ti * TILE, j0 = (int64_t)tj * TILE;
+  const int64_t rb = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t re = min(rows, rb + rows_per_split);
+  __shared__ double As[KCH][TILE + 1];
+  __shared__ double Bs[KCH][TILE + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int64_t k0 = rb; k0 < re; k0 += KCH) {
+    for (int e = threadIdx.x; e < KCH * TILE; e += 256) {
+      const int kk = e / TILE, c = e % TILE;
+      const int64_t r = k0 + kk;
+      As[kk][c] = (r < re && i0 + c < s) ? X[r * ldx + i0 + c] : 0.0;
+      Bs[kk][c] = (r < re && j0 + c < s) ? X[r * ldx + j0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KCH; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[kk][ty * 4 + q];
+        b[q] = Bs[kk][tx * 4 + q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+    }
+    __syncthreads();
+  }
+  double* G = Gp + (int64_t)blockIdx.y * s * s;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = i0 + ty * 4 + p, j = j0 + tx * 4 + q;
+      if (i < s && j < s) {
+        G[i * s + j] = acc[p][q];
+        G[j * s + i] = acc[p][q];
+      }
+    }
+}
+
+__global__ void k_sum_splits(const double* __restrict__ Gp, int splits, int64_t len, double* __restrict__ G) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double acc = 0.0;
+  for (int z = 0; z < splits; ++z) acc += Gp[(int64_t)z * len + i];
+  G[i] = acc;
+}
+
+// out = sym(a P + b Q) + c I, one thread per unordered pair (safe in place)
+__global__ void k_combine_sym(int64_t s, double a, const double* P, double b, const double* Q, double c,
+                              double* out) {
+  const int64_t i = blockIdx.y * (int64_t)blockDim.y + threadIdx.y;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= s || j >= s || j > i) return;
+  double v = 0.5 * a * (P[i * s + j] + P[j * s + i]);
+  if (Q) v += 0.5 * b * (Q[i * s + j] + Q[j * s + i]);
+  if (i == j) v += c;
+  out[i * s + j] = v;
+  out[j * s + i] = v;
+}
+
+__global__ void k_trace(int64_t s, const double* __restrict__ M, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < s; i += 256) acc += M[i * s + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_add_diag_scaled(int64_t s, double* M, const double* tr, double rel) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < s) M[i * s + i] += rel * (*tr) / (double)s;
+}
+
+// One block Gauss-Jordan sweep over pivots [k0, k0 + nbk). Tile of 64 x 64 per block.
+template <int NB>
+__global__ void __launch_bounds__(256) k_bgj_step(const double* __restrict__ in, double* __restrict__ out, int s,
+                                                  int k0, int32_t* status) {
+  __shared__ double P[NB][NB + 1];     // pivot block, inverted in place
+  __shared__ double Lk[TILE][NB + 1];  // in[I, K]
+  __shared__ double Uk[NB][TILE + 1];  // in[K, J], then P^{-1} in[K, J]
+  __shared__ double rowp[NB], colp[NB];
+  __shared__ int bad;
+  const int nbk = min(NB, s - k0);
+  const int I = blockIdx.y * TILE, J = blockIdx.x * TILE;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  for (int e = t; e < NB * NB; e += 256) {
+    const int a = e / NB, b = e % NB;
+    P[a][b] = (a < nbk && b < nbk) ? in[(int64_t)(k0 + a) * s + k0 + b] : (a == b ? 1.0 : 0.0);
+  }
+  for (int e = t; e < TILE * NB; e += 256) {
+    const int a = e / NB, b = e % NB;
+    const int i = I + a;
+    Lk[a][b] = (i < s && b < nbk) ? in[(int64_t)i * s + k0 + b] : 0.0;
+  }
+  for (int e = t; e < NB * TILE; e += 256) {
+    const int a = e / TILE, b = e % TILE;
+    const int j = J + b;
+    Uk[a][b] = (j < s && a < nbk) ? in[(int64_t)(k0 + a) * s + j] : 0.0;
+  }
+  __syncthreads();
+  // unblocked Gauss-Jordan on the pivot block
+  for (int p = 0; p < NB; ++p) {
+    const double piv = P[p][p];
+    if (t < NB) {
+      rowp[t] = P[p][t];
+      colp[t] = P[t][p];
+    }
+    if (t == 0 && !(piv > 0.0)) bad = 1;
+    __syncthreads();
+    const double ip = 1.0 / piv;
+    for (int e = t; e < NB * NB; e += 256) {
+      const int a = e / NB, b = e % NB;
+      double v;
+      if (a == p && b == p) v = ip;
+      else if (a == p) v = rowp[b] * ip;
+      else if (b == p) v = -colp[a] * ip;
+      else v = P[a][b] - colp[a] * rowp[b] * ip;
+      P[a][b] = v;
+    }
+    __syncthreads();
+  }
+  if (t == 0 && bad && blockIdx.x == 0 && blockIdx.y == 0) *status = 1;
+  // Uk <- P^{-1} Uk
+  {
+    double tmp[(NB * TILE + 255) / 256];
+    int q = 0;
+    for (int e = t; e < NB * TILE; e += 256, ++q) {
+      const int a = e / TILE, b = e % TILE;
+      double acc = 0.0;
+      for (int c = 0; c < NB; ++c) acc = fma(P[a][c], Uk[c][b], acc);
+      tmp[q] = acc;
+    }
+    __syncthreads();
+    q = 0;
+    for (int e = t; e < NB * TILE; e += 256, ++q) Uk[e / TILE][e % TILE] = tmp[q];
+    __syncthreads();
+  }
+  const bool rows_hit = (I < k0 + nbk) && (I + TILE > k0);
+  const bool cols_hit = (J < k0 + nbk) && (J + TILE > k0);
+  for (int e = t; e < TILE * TILE; e += 256) {
+    const int a = e / TILE, b = e % TILE;
+    const int i = I + a, j = J + b;
+    if (i >= s || j >= s) continue;
+    const bool ik = rows_hit && i >= k0 && i < k0 + nbk;
+    const bool jk = cols_hit && j >= k0 && j < k0 + nbk;
+    double v;
+    if (ik && jk) {
+      v = P[i - k0][j - k0];
+    } else if (ik) {
+      v = Uk[i - k0][b];
+    } else if (jk) {
+      double acc = 0.0;
+      for (int c = 0; c < NB; ++c) acc = fma(Lk[a][c], P[c][j - k0], acc);
+      v = -acc;
+    } else {
+      double acc = 0.0;
+      for (int c = 0; c < NB; ++c) acc = fma(Lk[a][c], Uk[c][b], acc);
+      v = in[(int64_t)i * s + j] - acc;
+    }
+    out[(int64_t)i * s + j] = v;
+  }
+}
+
+__global__ void k_copy(int64_t len, const double* __restrict__ a, double* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < len) b[i] = a[i];
+}
+
+// symmetrise the final inverse (rounding leaves it nearly symmetric)
+__global__ void k_sym_avg(int64_t s, double* M) {
+  const int64_t i = blockIdx.y * (int64_t)blockDim.y + threadIdx.y;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= s || j >= s || j >= i) return;
+  const double v = 0.5 * (M[i * s + j] + M[j * s + i]);
+  M[i * s + j] = v;
+  M[j * s + i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_gram(hipStream_t st, const double* X, int64_t rows, int64_t s, int64_t ldx, double* G,
+                       double* part, int splits) {
+  const int nt = (int)((s + TILE - 1) / TILE);
+  const int tiles = nt * (nt + 1) / 2;
+  const int64_t rps = ((rows + splits - 1) / splits + KCH - 1) / KCH * KCH;
+  double* dst = (splits == 1) ? G : part;
+  hipLaunchKernelGGL(k_gram, dim3(tiles, splits), dim3(256), 0, st, X, rows, s, ldx, rps, dst);
+  if (splits > 1) {
+    const int64_t len = s * s;
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, part, splits, len, G);
+  }
+  return hipGetLastError();
+}
+
+int gram_splits(int64_t rows, int64_t s) {
+  const int nt = (int)((s + TILE - 1) / TILE);
+  const int tiles = nt * (nt + 1) / 2;
+  int splits = (512 + tiles - 1) / tiles;
+  const int64_t max_by_rows = (rows + 255) / 256;
+  if (splits > max_by_rows) splits = (int)max_by_rows;
+  if (splits < 1) splits = 1;
+  if (splits > 16) splits = 16;
+  return splits;
+}
+
+hipError_t launch_combine_sym(hipStream_t st, int64_t s, double a, const double* P, double b, const double* Q,
+                              double c, double* out) {
+  dim3 blk(16, 16), grd((unsigned)((s + 15) / 16), (unsigned)((s + 15) / 16));
+  hipLaunchKernelGGL(k_combine_sym, grd, blk, 0, st, s, a, P, b, Q, c, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(hipStream_t st, int64_t s, double* Wm) {
+  return launch_combine_sym(st, s, 1.0, Wm, 0.0, nullptr, 0.0, Wm);
+}
+
+hipError_t launch_trace(hipStream_t st, int64_t s, const double* M, double* out) {
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, st, s, M, out);
+  return hipGetLastError();
+}
+
+hipError_t spd_inverse(hipStream_t st, int64_t s, double* M, double* tmp, double shift_rel, double* scal,
+                       int32_t* status) {
+  constexpr int NB = 32;
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, st, s, M, scal);
+  hipLaunchKernelGGL(k_add_diag_scaled, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, M, scal, shift_rel);
+  const int nt = (int)((s + TILE - 1) / TILE);
+  double* a = M;
+  double* b = tmp;
+  for (int k0 = 0; k0 < s; k0 += NB) {
+    hipLaunchKernelGGL(k_bgj_step<NB>, dim3(nt, nt), dim3(256), 0, st, a, b, (int)s, k0, status);
+    double* t = a;
+    a = b;
+    b = t;
+  }
+  if (a != M) {
+    const int64_t len = s * s;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, a, M);
+  }
+  dim3 blk(16, 16), grd((unsigned)((s + 15) / 16), (unsigned)((s + 15) / 16));
+  hipLaunchKernelGGL(k_sym_avg, grd, blk, 0, st, s, M);
+  return hipGetLastError();
+}

@@ -1,0 +1,196 @@
+// Internal declarations shared by the HIP translation units of libmsp.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "msp.h"
+
+#define MSP_CHECK_HIP(expr)                                                        \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) return msp_fail_hip(_e, #expr, __FILE__, __LINE__);      \
+  } while (0)
+
+msp_status msp_fail(msp_status st, const char* fmt, ...);
+msp_status msp_fail_hip(hipError_t e, const char* what, const char* file, int line);
+
+// ---------------------------------------------------------------------------------
+// Workspace carving: 256-byte aligned bump allocator over a caller-owned buffer.
+// ---------------------------------------------------------------------------------
+struct WsCarver {
+  char* base;
+  size_t cap;
+  size_t off = 0;
+  bool dry;  // size query only
+  WsCarver(void* b, size_t c) : base((char*)b), cap(c), dry(b == nullptr) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    T* p = dry ? nullptr : (T*)(base + off);
+    off += bytes;
+    return p;
+  }
+  bool ok() const { return dry || off <= cap; }
+};
+
+// ---------------------------------------------------------------------------------
+// Sketch kernels (k_sketch.hip)
+// ---------------------------------------------------------------------------------
+// Bucket lists of a sparse embedding: for each sketch row j, the (column, sign)
+// entries with S[j, col] != 0 in increasing column order. Entry = (col << 1) | neg.
+struct BucketLists {
+  int32_t* offsets;  // [rows + 1]
+  int32_t* entries;  // [n * gamma]
+};
+size_t bucket_scratch_bytes(int64_t n, int64_t rows, int32_t gamma);
+hipError_t launch_sketch_gen(hipStream_t st, uint64_t seed, int64_t n, int64_t s, int32_t gamma,
+                             int32_t* rows, int8_t* signs);
+hipError_t build_buckets(hipStream_t st, const int32_t* rows, const int8_t* signs, int64_t n, int64_t nrows,
+                         int32_t gamma, BucketLists out, void* scratch);
+// Y = A S^T with scale 1/sqrt(gamma): out[r, j] = scale * sum_{entries of bucket j} sign * A[r, col]
+hipError_t launch_sketch_apply(hipStream_t st, const void* A, msp_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                               int64_t s, BucketLists b, double scale, void* Y, msp_dtype y_t, int64_t ldy);
+// out[j, :] = scale * sum_{entries of bucket j} sign * X[col, :]   (out is F64, nrows x ncols)
+hipError_t launch_gather_rows(hipStream_t st, const void* X, msp_dtype x_t, int64_t ldx, int64_t ncols,
+                              int64_t nrows, BucketLists b, double scale, double* out, int64_t ldo);
+
+// ---------------------------------------------------------------------------------
+// Small dense FP64 kernels (k_dense.hip)
+// ---------------------------------------------------------------------------------
+// G = X^T X (X: rows x s row-major, F64), full symmetric result; the row range is split
+// `splits` ways (part: splits*s*s doubles when splits > 1) and summed in fixed order.
+int gram_splits(int64_t rows, int64_t s);
+hipError_t launch_gram(hipStream_t st, const double* X, int64_t rows, int64_t s, int64_t ldx, double* G,
+                       double* part, int splits);
+// out = sym(a*P + b*Q) + c*I  (P, Q may alias out; Q may be null)
+hipError_t launch_combine_sym(hipStream_t st, int64_t s, double a, const double* P, double b, const double* Q,
+                              double c, double* out);
+hipError_t launch_symmetrize(hipStream_t st, int64_t s, double* Wm);
+// trace(M) -> *out (device scalar)
+hipError_t launch_trace(hipStream_t st, int64_t s, const double* M, double* out);
+// In-place inverse of SPD M (s x s) by Gauss-Jordan sweeps, shifted by
+// mu = shift_rel * trace / s; tmp: s*s doubles; status: device int (0 ok, 1 not PD).
+// Result lands in M.
+hipError_t spd_inverse(hipStream_t st, int64_t s, double* M, double* tmp, double shift_rel,
+                       double* scal /*2 doubles*/, int32_t* status);
+
+// ---------------------------------------------------------------------------------
+// Sweep kernels (k_sweep.hip)
+// ---------------------------------------------------------------------------------
+// Y[:, j] = A X[:, j] + lam * X[:, j] (lam applied only if diag_shift) for j < k.
+// `skip` (device, per column; may be null): columns with skip[j] != 0 are left alone.
+// If dot_part != null, each block writes sum_r X[r,j] * Y[r,j] into dot_part[block*k + j]
+// and the number of blocks is returned in *nblocks (host).
+hipError_t launch_gemv(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,
+                       const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
+                       bool diag_shift, const int32_t* skip, double* dot_part, int* nblocks);
+// Y[:, j] = A^T X[:, j]  (A rows x cols row-major; X length rows; Y length cols)
+// part: scratch of gemv_t_part_doubles(rows, cols, k) doubles
+size_t gemv_t_part_doubles(int64_t rows, int64_t cols, int64_t k);
+hipError_t launch_gemv_t(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,
+                         const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip,
+                         double* part);
+
+// ---------------------------------------------------------------------------------
+// Tall-skinny kernels on Y (n x s) and reductions (k_tall.hip)
+// ---------------------------------------------------------------------------------
+int tall_blocks(int64_t rows);
+// part[blk][j][c] = sum_{rows r of blk} Y[r, c] * V[r, j]   (Y^T V partials), V n x k (ld ldv)
+hipError_t launch_yt_v(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_t s, int64_t ldy,
+                       const double* V, int64_t ldv, int64_t k, const int32_t* skip, double* part);
+// part[blk][j][c] = sum_r Y[r, c] * (Y[r, :] . Z[:, j])       (Y^T Y Z partials), Z s x k (ld s)
+hipError_t launch_yty_z(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_t s, int64_t ldy,
+                        const double* Z, int64_t k, const int32_t* skip, double* part);
+// out[:, j] = (a * V[:, j] + b * Y Z[:, j]) for j < k (Z s x k, ld s); out n x k (ld ldo)
+hipError_t launch_y_z(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_t s, int64_t ldy,
+                      const double* Z, int64_t k, double a, const double* V, int64_t ldv, double b,
+                      const int32_t* skip, double* out, int64_t ldo);
+// out[j][c] = sum_b part[b][j][c]  (fixed order)
+hipError_t launch_reduce_parts(hipStream_t st, const double* part, int nparts, int64_t len, double* out);
+// out[i, j] = sum_c M[i, c] * V[c, j] for s x s M (row-major), V s x k (ld s)
+hipError_t launch_small_mv(hipStream_t st, int64_t s, const double* M, const double* V, int64_t k,
+                           const int32_t* skip, double* out);
+
+// ---------------------------------------------------------------------------------
+// Flexible-PCG state machine kernels (k_fcg.hip). A level works on k columns of
+// vectors of length len stored contiguously (column j at ptr + j*len). Per-column
+// scalars live in device arrays; reductions use per-block partials summed in fixed
+// block order by the last block to finish (deterministic).
+// done[j]: 0 active, 1 converged (recurrence), 2 breakdown, 3 iteration cap,
+//          4 converged and confirmed on the recomputed residual.
+// ---------------------------------------------------------------------------------
+struct FcgState {
+  double* rz;
+  double* alpha;
+  double* beta;
+  double* bnorm;
+  double* rnorm;
+  int32_t* done;
+  int32_t* iters;
+  int32_t* active;   // [1]
+  int32_t* counter;  // [1] last-block ticket (reset by the last block)
+  double* part;      // per-block partials, >= fcg_part_doubles(len, k)
+  int64_t k;
+};
+size_t fcg_part_doubles(int64_t len, int64_t k);
+FcgState carve_fcg_state(WsCarver& w, int64_t len, int64_t k);
+// r = b, x = 0, bnorm; done = parent_done || |b| == 0; mirror <- active count
+hipError_t fcg_init(hipStream_t st, FcgState S, int64_t len, const double* b, int64_t ldb, double* r, double* x,
+                    const int32_t* parent_done, int32_t* mirror);
+// p = z, rz = <r, z>   (columns not done)
+hipError_t fcg_first_dir(hipStream_t st, FcgState S, int64_t len, const double* r, const double* z, double* p);
+// alpha = rz / pq with pq = sum of nparts per-block partials (layout part[b*k + j])
+hipError_t fcg_alpha_parts(hipStream_t st, FcgState S, const double* pq_part, int nparts);
+// alpha = rz / <p, q> computed directly (short vectors)
+hipError_t fcg_alpha_dot(hipStream_t st, FcgState S, int64_t len, const double* p, const double* q);
+// x += alpha p; r_old = r; r -= alpha q; |r| -> done by tol / max_iter; mirror <- active
+hipError_t fcg_update(hipStream_t st, FcgState S, int64_t len, double* x, double* r, double* r_old,
+                      const double* p, const double* q, double tol, int32_t max_iter, int32_t* mirror);
+// beta = <z, r - r_old> / rz ; rz = <r, z> ; p = z + beta p
+hipError_t fcg_direction(hipStream_t st, FcgState S, int64_t len, const double* r, const double* r_old,
+                         const double* z, double* p);
+// confirmation on rtrue = b - op(x) for columns with done == 1: done -> 4 if |rtrue| <= tol |b|,
+// else r = rtrue, done -> 0 (restart). relres[j] (device) receives |rtrue| / |b|; mirror <- active
+hipError_t fcg_confirm(hipStream_t st, FcgState S, int64_t len, const double* rtrue, double* r, double tol,
+                       double* relres, int32_t* mirror);
+// out = a*x + b*y on len x k blocks (each with its own ld); skip columns flagged in skip
+hipError_t launch_axpby(hipStream_t st, int64_t len, int64_t k, double a, const double* x, int64_t ldx, double b,
+                        const double* y, int64_t ldy, double* out, int64_t ldo, const int32_t* skip);
+// dev_out[j] = <x_j, y_j>
+hipError_t launch_coldots(hipStream_t st, int64_t len, int64_t k, const double* x, int64_t ldx, const double* y,
+                          int64_t ldy, double* dev_out);
+// dA = -dB X^T (n x n dense, ld ldda)
+hipError_t launch_outer_neg(hipStream_t st, int64_t n, int64_t k, const double* dB, int64_t lddb, const double* X,
+                            int64_t ldx, double* dA, int64_t ldda);
+// copy len x k block between leading dimensions
+hipError_t launch_copy_block(hipStream_t st, int64_t len, int64_t k, const double* x, int64_t ldx, double* y,
+                             int64_t ldy);
+
+// ---------------------------------------------------------------------------------
+// The preconditioner handle
+// ---------------------------------------------------------------------------------
+struct msp_precond {
+  msp_structure structure;
+  int64_t m, n, s, phi;
+  int32_t gamma, phi_gamma;
+  const int32_t* S_rows;
+  const int8_t* S_signs;
+  const void* Y;      // C (PSD) or A-tilde (general), m x s
+  msp_dtype y_t;
+  int64_t ldy;
+  double lam, lam0, lt;
+  double shift_rel;
+  // device data carved from the nystrom workspace
+  double* Wm;         // PSD: W = S C (symmetrised)
+  double* G;          // PSD: C~^T C~ ; general: A^^T A^ (M3a)
+  double* Minv;       // PSD: M2^{-1} ; general: M3a^{-1}
+  double* Minv2;      // general: M3b^{-1}
+  double* tmp;        // s*s scratch for refactoring
+  double* scal;       // small device scalars
+  int32_t* status;    // device status word
+  int32_t* host_flags;  // pinned, mapped host memory (mirrors of device counters)
+  int32_t* dev_view_flags;
+  double* host_d;     // pinned scratch doubles
+  int device;
+};

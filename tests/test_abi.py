@@ -1,0 +1,78 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol include/msp.h
+declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2405_05865_amd as msp
+from paper_2405_05865_amd import _binding as B
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "msp.h")
+
+
+def _declared():
+    txt = open(HDR).read()
+    return sorted(set(re.findall(r"^\s*(?:msp_status|void|const char\*)\s+(msp_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = msp.library()
+    names = _declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_version_and_defaults():
+    L = msp.library()
+    assert L.msp_version().decode().startswith("libmsp")
+    o = B.SolveOpts()
+    L.msp_solve_opts_default(ctypes.byref(o))
+    assert o.tol == 1e-8 and o.max_outer > 0 and o.inner_tol > 0
+
+
+@pytest.mark.parametrize("m,n,s,gamma", [(0, 10, 4, 2), (10, 10, 0, 1), (10, 10, 4, 5), (10, 10, 11, 2),
+                                         (10, 100, 64, 33)])
+def test_sketch_workspace_rejects_bad_sizes(m, n, s, gamma):
+    L = msp.library()
+    out = ctypes.c_size_t(0)
+    assert L.msp_sketch_workspace(m, n, s, gamma, ctypes.byref(out)) == 1
+    assert L.msp_last_error()
+
+
+def test_sketch_validation_happens_before_device_work():
+    L = msp.library()
+    # null pointers and an F64 Y from F32 A are rejected without any HIP call
+    assert L.msp_sketch(None, None, 0, 10, 10, 10, 4, 2, 1, None, None, None, 0, 4, None, 0) == 1
+    dummy = ctypes.c_void_p(256)
+    assert L.msp_sketch(None, dummy, B.MSP_F32, 10, 10, 10, 4, 2, 1, dummy, dummy, dummy, B.MSP_F64, 4, dummy,
+                        1 << 20) == 1
+    assert b"F64 Y" in L.msp_last_error()
+
+
+def test_nystrom_validation():
+    L = msp.library()
+    out = ctypes.c_size_t(0)
+    assert L.msp_nystrom_workspace(0, 100, 100, 16, 64, 8, ctypes.byref(out)) == 0 and out.value > 0
+    assert L.msp_nystrom_workspace(5, 100, 100, 16, 64, 8, ctypes.byref(out)) == 1
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(256)
+    # lam + lam0 must be > 0
+    assert L.msp_nystrom(None, 0, 100, 100, 16, 8, dummy, dummy, dummy, 0, 16, 0.0, 0.0, 64, 8, 3, dummy,
+                         1 << 30, ctypes.byref(h)) == 1
+    # NaN lambda
+    assert L.msp_nystrom(None, 0, 100, 100, 16, 8, dummy, dummy, dummy, 0, 16, float("nan"), 0.0, 64, 8, 3, dummy,
+                         1 << 30, ctypes.byref(h)) == 5
+    # PSD needs a square system
+    assert L.msp_nystrom(None, 0, 90, 100, 16, 8, dummy, dummy, dummy, 0, 16, 1.0, 0.0, 64, 8, 3, dummy,
+                         1 << 30, ctypes.byref(h)) == 1
+
+
+def test_solve_rejects_null_handle():
+    L = msp.library()
+    info = B.SolveInfo()
+    assert L.msp_solve(None, None, None, 0, None, 0, 10, None, 10, 1, None, 10, None, None, 0,
+                       ctypes.byref(info)) == 1
