@@ -155,6 +155,7 @@ typedef struct {
   int32_t refine;          /* FP64 iterative refinement around a low-precision sweep */
   double refine_inner_tol; /* inner MSP target per refinement step (default 1e-6) */
   int32_t max_refine;      /* refinement step cap (default 30) */
+  int32_t profile;         /* record HIP events around every level-1 sweep (sweep_ms in info) */
 } msp_solve_opts;
 
 typedef struct {
@@ -168,6 +169,8 @@ typedef struct {
   double rel_residual_max;  /* max over RHS of the FP64 relative residual at exit */
   double sweep_bytes;       /* algorithmic bytes of A read by all level-1/2 sweeps */
   int64_t sweeps;           /* number of passes over A (per block of k RHS) */
+  double sweep_ms;          /* profile != 0: summed duration of the timed level-1 sweeps */
+  int64_t timed_sweeps;     /* profile != 0: number of sweeps in sweep_ms */
 } msp_solve_info;
 
 void msp_solve_opts_default(msp_solve_opts* o /*host*/);

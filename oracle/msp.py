@@ -52,6 +52,12 @@ def paper_lambda0(eigs_desc: np.ndarray, l: int) -> float:
     return float(2.0 / l * e[l:].sum())
 
 
+def paper_lambda0_from_top(trace: float, top_l: np.ndarray, l: int) -> float:
+    """The same lam0 from tr(A) and the l largest eigenvalues: sum_{i>l} = tr - sum_{i<=l}."""
+    top = np.sort(np.asarray(top_l, dtype=np.float64))[::-1][:l]
+    return float(2.0 / l * (trace - top.sum()))
+
+
 def spd_inverse(m: np.ndarray, shift_rel: float) -> np.ndarray:
     """(M + mu I)^{-1} from a Cholesky factor, mu = shift_rel * tr(M) / dim."""
     d = m.shape[0]

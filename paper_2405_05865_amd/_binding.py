@@ -53,6 +53,7 @@ class SolveOpts(ctypes.Structure):
         ("refine", ctypes.c_int32),
         ("refine_inner_tol", ctypes.c_double),
         ("max_refine", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
     ]
 
 
@@ -68,6 +69,8 @@ class SolveInfo(ctypes.Structure):
         ("rel_residual_max", ctypes.c_double),
         ("sweep_bytes", ctypes.c_double),
         ("sweeps", ctypes.c_int64),
+        ("sweep_ms", ctypes.c_double),
+        ("timed_sweeps", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -252,6 +252,7 @@ extern "C" msp_status msp_nystrom(void* stream, msp_structure structure, int64_t
     return msp_fail(MSP_ERR_HIP, "hipHostGetDevicePointer failed");
   }
   H->host_d = nullptr;
+  H->events = new std::vector<hipEvent_t>();
 
   auto fail = [&](msp_status s_) {
     msp_precond_destroy(H);
@@ -296,6 +297,11 @@ extern "C" msp_status msp_nystrom(void* stream, msp_structure structure, int64_t
 extern "C" msp_status msp_precond_destroy(msp_precond* P) {
   if (!P) return MSP_OK;
   if (P->host_flags) (void)hipHostFree(P->host_flags);
+  if (P->events) {
+    auto* v = (std::vector<hipEvent_t>*)P->events;
+    for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+    delete v;
+  }
   delete P;
   return MSP_OK;
 }
@@ -335,6 +341,7 @@ extern "C" void msp_solve_opts_default(msp_solve_opts* o) {
   o->refine = 0;
   o->refine_inner_tol = 1e-6;
   o->max_refine = 30;
+  o->profile = 0;
 }
 
 namespace {
@@ -379,7 +386,40 @@ struct SolveCtx {
   int last_inner = 4;
   int last_l3 = 4;
   msp_solve_info acc{};
+  std::vector<hipEvent_t>* evpool = nullptr;
+  size_t evused = 0;
 };
+
+// profiled sweeps: an event pair around each level-1 sweep launch
+msp_status ev_begin(SolveCtx& c, hipEvent_t* stop_out) {
+  *stop_out = nullptr;
+  if (!c.o->profile || !c.evpool) return MSP_OK;
+  auto& pool = *c.evpool;
+  while (pool.size() < c.evused + 2) {
+    hipEvent_t e;
+    MSP_CHECK_HIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  MSP_CHECK_HIP(hipEventRecord(pool[c.evused], c.st));
+  *stop_out = pool[c.evused + 1];
+  c.evused += 2;
+  return MSP_OK;
+}
+
+msp_status ev_collect(SolveCtx& c) {
+  if (!c.o->profile || !c.evpool || c.evused == 0) return MSP_OK;
+  MSP_CHECK_HIP(hipStreamSynchronize(c.st));
+  double total = 0.0;
+  for (size_t i = 0; i + 1 < c.evused; i += 2) {
+    float ms = 0.f;
+    MSP_CHECK_HIP(hipEventElapsedTime(&ms, (*c.evpool)[i], (*c.evpool)[i + 1]));
+    total += ms;
+  }
+  c.acc.sweep_ms += total;
+  c.acc.timed_sweeps += (int64_t)(c.evused / 2);
+  c.evused = 0;
+  return MSP_OK;
+}
 
 size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c) {
   const int64_t n = P->n, m = P->m, s = P->s;
@@ -427,6 +467,8 @@ msp_status psd_op1(SolveCtx& c, const void* A, msp_dtype t, const double* p, dou
                    bool with_alpha, bool fp64 = false) {
   int nb = 0;
   hipError_t e;
+  hipEvent_t stop = nullptr;
+  if (with_alpha) TRY(ev_begin(c, &stop));
   if (fp64 && t == MSP_F32)
     e = launch_gemv_f32_as_f64(c.st, (const float*)A, c.n, c.n, c.lda, p, c.n, q, c.n, c.k, c.lam, true, skip,
                                with_alpha ? c.gpart : nullptr, &nb);
@@ -434,6 +476,7 @@ msp_status psd_op1(SolveCtx& c, const void* A, msp_dtype t, const double* p, dou
     e = launch_gemv(c.st, A, t, c.n, c.n, c.lda, p, c.n, q, c.n, c.k, c.lam, true, skip,
                     with_alpha ? c.gpart : nullptr, &nb);
   MSP_CHECK_HIP(e);
+  if (stop) MSP_CHECK_HIP(hipEventRecord(stop, c.st));
   if (with_alpha) MSP_CHECK_HIP(fcg_alpha_parts(c.st, c.L1.S, c.gpart, nb));
   c.acc.sweeps += 1;
   c.acc.sweep_bytes += (double)c.n * (double)c.n * (double)dsize(t);
@@ -611,8 +654,10 @@ extern "C" msp_status msp_solve(void* stream, const msp_precond* P, const void* 
   // the last-block tickets start at zero
   for (Level* L : {&c.L1, &c.L2, &c.L3}) MSP_CHECK_HIP(hipMemsetAsync(L->S.counter, 0, sizeof(int32_t), c.st));
 
+  c.evpool = (std::vector<hipEvent_t>*)P->events;
   msp_status st = psd_core(c, B, ldb, o->tol, o->max_outer);
   if (st != MSP_OK) return st;
+  TRY(ev_collect(c));
   MSP_CHECK_HIP(launch_copy_block(c.st, c.n, k, c.L1.x, c.n, X, ldx));
   return finish_info(c, info, MSP_OK);
 }

@@ -193,4 +193,5 @@ struct msp_precond {
   int32_t* dev_view_flags;
   double* host_d;     // pinned scratch doubles
   int device;
+  void* events;       // pool of hipEvent_t pairs for profiled sweeps (std::vector)
 };

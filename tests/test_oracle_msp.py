@@ -27,6 +27,11 @@ def test_paper_lambda0_formula():
     assert msp.paper_lambda0(e, 2) == pytest.approx(2.0 / 2 * (3 + 2 + 1))
 
 
+def test_lambda0_from_trace_and_top_eigenvalues():
+    e = np.sort(np.random.default_rng(2).uniform(0, 10, 50))[::-1]
+    assert msp.paper_lambda0_from_top(e.sum(), e[:7][::-1], 7) == pytest.approx(msp.paper_lambda0(e, 7), rel=1e-12)
+
+
 def test_nystrom_exact_recovery_low_rank():
     # Section 4.2: A_nys = A S^T (S A S^T)^+ S A equals A when rank(A) <= s.
     n, r, s = 300, 20, 32
