@@ -30,6 +30,20 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// sum of v over the block, valid in every thread
+__device__ __forceinline__ double block_sum_all(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / WAVE; ++q) t += sh[q];
+  __syncthreads();
+  return t;
+}
+
 // true in every thread of the last block of the grid to reach this point
 __device__ __forceinline__ bool last_block(int32_t* counter) {
   __shared__ int is_last;
@@ -73,6 +87,13 @@ __device__ __forceinline__ void count_active(FcgState S, int32_t* mirror) {
   }
 }
 
+// fixed-order parallel sum of part[b * stride] over b < count; valid in every thread
+__device__ __forceinline__ double strided_sum(const double* base, int count, int64_t stride, double* sh) {
+  double t = 0.0;
+  for (int b = threadIdx.x; b < count; b += NT) t += base[(int64_t)b * stride];
+  return block_sum_all(t, sh);
+}
+
 __device__ __forceinline__ int64_t chunk_begin(int64_t len) {
   const int64_t per = (len + gridDim.x - 1) / gridDim.x;
   return blockIdx.x * per;
@@ -98,9 +119,9 @@ __global__ void __launch_bounds__(NT) k_init(FcgState S, int64_t len, const doub
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) S.part[(int64_t)blockIdx.x * S.k + j] = t;
   if (!last_block(S.counter)) return;
-  for (int64_t jj = threadIdx.x; jj < S.k; jj += NT) {
-    double sum = 0.0;
-    for (unsigned bb = 0; bb < gridDim.x; ++bb) sum += S.part[(int64_t)bb * S.k + jj];
+  for (int64_t jj = 0; jj < S.k; ++jj) {
+    const double sum = strided_sum(S.part + jj, gridDim.x, S.k, sh);
+    if (threadIdx.x != 0) continue;
     const double bn = sqrt(sum);
     const bool p = parent_done && parent_done[jj] != 0;
     S.bnorm[jj] = bn;
@@ -131,11 +152,10 @@ __global__ void __launch_bounds__(NT) k_first_dir(FcgState S, int64_t len, const
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) S.part[(int64_t)blockIdx.x * S.k + j] = t;
   if (!last_block(S.counter)) return;
-  for (int64_t jj = threadIdx.x; jj < S.k; jj += NT) {
+  for (int64_t jj = 0; jj < S.k; ++jj) {
     if (S.done[jj] != 0) continue;
-    double sum = 0.0;
-    for (unsigned bb = 0; bb < gridDim.x; ++bb) sum += S.part[(int64_t)bb * S.k + jj];
-    S.rz[jj] = sum;
+    const double sum = strided_sum(S.part + jj, gridDim.x, S.k, sh);
+    if (threadIdx.x == 0) S.rz[jj] = sum;
   }
   if (threadIdx.x == 0) *S.counter = 0;
 }
@@ -182,13 +202,26 @@ __global__ void __launch_bounds__(NT) k_alpha_dot(FcgState S, int64_t len, const
 __global__ void __launch_bounds__(NT) k_update(FcgState S, int64_t len, double* __restrict__ x,
                                               double* __restrict__ r, double* __restrict__ r_old,
                                               const double* __restrict__ p, const double* __restrict__ q, double tol,
-                                              int32_t max_iter, int32_t* mirror) {
+                                              int32_t max_iter, int32_t* mirror, const double* __restrict__ pq_part,
+                                              int nparts) {
   __shared__ double sh[NT / WAVE];
   const int j = blockIdx.y;
   const bool live = S.done[j] == 0;
   double acc = 0.0;
   if (live) {
-    const double a = S.alpha[j];
+    double a;
+    if (pq_part) {
+      double t = 0.0;
+      for (int b = threadIdx.x; b < nparts; b += NT) t += pq_part[(int64_t)b * S.k + j];
+      const double pq = block_sum_all(t, sh);
+      a = (pq > 0.0) ? S.rz[j] / pq : 0.0;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S.alpha[j] = a;
+        S.brk[j] = (pq > 0.0) ? 0 : 1;
+      }
+    } else {
+      a = S.alpha[j];
+    }
     for (int64_t i = chunk_begin(len) + threadIdx.x; i < chunk_end(len); i += NT) {
       const int64_t o = (int64_t)j * len + i;
       x[o] = fma(a, p[o], x[o]);
@@ -202,10 +235,14 @@ __global__ void __launch_bounds__(NT) k_update(FcgState S, int64_t len, double* 
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) S.part[(int64_t)blockIdx.x * S.k + j] = t;
   if (!last_block(S.counter)) return;
-  for (int64_t jj = threadIdx.x; jj < S.k; jj += NT) {
+  for (int64_t jj = 0; jj < S.k; ++jj) {
     if (S.done[jj] != 0) continue;
-    double sum = 0.0;
-    for (unsigned bb = 0; bb < gridDim.x; ++bb) sum += S.part[(int64_t)bb * S.k + jj];
+    const double sum = strided_sum(S.part + jj, gridDim.x, S.k, sh);
+    if (threadIdx.x != 0) continue;
+    if (pq_part && S.brk[jj]) {
+      S.done[jj] = 2;
+      continue;
+    }
     const double rn = sqrt(sum);
     S.rnorm[jj] = rn;
     const int it = S.iters[jj] + 1;
@@ -238,15 +275,14 @@ __global__ void __launch_bounds__(NT) k_beta(FcgState S, int64_t len, const doub
     S.part[((int64_t)blockIdx.x * S.k + j) * 2 + 1] = t2;
   }
   if (!last_block(S.counter)) return;
-  for (int64_t jj = threadIdx.x; jj < S.k; jj += NT) {
+  for (int64_t jj = 0; jj < S.k; ++jj) {
     if (S.done[jj] != 0) continue;
-    double zr = 0.0, zro = 0.0;
-    for (unsigned bb = 0; bb < gridDim.x; ++bb) {
-      zr += S.part[((int64_t)bb * S.k + jj) * 2 + 0];
-      zro += S.part[((int64_t)bb * S.k + jj) * 2 + 1];
+    const double zr = strided_sum(S.part + jj * 2 + 0, gridDim.x, S.k * 2, sh);
+    const double zro = strided_sum(S.part + jj * 2 + 1, gridDim.x, S.k * 2, sh);
+    if (threadIdx.x == 0) {
+      S.beta[jj] = (zr - zro) / S.rz[jj];
+      S.rz[jj] = zr;
     }
-    S.beta[jj] = (zr - zro) / S.rz[jj];
-    S.rz[jj] = zr;
   }
   if (threadIdx.x == 0) *S.counter = 0;
 }
@@ -277,9 +313,9 @@ __global__ void __launch_bounds__(NT) k_confirm(FcgState S, int64_t len, const d
   const bool last = last_block(S.counter);
   if (!last) return;
   __syncthreads();
-  for (int64_t jj = threadIdx.x; jj < S.k; jj += NT) {
-    double sum = 0.0;
-    for (unsigned bb = 0; bb < gridDim.x; ++bb) sum += S.part[(int64_t)bb * S.k + jj];
+  for (int64_t jj = 0; jj < S.k; ++jj) {
+    const double sum = strided_sum(S.part + jj, gridDim.x, S.k, sh);
+    if (threadIdx.x != 0) continue;
     const double bn = S.bnorm[jj];
     const double rel = bn > 0.0 ? sqrt(sum) / bn : 0.0;
     relres[jj] = rel;
@@ -329,7 +365,7 @@ __global__ void k_outer_neg(int64_t n, int k, const double* __restrict__ dB, int
 }
 
 unsigned grid_x(int64_t len) {
-  int64_t b = (len + NT * 8 - 1) / (NT * 8);
+  int64_t b = (len + NT * 2 - 1) / (NT * 2);
   if (b < 1) b = 1;
   if (b > 256) b = 256;
   return (unsigned)b;
@@ -352,6 +388,9 @@ FcgState carve_fcg_state(WsCarver& w, int64_t len, int64_t k) {
   S.active = w.take<int32_t>(1);
   S.counter = w.take<int32_t>(1);
   S.part = w.take<double>(fcg_part_doubles(len, k));
+  S.brk = w.take<int32_t>(k);
+  S.done_next = w.take<int32_t>(k);
+  S.iters_next = w.take<int32_t>(k);
   return S;
 }
 
@@ -374,9 +413,10 @@ hipError_t fcg_alpha_dot(hipStream_t st, FcgState S, int64_t len, const double* 
   return hipGetLastError();
 }
 hipError_t fcg_update(hipStream_t st, FcgState S, int64_t len, double* x, double* r, double* r_old, const double* p,
-                      const double* q, double tol, int32_t max_iter, int32_t* mirror) {
+                      const double* q, double tol, int32_t max_iter, int32_t* mirror, const double* pq_part,
+                      int nparts) {
   hipLaunchKernelGGL(k_update, dim3(grid_x(len), (unsigned)S.k), dim3(NT), 0, st, S, len, x, r, r_old, p, q, tol,
-                     max_iter, mirror);
+                     max_iter, mirror, pq_part, nparts);
   return hipGetLastError();
 }
 hipError_t fcg_direction(hipStream_t st, FcgState S, int64_t len, const double* r, const double* r_old,

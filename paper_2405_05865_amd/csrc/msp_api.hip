@@ -380,6 +380,8 @@ struct SolveCtx {
   double lam;
   Level L1, L2, L3;
   double *tpart, *rhs2, *wp, *relres, *gpart;
+  double *l2part, *l2pq, *pqw, *l2b;
+  int nb_last = 0;  // blocks of the last level-1 sweep (its <p, q> partials)
   double *mvec, *mvec2, *nvec;  // general path: m x k, m x k, n x k
   int32_t* hf;                  // host mirror (pinned)
   int32_t* df;                  // device view of the host mirror
@@ -432,6 +434,10 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c) {
   double* wp = w.take<double>(s * k);
   double* relres = w.take<double>(k);
   double* gpart = w.take<double>(std::max<size_t>(nb_gemv * k, gemv_t_part_doubles(m, n, k)));
+  double* l2part = w.take<double>(l2_op_part_doubles(std::max(n, m), s, k));
+  double* l2pq = w.take<double>(l2_op_pq_doubles(std::max(n, m), k));
+  double* pqw = w.take<double>(s * k);
+  double* l2b = w.take<double>(l2_bpart_doubles(s, k));
   double *mvec = nullptr, *mvec2 = nullptr, *nvec = nullptr;
   if (P->structure == MSP_GENERAL) {
     mvec = w.take<double>(m * k);
@@ -450,6 +456,10 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c) {
     c->mvec = mvec;
     c->mvec2 = mvec2;
     c->nvec = nvec;
+    c->l2part = l2part;
+    c->l2pq = l2pq;
+    c->pqw = pqw;
+    c->l2b = l2b;
   }
   return w.off;
 }
@@ -477,39 +487,54 @@ msp_status psd_op1(SolveCtx& c, const void* A, msp_dtype t, const double* p, dou
                     with_alpha ? c.gpart : nullptr, &nb);
   MSP_CHECK_HIP(e);
   if (stop) MSP_CHECK_HIP(hipEventRecord(stop, c.st));
-  if (with_alpha) MSP_CHECK_HIP(fcg_alpha_parts(c.st, c.L1.S, c.gpart, nb));
+  c.nb_last = nb;
   c.acc.sweeps += 1;
   c.acc.sweep_bytes += (double)c.n * (double)c.n * (double)dsize(t);
   return MSP_OK;
 }
 
 // ---- level 2 of the PSD method (Algorithm 2) --------------------------------------
-// z = (r - C y^) / lam~ with y^ from level-2 FCG on (C^T C + lam~ W) y = C^T r
+// z = (r - C y^) / lam~ with y^ from level-2 FCG on (C^T C + lam~ W) y = C^T r, M2^{-1}
 msp_status psd_solve_m1(SolveCtx& c, const double* r, double* z) {
   const msp_precond* P = c.P;
   Level& L = c.L2;
   const int64_t s = c.s, n = c.n, k = c.k;
-  const int nb = tall_blocks(n);
   const int32_t* pdone = c.L1.S.done;
-  MSP_CHECK_HIP(launch_yt_v(c.st, P->Y, P->y_t, n, s, P->ldy, r, n, k, pdone, c.tpart));
-  MSP_CHECK_HIP(launch_reduce_parts(c.st, c.tpart, nb, s * k, c.rhs2));
-  MSP_CHECK_HIP(fcg_init(c.st, L.S, s, c.rhs2, s, L.r, L.x, pdone, c.df + SLOT_L2));
-  MSP_CHECK_HIP(launch_small_mv(c.st, s, P->Minv, L.r, k, L.S.done, L.z));
-  MSP_CHECK_HIP(fcg_first_dir(c.st, L.S, s, L.r, L.z, L.p));
+  L2Step a;
+  a.s = s;
+  a.k = k;
+  a.nbC = l2_blocks(n);
+  a.part = c.l2part;
+  a.pqpart = c.l2pq;
+  a.wp = c.wp;
+  a.pqw = c.pqw;
+  a.wscale = P->lt;
+  a.sigma = 0.0;
+  a.y = L.x;
+  a.r = L.r;
+  a.ro = L.ro;
+  a.z = L.z;
+  a.p = L.p;
+  a.q = L.q;
+  a.Minv = P->Minv;
+  a.S = L.S;
+  a.bpart = c.l2b;
+  a.tol = c.o->inner_tol;
+  a.max_iter = c.o->max_inner;
+  a.mirror = c.df + SLOT_L2;
+  a.parent_done = pdone;
+  // right-hand side C^T r, then z = M2^{-1} r2, p = z
+  MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, n, s, P->ldy, r, n, k, pdone, a.part, nullptr, nullptr, nullptr, nullptr,
+                      true));
+  MSP_CHECK_HIP(l2_init(c.st, a));
   int issued = 0;
   int chunk = std::max(1, c.last_inner);
   const int cap = c.o->max_inner;
   while (true) {
     for (int i = 0; i < chunk && issued < cap; ++i, ++issued) {
-      // q = C^T (C p) + lam~ W p
-      MSP_CHECK_HIP(launch_yty_z(c.st, P->Y, P->y_t, n, s, P->ldy, L.p, k, L.S.done, c.tpart));
-      MSP_CHECK_HIP(launch_reduce_parts(c.st, c.tpart, nb, s * k, L.q));
-      MSP_CHECK_HIP(launch_small_mv(c.st, s, P->Wm, L.p, k, L.S.done, c.wp));
-      MSP_CHECK_HIP(launch_axpby(c.st, s, k, 1.0, L.q, s, P->lt, c.wp, s, L.q, s, L.S.done));
-      MSP_CHECK_HIP(fcg_alpha_dot(c.st, L.S, s, L.p, L.q));
-      MSP_CHECK_HIP(fcg_update(c.st, L.S, s, L.x, L.r, L.ro, L.p, L.q, c.o->inner_tol, cap, c.df + SLOT_L2));
-      MSP_CHECK_HIP(launch_small_mv(c.st, s, P->Minv, L.r, k, L.S.done, L.z));
-      MSP_CHECK_HIP(fcg_direction(c.st, L.S, s, L.r, L.ro, L.z, L.p));
+      MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, n, s, P->ldy, L.p, s, k, L.S.done, a.part, a.pqpart, P->Wm, a.wp,
+                          a.pqw, false));
+      MSP_CHECK_HIP(l2_step(c.st, a));
     }
     TRY(sync(c));
     if (*slot(c, SLOT_L2) == 0 || issued >= cap) break;
@@ -548,7 +573,8 @@ msp_status psd_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int m
     }
     if (it >= max_outer) break;
     TRY(psd_op1(c, c.A_sw, c.sw_t, L.p, L.q, L.S.done, true));
-    MSP_CHECK_HIP(fcg_update(c.st, L.S, n, L.x, L.r, L.ro, L.p, L.q, tol, max_outer, c.df + SLOT_L1));
+    MSP_CHECK_HIP(fcg_update(c.st, L.S, n, L.x, L.r, L.ro, L.p, L.q, tol, max_outer, c.df + SLOT_L1, c.gpart,
+                             c.nb_last));
     TRY(psd_solve_m1(c, L.r, L.z));
     MSP_CHECK_HIP(fcg_direction(c.st, L.S, n, L.r, L.ro, L.z, L.p));
     ++it;
@@ -653,6 +679,8 @@ extern "C" msp_status msp_solve(void* stream, const msp_precond* P, const void* 
   solve_layout(w, P, k, &c);
   // the last-block tickets start at zero
   for (Level* L : {&c.L1, &c.L2, &c.L3}) MSP_CHECK_HIP(hipMemsetAsync(L->S.counter, 0, sizeof(int32_t), c.st));
+  MSP_CHECK_HIP(hipMemsetAsync(c.l2b, 0, sizeof(double) * l2_bpart_doubles(c.s, k), c.st));
+
 
   c.evpool = (std::vector<hipEvent_t>*)P->events;
   msp_status st = psd_core(c, B, ldb, o->tol, o->max_outer);

@@ -131,6 +131,9 @@ struct FcgState {
   int32_t* active;   // [1]
   int32_t* counter;  // [1] last-block ticket (reset by the last block)
   double* part;      // per-block partials, >= fcg_part_doubles(len, k)
+  int32_t* brk;      // [k] breakdown marker written by block 0 of each column
+  int32_t* done_next;   // [k] decision taken inside a multi-block kernel, committed by the next
+  int32_t* iters_next;  // [k] single-block kernel (so no block reads a value another block rewrites)
   int64_t k;
 };
 size_t fcg_part_doubles(int64_t len, int64_t k);
@@ -144,9 +147,12 @@ hipError_t fcg_first_dir(hipStream_t st, FcgState S, int64_t len, const double* 
 hipError_t fcg_alpha_parts(hipStream_t st, FcgState S, const double* pq_part, int nparts);
 // alpha = rz / <p, q> computed directly (short vectors)
 hipError_t fcg_alpha_dot(hipStream_t st, FcgState S, int64_t len, const double* p, const double* q);
-// x += alpha p; r_old = r; r -= alpha q; |r| -> done by tol / max_iter; mirror <- active
+// x += alpha p; r_old = r; r -= alpha q; |r| -> done by tol / max_iter; mirror <- active.
+// With pq_part (nparts per-block partials of <p, q>, layout [b][k]) every block forms
+// alpha = rz / <p, q> itself; otherwise alpha is read from S.alpha.
 hipError_t fcg_update(hipStream_t st, FcgState S, int64_t len, double* x, double* r, double* r_old,
-                      const double* p, const double* q, double tol, int32_t max_iter, int32_t* mirror);
+                      const double* p, const double* q, double tol, int32_t max_iter, int32_t* mirror,
+                      const double* pq_part = nullptr, int nparts = 0);
 // beta = <z, r - r_old> / rz ; rz = <r, z> ; p = z + beta p
 hipError_t fcg_direction(hipStream_t st, FcgState S, int64_t len, const double* r, const double* r_old,
                          const double* z, double* p);
@@ -166,6 +172,43 @@ hipError_t launch_outer_neg(hipStream_t st, int64_t n, int64_t k, const double* 
 // copy len x k block between leading dimensions
 hipError_t launch_copy_block(hipStream_t st, int64_t len, int64_t k, const double* x, int64_t ldx, double* y,
                              int64_t ldy);
+
+// ---------------------------------------------------------------------------------
+// Fused inner-iteration kernels on the sketch Y (k_level2.hip): one flexible-PCG step
+// for q = Y^T Y p + wscale W p + sigma p with preconditioner Minv. Vectors are s x k.
+// ---------------------------------------------------------------------------------
+struct L2Step {
+  int64_t s = 0, k = 0;
+  int nbC = 0;                 // blocks of the Y pass (l2_blocks(n))
+  double* part = nullptr;      // [nbC][k][s]
+  double* pqpart = nullptr;    // [nbC][k]
+  double* wp = nullptr;        // [k][s] (null without W)
+  double* pqw = nullptr;       // [k][s] (null without W)
+  double wscale = 0.0, sigma = 0.0;
+  double *y = nullptr, *r = nullptr, *ro = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  const double* Minv = nullptr;
+  FcgState S{};
+  double* bpart = nullptr;     // l2_bpart_doubles(s, k)
+  double tol = 0.0;
+  int max_iter = 0;
+  int32_t* mirror = nullptr;
+  const int32_t* parent_done = nullptr;
+};
+int l2_blocks(int64_t n);
+size_t l2_bpart_doubles(int64_t s, int64_t k);
+// sizes of the Y-pass partial buffers (block partials, group sums and group counters);
+// the counters must be zero before the first pass (l2_op_counters)
+size_t l2_op_part_doubles(int64_t n, int64_t s, int64_t k);
+size_t l2_op_pq_doubles(int64_t n, int64_t k);
+// Y pass: rhs_mode=false: partials of Y^T Y v (v: s x k) and <v, Y^T Y v>, plus W v rows;
+//         rhs_mode=true : partials of Y^T v (v: n x k, ld ldv) for the right-hand side.
+hipError_t l2_op(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_t s, int64_t ldy, const double* v,
+                 int64_t ldv, int64_t k, const int32_t* done, double* part, double* pqpart, const double* W,
+                 double* wp, double* pqw, bool rhs_mode);
+// right-hand side (after l2_op in rhs mode): y = 0, r = rhs, |rhs|, z = Minv r, p = z
+hipError_t l2_init(hipStream_t st, const L2Step& a);
+// one step after l2_op(p): alpha, y/r update, convergence decision, z = Minv r, p = z + beta p
+hipError_t l2_step(hipStream_t st, const L2Step& a);
 
 // ---------------------------------------------------------------------------------
 // The preconditioner handle
