@@ -153,7 +153,7 @@ typedef struct {
   int32_t max_level3;      /* level-3 iteration cap (default 200) */
   int32_t normal;          /* general only: solve (A^T A + lam I) x = B instead of A x = B */
   int32_t refine;          /* FP64 iterative refinement around a low-precision sweep */
-  double refine_inner_tol; /* inner MSP target per refinement step (default 1e-6) */
+  double refine_inner_tol; /* inner MSP target per refinement step (default 1e-4) */
   int32_t max_refine;      /* refinement step cap (default 30) */
   int32_t profile;         /* record HIP events around every level-1 sweep (sweep_ms in info) */
 } msp_solve_opts;

@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(NT) k_update(FcgState S, int64_t len, double* 
                                               double* __restrict__ r, double* __restrict__ r_old,
                                               const double* __restrict__ p, const double* __restrict__ q, double tol,
                                               int32_t max_iter, int32_t* mirror, const double* __restrict__ pq_part,
-                                              int nparts) {
+                                              int nparts, int decide) {
   __shared__ double sh[NT / WAVE];
   const int j = blockIdx.y;
   const bool live = S.done[j] == 0;
@@ -232,6 +232,7 @@ __global__ void __launch_bounds__(NT) k_update(FcgState S, int64_t len, double* 
       acc = fma(rn, rn, acc);
     }
   }
+  if (!decide) return;
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) S.part[(int64_t)blockIdx.x * S.k + j] = t;
   if (!last_block(S.counter)) return;
@@ -416,7 +417,68 @@ hipError_t fcg_update(hipStream_t st, FcgState S, int64_t len, double* x, double
                       const double* q, double tol, int32_t max_iter, int32_t* mirror, const double* pq_part,
                       int nparts) {
   hipLaunchKernelGGL(k_update, dim3(grid_x(len), (unsigned)S.k), dim3(NT), 0, st, S, len, x, r, r_old, p, q, tol,
-                     max_iter, mirror, pq_part, nparts);
+                     max_iter, mirror, pq_part, nparts, 1);
+  return hipGetLastError();
+}
+
+// the same update without the convergence decision (the general path decides on rho)
+hipError_t fcg_update_nodecide(hipStream_t st, FcgState S, int64_t len, double* x, double* r, double* r_old,
+                               const double* p, const double* q) {
+  hipLaunchKernelGGL(k_update, dim3(grid_x(len), (unsigned)S.k), dim3(NT), 0, st, S, len, x, r, r_old, p, q, 0.0, 0,
+                     nullptr, nullptr, 0, 0);
+  return hipGetLastError();
+}
+
+// rho -= alpha t (the residual of A x = b carried next to the normal-equation residual);
+// the decision (tol, cap, NaN, breakdown) is taken on |rho|
+__global__ void __launch_bounds__(NT) k_rho_update(FcgState S, int64_t len, double* __restrict__ rho,
+                                                  const double* __restrict__ t, double tol, int32_t max_iter,
+                                                  int32_t* mirror) {
+  __shared__ double sh[NT / WAVE];
+  const int j = blockIdx.y;
+  double acc = 0.0;
+  if (S.done[j] == 0) {
+    const double a = S.alpha[j];
+    for (int64_t i = chunk_begin(len) + threadIdx.x; i < chunk_end(len); i += NT) {
+      const int64_t o = (int64_t)j * len + i;
+      const double v = fma(-a, t[o], rho[o]);
+      rho[o] = v;
+      acc = fma(v, v, acc);
+    }
+  }
+  const double tt = block_sum(acc, sh);
+  if (threadIdx.x == 0) S.part[(int64_t)blockIdx.x * S.k + j] = tt;
+  if (!last_block(S.counter)) return;
+  for (int64_t jj = 0; jj < S.k; ++jj) {
+    if (S.done[jj] != 0) continue;
+    const double sum = strided_sum(S.part + jj, gridDim.x, S.k, sh);
+    if (threadIdx.x != 0) continue;
+    const double rn = sqrt(sum);
+    S.rnorm[jj] = rn;
+    const int it = S.iters[jj] + 1;
+    S.iters[jj] = it;
+    if (S.alpha[jj] == 0.0 || !(rn == rn)) S.done[jj] = 2;
+    else if (rn <= tol * S.bnorm[jj]) S.done[jj] = 1;
+    else if (it >= max_iter) S.done[jj] = 3;
+  }
+  __syncthreads();
+  count_active(S, mirror);
+}
+
+hipError_t fcg_rho_update(hipStream_t st, FcgState S, int64_t len, double* rho, const double* t, double tol,
+                          int32_t max_iter, int32_t* mirror) {
+  hipLaunchKernelGGL(k_rho_update, dim3(grid_x(len), (unsigned)S.k), dim3(NT), 0, st, S, len, rho, t, tol, max_iter,
+                     mirror);
+  return hipGetLastError();
+}
+
+// done = 0 for columns whose done flag equals `from` (restart after a failed confirmation
+// is handled by k_confirm; this re-arms columns for a fresh solve)
+__global__ void k_set_done(FcgState S, const int32_t* src) {
+  for (int64_t j = threadIdx.x; j < S.k; j += blockDim.x) S.done[j] = src ? src[j] : 0;
+}
+hipError_t fcg_copy_done(hipStream_t st, FcgState S, const int32_t* src) {
+  hipLaunchKernelGGL(k_set_done, dim3(1), dim3(256), 0, st, S, src);
   return hipGetLastError();
 }
 hipError_t fcg_direction(hipStream_t st, FcgState S, int64_t len, const double* r, const double* r_old,

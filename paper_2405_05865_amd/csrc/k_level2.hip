@@ -247,6 +247,7 @@ struct L2Args {
   int max_iter;
   int32_t* mirror;
   const int32_t* parent_done;
+  const double* rhs;     // k_l2_init: given right-hand side (s x k) or null
 };
 
 constexpr int NTU = 1024;  // 16 wavefronts
@@ -288,7 +289,8 @@ __global__ void __launch_bounds__(NTU) k_l2_init(L2Args a) {
   const int j = blockIdx.y, lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int c = blockIdx.x * WAVE + lane;
   const bool pd = a.parent_done && a.parent_done[j];
-  const double rhs = reduce_groups_col(a.gpart, ngroups(a.nbC), a.k, a.s, j, c, sh);
+  const double rhs = a.rhs ? ((c < a.s) ? a.rhs[(int64_t)j * a.s + c] : 0.0)
+                           : reduce_groups_col(a.gpart, ngroups(a.nbC), a.k, a.s, j, c, sh);
   double sq = 0.0;
   if (w == 0 && c < a.s) {
     const double v = pd ? 0.0 : rhs;
@@ -537,7 +539,17 @@ L2Args make_args(const L2Step& a) {
   x.max_iter = a.max_iter;
   x.mirror = a.mirror;
   x.parent_done = a.parent_done;
+  x.rhs = a.rhs;
   return x;
+}
+
+__global__ void __launch_bounds__(NTU) k_l2_reduce_to(L2Args a, double* out, const int32_t* skip) {
+  __shared__ double sh[NTU];
+  const int j = blockIdx.y, lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int c = blockIdx.x * WAVE + lane;
+  if (skip && skip[j]) return;
+  const double v = reduce_groups_col(a.gpart, ngroups(a.nbC), a.k, a.s, j, c, sh);
+  if (w == 0 && c < a.s) out[(int64_t)j * a.s + c] = v;
 }
 
 hipError_t prec_launch(hipStream_t st, const L2Step& a, int decide) {
@@ -594,6 +606,12 @@ hipError_t l2_init(hipStream_t st, const L2Step& a) {
   hipError_t e = prec_launch(st, a, 2);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_l2_dir, dim3(1), dim3(256), 0, st, make_args(a), 1);
+  return hipGetLastError();
+}
+
+hipError_t l2_reduce_to(hipStream_t st, const L2Step& a, double* out, const int32_t* skip) {
+  hipLaunchKernelGGL(k_l2_reduce_to, dim3((unsigned)ublocks((int)a.s), (unsigned)a.k), dim3(NTU), 0, st, make_args(a),
+                     out, skip);
   return hipGetLastError();
 }
 

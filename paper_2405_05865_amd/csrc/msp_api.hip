@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -54,6 +55,17 @@ bool valid_dtype(int t) { return t == MSP_F64 || t == MSP_F32 || t == MSP_BF16; 
 bool isfin(double v) { return std::isfinite(v); }
 
 constexpr int kMaxGammaDraw = 32;
+
+// MSP_LOG=1 in the environment: one progress line per refinement step, per level-1
+// restart and per quadrature node, on stderr
+bool log_on() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = getenv("MSP_LOG");
+    on = (e && e[0] && e[0] != '0') ? 1 : 0;
+  }
+  return on == 1;
+}
 constexpr int64_t kMaxS = 2048;    // tall-kernel register layout bound (32 columns per lane)
 constexpr int64_t kMaxK = 1024;
 
@@ -339,10 +351,11 @@ extern "C" void msp_solve_opts_default(msp_solve_opts* o) {
   o->max_level3 = 200;
   o->normal = 0;
   o->refine = 0;
-  o->refine_inner_tol = 1e-6;
+  o->refine_inner_tol = 1e-4;
   o->max_refine = 30;
   o->profile = 0;
 }
+
 
 namespace {
 
@@ -352,7 +365,7 @@ struct Level {
   FcgState S{};
 };
 
-Level carve_level(WsCarver& w, int64_t len, int64_t k) {
+Level carve_level(WsCarver& w, int64_t len, int64_t k, int64_t state_len = 0) {
   Level L;
   L.len = len;
   L.k = k;
@@ -362,7 +375,7 @@ Level carve_level(WsCarver& w, int64_t len, int64_t k) {
   L.z = w.take<double>(len * k);
   L.p = w.take<double>(len * k);
   L.q = w.take<double>(len * k);
-  L.S = carve_fcg_state(w, len, k);
+  L.S = carve_fcg_state(w, std::max(len, state_len), k);
   return L;
 }
 
@@ -371,26 +384,87 @@ struct SolveCtx {
   const msp_precond* P;
   const msp_solve_opts* o;
   int64_t n, m, s, k;
-  // sweep matrix (inside MSP) and confirmation matrix (FP64 residuals)
-  const void* A_sw;
+  const void* A_sw;  // matrix swept inside MSP
   msp_dtype sw_t;
-  const void* A_cf;
+  const void* A_cf;  // matrix of the confirmation / refinement residuals (FP64 arithmetic)
   msp_dtype cf_t;
   int64_t lda;
   double lam;
-  Level L1, L2, L3;
-  double *tpart, *rhs2, *wp, *relres, *gpart;
-  double *l2part, *l2pq, *pqw, *l2b;
-  int nb_last = 0;  // blocks of the last level-1 sweep (its <p, q> partials)
-  double *mvec, *mvec2, *nvec;  // general path: m x k, m x k, n x k
-  int32_t* hf;                  // host mirror (pinned)
-  int32_t* df;                  // device view of the host mirror
-  int last_inner = 4;
-  int last_l3 = 4;
+  Level L0, L1, L2, L3;
+  double *rhs2, *wp, *pqw, *tmp_s, *relres, *dots, *gpart, *l2part, *l2pq, *l2b;
+  double *rho, *tvec, *mvec, *mvec2, *nvec;  // general path: m x k (4) and n x k
+  double *xh, *rh, *bn;                      // refinement
+  int32_t* hf;
+  int32_t* df;
+  int last_inner = 4, last_l3a = 4, last_l3b = 4;
+  int nb_last = 0;
   msp_solve_info acc{};
   std::vector<hipEvent_t>* evpool = nullptr;
   size_t evused = 0;
 };
+
+size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c) {
+  const int64_t n = P->n, m = P->m, s = P->s;
+  const int64_t mx = std::max(n, m);
+  const int64_t nb_gemv = (mx + 3) / 4;  // upper bound of gemv blocks (R >= 4)
+  Level L0 = carve_level(w, n, k, mx);
+  Level L1 = carve_level(w, n, k, mx);
+  Level L2 = carve_level(w, s, k);
+  Level L3 = carve_level(w, s, k);
+  double* rhs2 = w.take<double>(s * k);
+  double* wp = w.take<double>(s * k);
+  double* pqw = w.take<double>(s * k);
+  double* tmp_s = w.take<double>(s * k);
+  double* relres = w.take<double>(k);
+  double* dots = w.take<double>(4 * k);
+  double* gpart = w.take<double>(std::max<size_t>(nb_gemv * k, gemv_t_part_doubles(m, n, k)));
+  double* l2part = w.take<double>(l2_op_part_doubles(mx, s, k));
+  double* l2pq = w.take<double>(l2_op_pq_doubles(mx, k));
+  double* l2b = w.take<double>(l2_bpart_doubles(s, k));
+  double *rho = nullptr, *tvec = nullptr, *mvec = nullptr, *mvec2 = nullptr, *nvec = nullptr;
+  if (P->structure == MSP_GENERAL) {
+    rho = w.take<double>(m * k);
+    tvec = w.take<double>(m * k);
+    mvec = w.take<double>(m * k);
+    mvec2 = w.take<double>(m * k);
+    nvec = w.take<double>(n * k);
+  }
+  double* xh = w.take<double>(n * k);
+  double* rh = w.take<double>(mx * k);
+  double* bn = w.take<double>(k);
+  if (c) {
+    c->L0 = L0;
+    c->L1 = L1;
+    c->L2 = L2;
+    c->L3 = L3;
+    c->rhs2 = rhs2;
+    c->wp = wp;
+    c->pqw = pqw;
+    c->tmp_s = tmp_s;
+    c->relres = relres;
+    c->dots = dots;
+    c->gpart = gpart;
+    c->l2part = l2part;
+    c->l2pq = l2pq;
+    c->l2b = l2b;
+    c->rho = rho;
+    c->tvec = tvec;
+    c->mvec = mvec;
+    c->mvec2 = mvec2;
+    c->nvec = nvec;
+    c->xh = xh;
+    c->rh = rh;
+    c->bn = bn;
+  }
+  return w.off;
+}
+
+inline volatile int32_t* slot(SolveCtx& c, int i) { return (volatile int32_t*)(c.hf + i); }
+
+msp_status sync(SolveCtx& c) {
+  MSP_CHECK_HIP(hipStreamSynchronize(c.st));
+  return MSP_OK;
+}
 
 // profiled sweeps: an event pair around each level-1 sweep launch
 msp_status ev_begin(SolveCtx& c, hipEvent_t* stop_out) {
@@ -423,133 +497,104 @@ msp_status ev_collect(SolveCtx& c) {
   return MSP_OK;
 }
 
-size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c) {
-  const int64_t n = P->n, m = P->m, s = P->s;
-  const int64_t nb_gemv = (std::max(n, m) + 3) / 4;  // upper bound of gemv blocks (R >= 4)
-  Level L1 = carve_level(w, n, k);
-  Level L2 = carve_level(w, s, k);
-  Level L3 = carve_level(w, s, k);
-  double* tpart = w.take<double>((size_t)tall_blocks(std::max(n, m)) * s * k);
-  double* rhs2 = w.take<double>(s * k);
-  double* wp = w.take<double>(s * k);
-  double* relres = w.take<double>(k);
-  double* gpart = w.take<double>(std::max<size_t>(nb_gemv * k, gemv_t_part_doubles(m, n, k)));
-  double* l2part = w.take<double>(l2_op_part_doubles(std::max(n, m), s, k));
-  double* l2pq = w.take<double>(l2_op_pq_doubles(std::max(n, m), k));
-  double* pqw = w.take<double>(s * k);
-  double* l2b = w.take<double>(l2_bpart_doubles(s, k));
-  double *mvec = nullptr, *mvec2 = nullptr, *nvec = nullptr;
-  if (P->structure == MSP_GENERAL) {
-    mvec = w.take<double>(m * k);
-    mvec2 = w.take<double>(m * k);
-    nvec = w.take<double>(n * k);
-  }
-  if (c) {
-    c->L1 = L1;
-    c->L2 = L2;
-    c->L3 = L3;
-    c->tpart = tpart;
-    c->rhs2 = rhs2;
-    c->wp = wp;
-    c->relres = relres;
-    c->gpart = gpart;
-    c->mvec = mvec;
-    c->mvec2 = mvec2;
-    c->nvec = nvec;
-    c->l2part = l2part;
-    c->l2pq = l2pq;
-    c->pqw = pqw;
-    c->l2b = l2b;
-  }
-  return w.off;
-}
-
-inline volatile int32_t* slot(SolveCtx& c, int i) { return (volatile int32_t*)(c.hf + i); }
-
-msp_status sync(SolveCtx& c) {
-  MSP_CHECK_HIP(hipStreamSynchronize(c.st));
-  return MSP_OK;
-}
-
-// q = (A + lam I) p with per-block <p, q> partials; alpha for level 1. fp64: FP64
-// arithmetic also for FP32 storage (the refinement residual).
-msp_status psd_op1(SolveCtx& c, const void* A, msp_dtype t, const double* p, double* q, const int32_t* skip,
-                   bool with_alpha, bool fp64 = false) {
+// Y = A X (+ lam X on the diagonal) for A rows x cols; fp64 forces FP64 arithmetic on
+// FP32 storage (residuals); timed marks a level-1 sweep for the profile
+msp_status sweep(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t cols, const double* X, int64_t ldx,
+                 double* Y, int64_t ldy, bool diag, const int32_t* skip, bool parts, bool fp64, bool timed) {
   int nb = 0;
-  hipError_t e;
   hipEvent_t stop = nullptr;
-  if (with_alpha) TRY(ev_begin(c, &stop));
+  if (timed) TRY(ev_begin(c, &stop));
+  hipError_t e;
   if (fp64 && t == MSP_F32)
-    e = launch_gemv_f32_as_f64(c.st, (const float*)A, c.n, c.n, c.lda, p, c.n, q, c.n, c.k, c.lam, true, skip,
-                               with_alpha ? c.gpart : nullptr, &nb);
+    e = launch_gemv_f32_as_f64(c.st, (const float*)A, rows, cols, c.lda, X, ldx, Y, ldy, c.k, c.lam, diag, skip,
+                               parts ? c.gpart : nullptr, &nb);
   else
-    e = launch_gemv(c.st, A, t, c.n, c.n, c.lda, p, c.n, q, c.n, c.k, c.lam, true, skip,
-                    with_alpha ? c.gpart : nullptr, &nb);
+    e = launch_gemv(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k, c.lam, diag, skip, parts ? c.gpart : nullptr,
+                    &nb);
   MSP_CHECK_HIP(e);
   if (stop) MSP_CHECK_HIP(hipEventRecord(stop, c.st));
   c.nb_last = nb;
   c.acc.sweeps += 1;
-  c.acc.sweep_bytes += (double)c.n * (double)c.n * (double)dsize(t);
+  c.acc.sweep_bytes += (double)rows * (double)cols * (double)dsize(t);
   return MSP_OK;
 }
 
-// ---- level 2 of the PSD method (Algorithm 2) --------------------------------------
-// z = (r - C y^) / lam~ with y^ from level-2 FCG on (C^T C + lam~ W) y = C^T r, M2^{-1}
-msp_status psd_solve_m1(SolveCtx& c, const double* r, double* z) {
-  const msp_precond* P = c.P;
-  Level& L = c.L2;
-  const int64_t s = c.s, n = c.n, k = c.k;
-  const int32_t* pdone = c.L1.S.done;
+// Y = A^T X for A rows x cols (X length rows, Y length cols)
+msp_status sweep_t(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t cols, const double* X, int64_t ldx,
+                   double* Y, int64_t ldy, const int32_t* skip) {
+  MSP_CHECK_HIP(launch_gemv_t(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k, skip, c.gpart));
+  c.acc.sweeps += 1;
+  c.acc.sweep_bytes += (double)rows * (double)cols * (double)dsize(t);
+  return MSP_OK;
+}
+
+L2Step l2step_for(SolveCtx& c, Level& L, const double* Minv, const double* W, double wscale, double sigma,
+                  double tol, int max_iter, int slotid, const int32_t* parent_done) {
   L2Step a;
-  a.s = s;
-  a.k = k;
-  a.nbC = l2_blocks(n);
+  a.s = c.s;
+  a.k = c.k;
+  a.nbC = l2_blocks(std::max(c.n, c.m));
   a.part = c.l2part;
   a.pqpart = c.l2pq;
-  a.wp = c.wp;
-  a.pqw = c.pqw;
-  a.wscale = P->lt;
-  a.sigma = 0.0;
+  a.wp = W ? c.wp : nullptr;
+  a.pqw = W ? c.pqw : nullptr;
+  a.wscale = wscale;
+  a.sigma = sigma;
   a.y = L.x;
   a.r = L.r;
   a.ro = L.ro;
   a.z = L.z;
   a.p = L.p;
   a.q = L.q;
-  a.Minv = P->Minv;
+  a.Minv = Minv;
   a.S = L.S;
   a.bpart = c.l2b;
-  a.tol = c.o->inner_tol;
-  a.max_iter = c.o->max_inner;
-  a.mirror = c.df + SLOT_L2;
-  a.parent_done = pdone;
-  // right-hand side C^T r, then z = M2^{-1} r2, p = z
-  MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, n, s, P->ldy, r, n, k, pdone, a.part, nullptr, nullptr, nullptr, nullptr,
-                      true));
-  MSP_CHECK_HIP(l2_init(c.st, a));
+  a.tol = tol;
+  a.max_iter = max_iter;
+  a.mirror = c.df + slotid;
+  a.parent_done = parent_done;
+  return a;
+}
+
+// iterations of an inner FCG on the sketch: chunk = predicted count, then pairs
+msp_status run_l2(SolveCtx& c, const L2Step& a, const double* W, int slotid, int* last, int64_t* counter) {
+  const msp_precond* P = c.P;
+  const int64_t rows = P->structure == MSP_SYM_PSD ? c.n : c.m;
   int issued = 0;
-  int chunk = std::max(1, c.last_inner);
-  const int cap = c.o->max_inner;
+  int chunk = std::max(1, *last);
+  const int cap = a.max_iter;
   while (true) {
     for (int i = 0; i < chunk && issued < cap; ++i, ++issued) {
-      MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, n, s, P->ldy, L.p, s, k, L.S.done, a.part, a.pqpart, P->Wm, a.wp,
+      MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, rows, c.s, P->ldy, a.p, c.s, c.k, a.S.done, a.part, a.pqpart, W, a.wp,
                           a.pqw, false));
       MSP_CHECK_HIP(l2_step(c.st, a));
     }
     TRY(sync(c));
-    if (*slot(c, SLOT_L2) == 0 || issued >= cap) break;
+    if (*slot(c, slotid) == 0 || issued >= cap) break;
     chunk = 2;
   }
-  const int taken = *slot(c, SLOT_L2 + 1);
-  c.acc.inner_iters += taken;
-  if (taken > 0) c.last_inner = taken;
-  // w^ = (r - C y^) / lam~
-  MSP_CHECK_HIP(launch_y_z(c.st, P->Y, P->y_t, n, s, P->ldy, L.x, k, 1.0 / P->lt, r, n, -1.0 / P->lt, pdone, z, n));
+  const int taken = *slot(c, slotid + 1);
+  *counter += taken;
+  if (taken > 0) *last = taken;
   return MSP_OK;
 }
 
-// ---- level 1 of the PSD method (Algorithm 1 line 5) --------------------------------
-// Solves (A_sw + lam I) X = B to tolerance tol, confirmed with A_cf. Result in L1.x.
+// ---------------------------------- PSD (Algorithms 1-2) ----------------------------
+// z = (r - C y^) / lam~ with y^ from level-2 FCG on (C^T C + lam~ W) y = C^T r, M2^{-1}
+msp_status psd_solve_m1(SolveCtx& c, const double* r, double* z) {
+  const msp_precond* P = c.P;
+  const int64_t s = c.s, n = c.n, k = c.k;
+  const int32_t* pdone = c.L1.S.done;
+  L2Step a = l2step_for(c, c.L2, P->Minv, P->Wm, P->lt, 0.0, c.o->inner_tol, c.o->max_inner, SLOT_L2, pdone);
+  MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, n, s, P->ldy, r, n, k, pdone, a.part, nullptr, nullptr, nullptr, nullptr,
+                      true));
+  MSP_CHECK_HIP(l2_init(c.st, a));
+  TRY(run_l2(c, a, P->Wm, SLOT_L2, &c.last_inner, &c.acc.inner_iters));
+  MSP_CHECK_HIP(launch_y_z(c.st, P->Y, P->y_t, n, s, P->ldy, c.L2.x, k, 1.0 / P->lt, r, n, -1.0 / P->lt, pdone, z, n));
+  return MSP_OK;
+}
+
+// Algorithm 1 line 5: level-1 FCG on (A_sw + lam I) X = B, confirmed on A_cf. X -> L1.x
 msp_status psd_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int max_outer) {
   Level& L = c.L1;
   const int64_t n = c.n, k = c.k;
@@ -558,10 +603,9 @@ msp_status psd_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int m
   MSP_CHECK_HIP(fcg_first_dir(c.st, L.S, n, L.r, L.z, L.p));
   int it = 0;
   while (true) {
-    // the host mirror of level 1 is current here: psd_solve_m1 synchronised after the update
+    // the level-1 mirror is current: psd_solve_m1 synchronised after the update
     if (*slot(c, SLOT_L1) == 0) {
-      // confirm every column that converged on its recurrence residual
-      TRY(psd_op1(c, c.A_cf, c.cf_t, L.x, L.q, nullptr, false, true));
+      TRY(sweep(c, c.A_cf, c.cf_t, n, n, L.x, n, L.q, n, true, nullptr, false, true, false));
       MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, B, ldb, -1.0, L.q, n, L.q, n, nullptr));
       MSP_CHECK_HIP(fcg_confirm(c.st, L.S, n, L.q, L.r, tol, c.relres, c.df + SLOT_L1));
       TRY(sync(c));
@@ -572,59 +616,258 @@ msp_status psd_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int m
       continue;
     }
     if (it >= max_outer) break;
-    TRY(psd_op1(c, c.A_sw, c.sw_t, L.p, L.q, L.S.done, true));
+    TRY(sweep(c, c.A_sw, c.sw_t, n, n, L.p, n, L.q, n, true, L.S.done, true, false, true));
     MSP_CHECK_HIP(fcg_update(c.st, L.S, n, L.x, L.r, L.ro, L.p, L.q, tol, max_outer, c.df + SLOT_L1, c.gpart,
                              c.nb_last));
     TRY(psd_solve_m1(c, L.r, L.z));
     MSP_CHECK_HIP(fcg_direction(c.st, L.S, n, L.r, L.ro, L.z, L.p));
     ++it;
   }
-  c.acc.outer_iters = std::max(c.acc.outer_iters, (int32_t)*slot(c, SLOT_L1 + 1));
+  c.acc.outer_iters += (int32_t)*slot(c, SLOT_L1 + 1);
   return MSP_OK;
 }
 
-msp_status finish_info(SolveCtx& c, msp_solve_info* info, msp_status st) {
-  // per-column status and residuals
-  std::vector<int32_t> done(c.k);
-  std::vector<double> rel(c.k);
-  MSP_CHECK_HIP(hipMemcpyAsync(done.data(), c.L1.S.done, sizeof(int32_t) * c.k, hipMemcpyDeviceToHost, c.st));
-  MSP_CHECK_HIP(hipMemcpyAsync(rel.data(), c.relres, sizeof(double) * c.k, hipMemcpyDeviceToHost, c.st));
+// -------------------------------- general (Algorithms 3-5) --------------------------
+// level 3 (Algorithm 5): (A~^T A~ + sigma I) u = rhs by FCG with Minv; result -> out
+msp_status gen_level3(SolveCtx& c, const double* rhs, double* out, double sigma, const double* Minv,
+                      const int32_t* parent_done, int* last) {
+  L2Step a = l2step_for(c, c.L3, Minv, nullptr, 0.0, sigma, c.o->level3_tol, c.o->max_level3, SLOT_L3, parent_done);
+  a.rhs = rhs;
+  MSP_CHECK_HIP(l2_init(c.st, a));
+  TRY(run_l2(c, a, nullptr, SLOT_L3, last, &c.acc.level3_iters));
+  MSP_CHECK_HIP(launch_copy_block(c.st, c.s, c.k, c.L3.x, c.s, out, c.s));
+  return MSP_OK;
+}
+
+// SolveM2 (Algorithm 5) in the product form z = W^{-1} ((W + lam~ I)^{-1} r)
+msp_status gen_solve_m2(SolveCtx& c, const double* r, double* z, const int32_t* parent_done) {
+  const msp_precond* P = c.P;
+  TRY(gen_level3(c, r, c.tmp_s, P->lt, P->Minv2, parent_done, &c.last_l3b));
+  TRY(gen_level3(c, c.tmp_s, z, 0.0, P->Minv, parent_done, &c.last_l3a));
+  return MSP_OK;
+}
+
+// q2 = A~^T A A^T A~ p2 + lam~ A~^T A~ p2   (Algorithm 4, line 2)
+msp_status gen_op2(SolveCtx& c, const double* p2, double* q2, const int32_t* skip) {
+  const msp_precond* P = c.P;
+  const int64_t m = c.m, n = c.n, s = c.s, k = c.k;
+  MSP_CHECK_HIP(launch_y_z(c.st, P->Y, P->y_t, m, s, P->ldy, p2, k, 0.0, nullptr, 0, 1.0, skip, c.mvec, m));
+  TRY(sweep_t(c, c.A_sw, c.sw_t, m, n, c.mvec, m, c.nvec, n, skip));
+  TRY(sweep(c, c.A_sw, c.sw_t, m, n, c.nvec, n, c.mvec2, m, false, skip, false, false, false));
+  MSP_CHECK_HIP(launch_axpby(c.st, m, k, 1.0, c.mvec2, m, P->lt, c.mvec, m, c.mvec2, m, skip));
+  L2Step a = l2step_for(c, c.L2, nullptr, nullptr, 0.0, 0.0, 0.0, 1, SLOT_L2, nullptr);
+  MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, m, s, P->ldy, c.mvec2, m, k, skip, a.part, nullptr, nullptr, nullptr,
+                      nullptr, true));
+  MSP_CHECK_HIP(l2_reduce_to(c.st, a, q2, skip));
+  return MSP_OK;
+}
+
+// SolveM1 (Algorithm 4): y^ from level-2 FCG on (A~^T A A^T A~ + lam~ A~^T A~) y = A~^T A r
+// preconditioned by SolveM2, then w^ = (r - A^T A~ y^) / lam~
+msp_status gen_solve_m1(SolveCtx& c, const double* r, double* z) {
+  const msp_precond* P = c.P;
+  Level& L = c.L2;
+  const int64_t m = c.m, n = c.n, s = c.s, k = c.k;
+  const int32_t* pdone = c.L1.S.done;
+  TRY(sweep(c, c.A_sw, c.sw_t, m, n, r, n, c.mvec, m, false, pdone, false, false, false));
+  L2Step a = l2step_for(c, L, nullptr, nullptr, 0.0, 0.0, 0.0, 1, SLOT_L2, nullptr);
+  MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, m, s, P->ldy, c.mvec, m, k, pdone, a.part, nullptr, nullptr, nullptr,
+                      nullptr, true));
+  MSP_CHECK_HIP(l2_reduce_to(c.st, a, c.rhs2, pdone));
+  MSP_CHECK_HIP(fcg_init(c.st, L.S, s, c.rhs2, s, L.r, L.x, pdone, c.df + SLOT_L2));
+  TRY(gen_solve_m2(c, L.r, L.z, L.S.done));
+  MSP_CHECK_HIP(fcg_first_dir(c.st, L.S, s, L.r, L.z, L.p));
+  for (int it = 0; it < c.o->max_inner; ++it) {
+    TRY(sync(c));
+    if (*slot(c, SLOT_L2) == 0) break;
+    TRY(gen_op2(c, L.p, L.q, L.S.done));
+    MSP_CHECK_HIP(fcg_alpha_dot(c.st, L.S, s, L.p, L.q));
+    MSP_CHECK_HIP(fcg_update(c.st, L.S, s, L.x, L.r, L.ro, L.p, L.q, c.o->inner_tol, c.o->max_inner, c.df + SLOT_L2));
+    TRY(gen_solve_m2(c, L.r, L.z, L.S.done));
+    MSP_CHECK_HIP(fcg_direction(c.st, L.S, s, L.r, L.ro, L.z, L.p));
+  }
+  TRY(sync(c));
+  c.acc.inner_iters += *slot(c, SLOT_L2 + 1);
+  // w^ = (r - A^T (A~ y^)) / lam~
+  MSP_CHECK_HIP(launch_y_z(c.st, P->Y, P->y_t, m, s, P->ldy, L.x, k, 0.0, nullptr, 0, 1.0, pdone, c.mvec, m));
+  TRY(sweep_t(c, c.A_sw, c.sw_t, m, n, c.mvec, m, c.nvec, n, pdone));
+  MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0 / P->lt, r, n, -1.0 / P->lt, c.nvec, n, z, n, pdone));
+  return MSP_OK;
+}
+
+// q = A^T (A p) + lam p ; t = A p kept for the rho recurrence
+msp_status gen_op1(SolveCtx& c, const double* p, double* q, double* t, const int32_t* skip) {
+  const int64_t m = c.m, n = c.n, k = c.k;
+  TRY(sweep(c, c.A_sw, c.sw_t, m, n, p, n, t, m, false, skip, false, false, true));
+  TRY(sweep_t(c, c.A_sw, c.sw_t, m, n, t, m, q, n, skip));
+  if (c.lam != 0.0) MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, q, n, c.lam, p, n, q, n, skip));
+  return MSP_OK;
+}
+
+// Algorithm 3 line 7. normal == 0: A x = B (B m x k) with the stop on |B - A x|;
+// normal != 0: (A^T A + lam I) x = B (B n x k). X -> L1.x
+msp_status gen_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int max_outer, bool normal) {
+  Level& L = c.L1;
+  const int64_t m = c.m, n = c.n, k = c.k;
+  if (normal) {
+    MSP_CHECK_HIP(fcg_init(c.st, L.S, n, B, ldb, L.r, L.x, nullptr, c.df + SLOT_L1));
+  } else {
+    MSP_CHECK_HIP(fcg_init(c.st, L.S, m, B, ldb, c.rho, nullptr, nullptr, c.df + SLOT_L1));
+    MSP_CHECK_HIP(launch_axpby(c.st, n, k, 0.0, L.x, n, 0.0, nullptr, 0, L.x, n, nullptr));
+    TRY(sweep_t(c, c.A_sw, c.sw_t, m, n, c.rho, m, L.r, n, nullptr));
+  }
+  TRY(gen_solve_m1(c, L.r, L.z));
+  MSP_CHECK_HIP(fcg_first_dir(c.st, L.S, n, L.r, L.z, L.p));
+  int it = 0;
+  while (true) {
+    TRY(sync(c));
+    if (*slot(c, SLOT_L1) == 0) {
+      if (normal) {
+        // rtrue = B - (A^T A + lam I) x
+        TRY(sweep(c, c.A_cf, c.cf_t, m, n, L.x, n, c.tvec, m, false, nullptr, false, true, false));
+        MSP_CHECK_HIP(launch_gemv_t(c.st, c.A_cf, c.cf_t, m, n, c.lda, c.tvec, m, L.q, n, k, nullptr, c.gpart));
+        if (c.lam != 0.0) MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, L.q, n, c.lam, L.x, n, L.q, n, nullptr));
+        MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, B, ldb, -1.0, L.q, n, L.q, n, nullptr));
+        MSP_CHECK_HIP(fcg_confirm(c.st, L.S, n, L.q, L.r, tol, c.relres, c.df + SLOT_L1));
+      } else {
+        TRY(sweep(c, c.A_cf, c.cf_t, m, n, L.x, n, c.tvec, m, false, nullptr, false, true, false));
+        MSP_CHECK_HIP(launch_axpby(c.st, m, k, 1.0, B, ldb, -1.0, c.tvec, m, c.tvec, m, nullptr));
+        MSP_CHECK_HIP(fcg_confirm(c.st, L.S, m, c.tvec, c.rho, tol, c.relres, c.df + SLOT_L1));
+      }
+      TRY(sync(c));
+      if (*slot(c, SLOT_L1) == 0) break;
+      c.acc.restarts += 1;
+      if (!normal) TRY(sweep_t(c, c.A_sw, c.sw_t, m, n, c.rho, m, L.r, n, L.S.done));
+      TRY(gen_solve_m1(c, L.r, L.z));
+      MSP_CHECK_HIP(fcg_first_dir(c.st, L.S, n, L.r, L.z, L.p));
+      continue;
+    }
+    if (it >= max_outer) break;
+    TRY(gen_op1(c, L.p, L.q, c.tvec, L.S.done));
+    MSP_CHECK_HIP(fcg_alpha_dot(c.st, L.S, n, L.p, L.q));
+    if (normal) {
+      MSP_CHECK_HIP(fcg_update(c.st, L.S, n, L.x, L.r, L.ro, L.p, L.q, tol, max_outer, c.df + SLOT_L1));
+    } else {
+      MSP_CHECK_HIP(fcg_update_nodecide(c.st, L.S, n, L.x, L.r, L.ro, L.p, L.q));
+      MSP_CHECK_HIP(fcg_rho_update(c.st, L.S, m, c.rho, c.tvec, tol, max_outer, c.df + SLOT_L1));
+    }
+    TRY(gen_solve_m1(c, L.r, L.z));
+    MSP_CHECK_HIP(fcg_direction(c.st, L.S, n, L.r, L.ro, L.z, L.p));
+    ++it;
+  }
+  c.acc.outer_iters += (int32_t)*slot(c, SLOT_L1 + 1);
+  return MSP_OK;
+}
+
+msp_status core(SolveCtx& c, const double* B, int64_t ldb, double tol, int max_outer) {
+  if (c.P->structure == MSP_SYM_PSD) return psd_core(c, B, ldb, tol, max_outer);
+  return gen_core(c, B, ldb, tol, max_outer, c.o->normal != 0);
+}
+
+// ------------------------------- FP64 iterative refinement --------------------------
+// residual of the user's system with A_hi in FP64: rh = B - op_hi(xh)
+msp_status hi_residual(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const double* B, int64_t ldb, double* out) {
+  const int64_t n = c.n, m = c.m, k = c.k;
+  const bool psd = c.P->structure == MSP_SYM_PSD;
+  if (psd) {
+    TRY(sweep(c, A_hi, hi_t, n, n, c.xh, n, out, n, true, nullptr, false, true, false));
+    MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, B, ldb, -1.0, out, n, out, n, nullptr));
+  } else if (!c.o->normal) {
+    TRY(sweep(c, A_hi, hi_t, m, n, c.xh, n, out, m, false, nullptr, false, true, false));
+    MSP_CHECK_HIP(launch_axpby(c.st, m, k, 1.0, B, ldb, -1.0, out, m, out, m, nullptr));
+  } else {
+    TRY(sweep(c, A_hi, hi_t, m, n, c.xh, n, c.tvec, m, false, nullptr, false, true, false));
+    MSP_CHECK_HIP(launch_gemv_t(c.st, A_hi, hi_t, m, n, c.lda, c.tvec, m, out, n, k, nullptr, c.gpart));
+    if (c.lam != 0.0) MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, out, n, c.lam, c.xh, n, out, n, nullptr));
+    MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, B, ldb, -1.0, out, n, out, n, nullptr));
+  }
+  return MSP_OK;
+}
+
+// per-column |v| / |B| -> host
+msp_status rel_norms(SolveCtx& c, const double* v, int64_t len, std::vector<double>& out) {
+  std::vector<double> num(c.k), den(c.k);
+  MSP_CHECK_HIP(launch_coldots(c.st, len, c.k, v, len, v, len, c.dots));
+  MSP_CHECK_HIP(hipMemcpyAsync(num.data(), c.dots, sizeof(double) * c.k, hipMemcpyDeviceToHost, c.st));
+  MSP_CHECK_HIP(hipMemcpyAsync(den.data(), c.bn, sizeof(double) * c.k, hipMemcpyDeviceToHost, c.st));
   MSP_CHECK_HIP(hipStreamSynchronize(c.st));
-  double worst = 0.0;
-  msp_status out = st;
-  for (int64_t j = 0; j < c.k; ++j) {
-    worst = std::max(worst, rel[j]);
-    if (out == MSP_OK) {
-      if (done[j] == 2) out = MSP_ERR_BREAKDOWN;
-      else if (done[j] == 3 || done[j] == 0) out = MSP_ERR_NO_CONVERGENCE;
-      else if (!std::isfinite(rel[j])) out = MSP_ERR_NONFINITE;
+  out.resize(c.k);
+  for (int64_t j = 0; j < c.k; ++j) out[j] = den[j] > 0 ? std::sqrt(num[j] / den[j]) : 0.0;
+  return MSP_OK;
+}
+
+// x += MSP_lo(b - A_hi x) until |b - A_hi x| <= tol |b|; Krylov refinement (PSD) or a
+// tighter inner tolerance (general) after two steps that fail to halve the residual
+msp_status refine(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const double* B, int64_t ldb, double tol,
+                  std::vector<double>& rel) {
+  const int64_t n = c.n, k = c.k;
+  const bool psd = c.P->structure == MSP_SYM_PSD;
+  const int64_t blen = (!psd && !c.o->normal) ? c.m : n;
+  MSP_CHECK_HIP(launch_coldots(c.st, blen, k, B, ldb, B, ldb, c.bn));
+  MSP_CHECK_HIP(launch_axpby(c.st, n, k, 0.0, c.xh, n, 0.0, nullptr, 0, c.xh, n, nullptr));
+  MSP_CHECK_HIP(launch_copy_block(c.st, blen, k, B, ldb, c.rh, blen));
+  double inner = c.o->refine_inner_tol;
+  std::vector<double> prev(k, 1.0);
+  std::vector<int> slow(k, 0);
+  bool krylov = false;
+  for (int step = 0; step < c.o->max_refine; ++step) {
+    TRY(core(c, c.rh, blen, inner, c.o->max_outer));
+    MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, c.xh, n, 1.0, c.L1.x, n, c.xh, n, nullptr));
+    TRY(hi_residual(c, A_hi, hi_t, B, ldb, c.rh));
+    TRY(rel_norms(c, c.rh, blen, rel));
+    c.acc.refine_steps += 1;
+    if (log_on()) {
+      double wv = 0.0;
+      for (double v : rel) wv = std::max(wv, v);
+      fprintf(stderr, "[msp] refine step %d: max rel residual %.3e (inner tol %.1e)\n", step + 1, wv, inner);
+    }
+    bool all = true, stalled = false;
+    for (int64_t j = 0; j < k; ++j) {
+      if (rel[j] > tol) all = false;
+      slow[j] = (rel[j] > 0.5 * prev[j]) ? slow[j] + 1 : 0;
+      if (slow[j] >= 2 && rel[j] > tol) stalled = true;
+      prev[j] = rel[j];
+    }
+    if (all) return MSP_OK;
+    if (stalled) {
+      if (psd) {
+        krylov = true;
+        break;
+      }
+      inner *= 1e-2;  // general path: ask the inner solve for more accuracy
+      std::fill(slow.begin(), slow.end(), 0);
     }
   }
-  c.acc.rel_residual_max = worst;
-  c.acc.status = out;
-  if (info) *info = c.acc;
-  if (out != MSP_OK && out != st) {
-    if (out == MSP_ERR_NO_CONVERGENCE) msp_fail(out, "iteration cap reached before the tolerance");
-    if (out == MSP_ERR_BREAKDOWN) msp_fail(out, "breakdown: p^T A p <= 0");
-    if (out == MSP_ERR_NONFINITE) msp_fail(out, "non-finite residual");
+  if (!krylov) return MSP_OK;
+  // Krylov refinement: FCG in FP64 on (A_hi + lam I) e = rh, preconditioned by MSP_lo
+  c.acc.krylov_refine = 1;
+  Level& L = c.L0;
+  MSP_CHECK_HIP(fcg_init(c.st, L.S, n, c.rh, n, L.r, L.x, nullptr, c.df + SLOT_L0));
+  TRY(core(c, L.r, n, inner, c.o->max_outer));
+  MSP_CHECK_HIP(launch_copy_block(c.st, n, k, c.L1.x, n, L.z, n));
+  MSP_CHECK_HIP(fcg_first_dir(c.st, L.S, n, L.r, L.z, L.p));
+  // target: |rh - A e| <= tol |B| / |rh| relative to the current residual
+  double worst = 0.0;
+  for (double v : rel) worst = std::max(worst, v);
+  const double ktol = worst > 0 ? tol / worst : tol;
+  for (int it = 0; it < c.o->max_outer; ++it) {
+    TRY(sync(c));
+    if (*slot(c, SLOT_L0) == 0) break;
+    const double lam = c.lam;
+    (void)lam;
+    TRY(sweep(c, A_hi, hi_t, n, n, L.p, n, L.q, n, true, L.S.done, true, true, false));
+    MSP_CHECK_HIP(fcg_update(c.st, L.S, n, L.x, L.r, L.ro, L.p, L.q, ktol, c.o->max_outer, c.df + SLOT_L0, c.gpart,
+                             c.nb_last));
+    TRY(core(c, L.r, n, inner, c.o->max_outer));
+    MSP_CHECK_HIP(launch_copy_block(c.st, n, k, c.L1.x, n, L.z, n));
+    MSP_CHECK_HIP(fcg_direction(c.st, L.S, n, L.r, L.ro, L.z, L.p));
   }
-  return out;
-}
-
-}  // namespace
-
-extern "C" msp_status msp_solve_workspace(const msp_precond* P, int64_t k, const msp_solve_opts* opts,
-                                          size_t* bytes) {
-  REQUIRE(P && bytes, "null argument");
-  REQUIRE(k >= 1 && k <= kMaxK, "need 1 <= k <= %lld", (long long)kMaxK);
-  (void)opts;
-  WsCarver w(nullptr, 0);
-  solve_layout(w, P, k, nullptr);
-  *bytes = w.off;
+  MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, c.xh, n, 1.0, L.x, n, c.xh, n, nullptr));
+  TRY(hi_residual(c, A_hi, hi_t, B, ldb, c.rh));
+  TRY(rel_norms(c, c.rh, n, rel));
   return MSP_OK;
 }
 
-namespace {
 msp_status validate_solve(const msp_precond* P, const void* A_hi, msp_dtype hi_t, const void* A_lo, msp_dtype lo_t,
                           int64_t lda, const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx,
                           const msp_solve_opts* o) {
@@ -640,26 +883,62 @@ msp_status validate_solve(const msp_precond* P, const void* A_hi, msp_dtype hi_t
     return msp_fail(MSP_ERR_NONFINITE, "non-finite tolerance");
   REQUIRE(o->tol > 0 && o->inner_tol > 0 && o->level3_tol > 0 && o->refine_inner_tol > 0, "tolerances must be > 0");
   REQUIRE(o->max_outer >= 1 && o->max_inner >= 1 && o->max_level3 >= 1 && o->max_refine >= 1, "caps must be >= 1");
+  REQUIRE(!(P->structure == MSP_GENERAL && !o->normal && P->lam != 0.0),
+          "A x = b needs lambda = 0 (use normal = 1 for (A^T A + lam I) x = c)");
+  REQUIRE(lo_t == hi_t || o->refine || lo_t == MSP_F64 || true, "");
   return MSP_OK;
 }
-}  // namespace
 
-extern "C" msp_status msp_solve(void* stream, const msp_precond* P, const void* A_hi, msp_dtype hi_t,
-                                const void* A_lo, msp_dtype lo_t, int64_t lda, const double* B, int64_t ldb,
-                                int64_t k, double* X, int64_t ldx, const msp_solve_opts* opts, void* ws,
-                                size_t ws_bytes, msp_solve_info* info) {
-  msp_solve_opts dflt;
-  msp_solve_opts_default(&dflt);
-  const msp_solve_opts* o = opts ? opts : &dflt;
-  TRY(validate_solve(P, A_hi, hi_t, A_lo, lo_t, lda, B, ldb, k, X, ldx, o));
-  REQUIRE(ws, "workspace is null");
-  size_t need = 0;
-  TRY(msp_solve_workspace(P, k, o, &need));
-  if (ws_bytes < need || ((uintptr_t)ws & 255))
-    return msp_fail(MSP_ERR_WORKSPACE, "solve workspace needs %zu bytes, 256-B aligned", need);
-  if (P->structure != MSP_SYM_PSD) return msp_fail(MSP_ERR_UNSUPPORTED, "general structure not in this build yet");
+// the whole solve into X; status from the residuals
+msp_status solve_into(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const double* B, int64_t ldb, double* X,
+                      int64_t ldx, msp_solve_info* info) {
+  const msp_solve_opts* o = c.o;
+  msp_status st = MSP_OK;
+  std::vector<double> rel;
+  const bool do_refine = o->refine && (c.sw_t != MSP_F64);
+  if (do_refine) {
+    c.A_cf = c.A_sw;  // the inner solves confirm on the matrix they sweep
+    c.cf_t = c.sw_t;
+    TRY(refine(c, A_hi, hi_t, B, ldb, o->tol, rel));
+    MSP_CHECK_HIP(launch_copy_block(c.st, c.n, c.k, c.xh, c.n, X, ldx));
+  } else {
+    TRY(core(c, B, ldb, o->tol, o->max_outer));
+    MSP_CHECK_HIP(launch_copy_block(c.st, c.n, c.k, c.L1.x, c.n, X, ldx));
+    // FP64 residual of the returned solution on A_hi
+    const bool psd = c.P->structure == MSP_SYM_PSD;
+    const int64_t blen = (!psd && !o->normal) ? c.m : c.n;
+    MSP_CHECK_HIP(launch_coldots(c.st, blen, c.k, B, ldb, B, ldb, c.bn));
+    MSP_CHECK_HIP(launch_copy_block(c.st, c.n, c.k, c.L1.x, c.n, c.xh, c.n));
+    TRY(hi_residual(c, A_hi, hi_t, B, ldb, c.rh));
+    TRY(rel_norms(c, c.rh, blen, rel));
+  }
+  TRY(ev_collect(c));
+  std::vector<int32_t> done(c.k);
+  MSP_CHECK_HIP(hipMemcpyAsync(done.data(), c.L1.S.done, sizeof(int32_t) * c.k, hipMemcpyDeviceToHost, c.st));
+  MSP_CHECK_HIP(hipStreamSynchronize(c.st));
+  double worst = 0.0;
+  for (int64_t j = 0; j < c.k; ++j) {
+    worst = std::max(worst, rel[j]);
+    if (!std::isfinite(rel[j])) st = MSP_ERR_NONFINITE;
+  }
+  if (st == MSP_OK && worst > o->tol) {
+    st = MSP_ERR_NO_CONVERGENCE;
+    if (!do_refine)
+      for (int64_t j = 0; j < c.k; ++j)
+        if (done[j] == 2) st = MSP_ERR_BREAKDOWN;
+  }
+  c.acc.rel_residual_max = worst;
+  c.acc.status = st;
+  if (info) *info = c.acc;
+  if (st == MSP_ERR_NO_CONVERGENCE) msp_fail(st, "tolerance not reached (relative residual %.3e)", worst);
+  if (st == MSP_ERR_BREAKDOWN) msp_fail(st, "breakdown: p^T A p <= 0");
+  if (st == MSP_ERR_NONFINITE) msp_fail(st, "non-finite residual");
+  return st;
+}
 
-  SolveCtx c;
+msp_status make_ctx(SolveCtx& c, void* stream, const msp_precond* P, const void* A_hi, msp_dtype hi_t,
+                    const void* A_lo, msp_dtype lo_t, int64_t lda, int64_t k, const msp_solve_opts* o, void* ws,
+                    size_t ws_bytes) {
   c.st = (hipStream_t)stream;
   c.P = P;
   c.o = o;
@@ -675,34 +954,225 @@ extern "C" msp_status msp_solve(void* stream, const msp_precond* P, const void* 
   c.lam = P->lam;
   c.hf = P->host_flags;
   c.df = P->dev_view_flags;
+  c.evpool = (std::vector<hipEvent_t>*)P->events;
   WsCarver w(ws, ws_bytes);
   solve_layout(w, P, k, &c);
-  // the last-block tickets start at zero
-  for (Level* L : {&c.L1, &c.L2, &c.L3}) MSP_CHECK_HIP(hipMemsetAsync(L->S.counter, 0, sizeof(int32_t), c.st));
+  if (!w.ok()) return msp_fail(MSP_ERR_WORKSPACE, "workspace overflow");
+  for (Level* L : {&c.L0, &c.L1, &c.L2, &c.L3}) MSP_CHECK_HIP(hipMemsetAsync(L->S.counter, 0, sizeof(int32_t), c.st));
   MSP_CHECK_HIP(hipMemsetAsync(c.l2b, 0, sizeof(double) * l2_bpart_doubles(c.s, k), c.st));
-
-
-  c.evpool = (std::vector<hipEvent_t>*)P->events;
-  msp_status st = psd_core(c, B, ldb, o->tol, o->max_outer);
-  if (st != MSP_OK) return st;
-  TRY(ev_collect(c));
-  MSP_CHECK_HIP(launch_copy_block(c.st, c.n, k, c.L1.x, c.n, X, ldx));
-  return finish_info(c, info, MSP_OK);
+  return MSP_OK;
 }
 
-extern "C" msp_status msp_solve_backward(void*, const msp_precond*, const void*, msp_dtype, const void*, msp_dtype,
-                                         int64_t, const double*, int64_t, const double*, int64_t, int64_t, double*,
-                                         int64_t, double*, double*, int64_t, const msp_solve_opts*, void*, size_t,
-                                         msp_solve_info*) {
-  return msp_fail(MSP_ERR_UNSUPPORTED, "not in this build yet");
+}  // namespace
+
+extern "C" msp_status msp_solve_workspace(const msp_precond* P, int64_t k, const msp_solve_opts* opts,
+                                          size_t* bytes) {
+  REQUIRE(P && bytes, "null argument");
+  REQUIRE(k >= 1 && k <= kMaxK, "need 1 <= k <= %lld", (long long)kMaxK);
+  (void)opts;
+  WsCarver w(nullptr, 0);
+  solve_layout(w, P, k, nullptr);
+  *bytes = w.off;
+  return MSP_OK;
 }
 
-extern "C" msp_status msp_schatten_workspace(const msp_precond*, int64_t, const msp_solve_opts*, size_t*) {
-  return msp_fail(MSP_ERR_UNSUPPORTED, "not in this build yet");
+extern "C" msp_status msp_solve(void* stream, const msp_precond* P, const void* A_hi, msp_dtype hi_t,
+                                const void* A_lo, msp_dtype lo_t, int64_t lda, const double* B, int64_t ldb,
+                                int64_t k, double* X, int64_t ldx, const msp_solve_opts* opts, void* ws,
+                                size_t ws_bytes, msp_solve_info* info) {
+  msp_solve_opts dflt;
+  msp_solve_opts_default(&dflt);
+  const msp_solve_opts* o = opts ? opts : &dflt;
+  TRY(validate_solve(P, A_hi, hi_t, A_lo, lo_t, lda, B, ldb, k, X, ldx, o));
+  REQUIRE(ws, "workspace is null");
+  size_t need = 0;
+  TRY(msp_solve_workspace(P, k, o, &need));
+  if (ws_bytes < need || ((uintptr_t)ws & 255))
+    return msp_fail(MSP_ERR_WORKSPACE, "solve workspace needs %zu bytes, 256-B aligned", need);
+  SolveCtx c;
+  TRY(make_ctx(c, stream, P, A_hi, hi_t, A_lo, lo_t, lda, k, o, ws, ws_bytes));
+  return solve_into(c, A_hi, hi_t, B, ldb, X, ldx, info);
 }
 
-extern "C" msp_status msp_schatten(void*, msp_trace_kind, msp_precond*, const void*, msp_dtype, const void*, msp_dtype,
-                                   int64_t, double, const double*, int64_t, int64_t, double, double, double,
-                                   const msp_solve_opts*, void*, size_t, double*, double*, msp_solve_info*) {
-  return msp_fail(MSP_ERR_UNSUPPORTED, "not in this build yet");
+extern "C" msp_status msp_solve_backward(void* stream, const msp_precond* P, const void* A_hi, msp_dtype hi_t,
+                                         const void* A_lo, msp_dtype lo_t, int64_t lda, const double* X, int64_t ldx,
+                                         const double* G, int64_t ldg, int64_t k, double* dB, int64_t lddb,
+                                         double* dlambda, double* dA, int64_t ldda, const msp_solve_opts* opts,
+                                         void* ws, size_t ws_bytes, msp_solve_info* info) {
+  msp_solve_opts dflt;
+  msp_solve_opts_default(&dflt);
+  const msp_solve_opts* o = opts ? opts : &dflt;
+  REQUIRE(P, "P is null");
+  if (P->structure != MSP_SYM_PSD)
+    return msp_fail(MSP_ERR_UNSUPPORTED, "the adjoint needs A^{-T}; only symmetric (MSP_SYM_PSD) handles");
+  REQUIRE(X && G && dB, "null pointer argument");
+  REQUIRE(ldx >= P->n && ldg >= P->n && lddb >= P->n, "leading dimension too small");
+  REQUIRE(!dA || ldda >= P->n, "ldda < n");
+  TRY(validate_solve(P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, k, dB, lddb, o));
+  size_t need = 0;
+  TRY(msp_solve_workspace(P, k, o, &need));
+  if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
+    return msp_fail(MSP_ERR_WORKSPACE, "solve workspace needs %zu bytes, 256-B aligned", need);
+  SolveCtx c;
+  TRY(make_ctx(c, stream, P, A_hi, hi_t, A_lo, lo_t, lda, k, o, ws, ws_bytes));
+  // dB = (A + lam I)^{-T} G = (A + lam I)^{-1} G for symmetric A, same handle
+  msp_status st = solve_into(c, A_hi, hi_t, G, ldg, dB, lddb, info);
+  if (st != MSP_OK && st != MSP_ERR_NO_CONVERGENCE) return st;
+  if (dlambda) {
+    std::vector<double> d(k);
+    MSP_CHECK_HIP(launch_coldots(c.st, c.n, k, dB, lddb, X, ldx, c.dots));
+    MSP_CHECK_HIP(hipMemcpyAsync(d.data(), c.dots, sizeof(double) * k, hipMemcpyDeviceToHost, c.st));
+    MSP_CHECK_HIP(hipStreamSynchronize(c.st));
+    double acc = 0.0;
+    for (double v : d) acc += v;
+    *dlambda = -acc;
+  }
+  if (dA) {
+    MSP_CHECK_HIP(launch_outer_neg(c.st, c.n, k, dB, lddb, X, ldx, dA, ldda));
+    MSP_CHECK_HIP(hipStreamSynchronize(c.st));
+  }
+  return st;
+}
+
+// ====================================================================================
+// msp_schatten
+// ====================================================================================
+namespace {
+size_t schatten_extra(const msp_precond* P, int64_t N) {
+  // X, A G, A X (n x N each), the A^T partials of the power iteration, probe dots
+  return ((size_t)3 * P->n * N + gemv_t_part_doubles(P->n, P->n, 1) + 4 * N + 4096) * sizeof(double);
+}
+}  // namespace
+
+extern "C" msp_status msp_schatten_workspace(const msp_precond* P, int64_t nprobes, const msp_solve_opts* opts,
+                                             size_t* bytes) {
+  REQUIRE(P && bytes, "null argument");
+  size_t solve = 0;
+  TRY(msp_solve_workspace(P, nprobes, opts, &solve));
+  *bytes = ((solve + 255) & ~size_t(255)) + schatten_extra(P, nprobes);
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precond* P, const void* A_hi,
+                                   msp_dtype hi_t, const void* A_lo, msp_dtype lo_t, int64_t lda, double p,
+                                   const double* G, int64_t ldg, int64_t N, double h, double u_lo, double u_hi,
+                                   const msp_solve_opts* opts, void* ws, size_t ws_bytes, double* estimate,
+                                   double* std_err, msp_solve_info* info) {
+  msp_solve_opts dflt;
+  msp_solve_opts_default(&dflt);
+  msp_solve_opts o = opts ? *opts : dflt;
+  REQUIRE(P && G && estimate, "null argument");
+  REQUIRE(kind == MSP_TRACE_SCHATTEN_P || kind == MSP_TRACE_EFFDIM, "bad kind");
+  REQUIRE(N >= 1 && ldg >= P->n, "bad probe block");
+  REQUIRE(P->m == P->n, "square A only");
+  if (!isfin(p)) return msp_fail(MSP_ERR_NONFINITE, "p not finite");
+  size_t need = 0;
+  TRY(msp_schatten_workspace(P, N, &o, &need));
+  if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
+    return msp_fail(MSP_ERR_WORKSPACE, "schatten workspace needs %zu bytes, 256-B aligned", need);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = P->n;
+  size_t solve_bytes = 0;
+  TRY(msp_solve_workspace(P, N, &o, &solve_bytes));
+  solve_bytes = (solve_bytes + 255) & ~size_t(255);
+  double* X = (double*)((char*)ws + solve_bytes);
+  double* AG = X + n * N;
+  double* AX = AG + n * N;
+  double* gtp = AX + n * N;
+  double* dv = gtp + gemv_t_part_doubles(n, n, 1);
+  std::vector<double> per(N, 0.0), d(N);
+  msp_solve_info acc{};
+  auto add_info = [&](const msp_solve_info& i) {
+    acc.outer_iters += i.outer_iters;
+    acc.inner_iters += i.inner_iters;
+    acc.level3_iters += i.level3_iters;
+    acc.refine_steps += i.refine_steps;
+    acc.sweeps += i.sweeps;
+    acc.sweep_bytes += i.sweep_bytes;
+    acc.rel_residual_max = std::max(acc.rel_residual_max, i.rel_residual_max);
+  };
+  if (kind == MSP_TRACE_EFFDIM) {
+    REQUIRE(P->structure == MSP_SYM_PSD, "effective dimension needs an MSP_SYM_PSD handle");
+    REQUIRE(p > 0.0, "lam > 0");
+    if (P->lam != p) TRY(msp_precond_set_lambda(stream, P, p));
+    msp_solve_info i{};
+    msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
+    if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) return s_;
+    add_info(i);
+    // per probe: g^T g - lam g^T x
+    MSP_CHECK_HIP(launch_coldots(st, n, N, G, ldg, G, ldg, dv));
+    MSP_CHECK_HIP(launch_coldots(st, n, N, G, ldg, X, n, dv + N));
+    std::vector<double> gg(N), gx(N);
+    MSP_CHECK_HIP(hipMemcpyAsync(gg.data(), dv, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    MSP_CHECK_HIP(hipMemcpyAsync(gx.data(), dv + N, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    MSP_CHECK_HIP(hipStreamSynchronize(st));
+    for (int64_t j = 0; j < N; ++j) per[j] = gg[j] - p * gx[j];
+  } else {
+    REQUIRE(P->structure == MSP_GENERAL, "Schatten-p needs an MSP_GENERAL handle");
+    REQUIRE(p > 0.0 && p < 2.0, "need 0 < p < 2");
+    REQUIRE(h > 0.0, "need h > 0");
+    o.normal = 1;
+    // the node range from a power-iteration estimate of |A| when not given
+    if (!(u_lo == u_lo) || !(u_hi == u_hi)) {
+      double* v = X;
+      MSP_CHECK_HIP(launch_copy_block(st, n, 1, G, ldg, v, n));
+      double s2 = 0.0;
+      std::vector<double> nn(1);
+      for (int it = 0; it < 30; ++it) {
+        MSP_CHECK_HIP(launch_coldots(st, n, 1, v, n, v, n, dv));
+        MSP_CHECK_HIP(hipMemcpyAsync(nn.data(), dv, sizeof(double), hipMemcpyDeviceToHost, st));
+        MSP_CHECK_HIP(hipStreamSynchronize(st));
+        const double nv = std::sqrt(nn[0]);
+        if (nv == 0.0) break;
+        MSP_CHECK_HIP(launch_axpby(st, n, 1, 1.0 / nv, v, n, 0.0, nullptr, 0, v, n, nullptr));
+        int nb = 0;
+        MSP_CHECK_HIP(launch_gemv(st, A_hi, hi_t, n, n, lda, v, n, AG, n, 1, 0.0, false, nullptr, nullptr, &nb));
+        MSP_CHECK_HIP(launch_gemv_t(st, A_hi, hi_t, n, n, lda, AG, n, v, n, 1, nullptr, gtp));
+        MSP_CHECK_HIP(launch_coldots(st, n, 1, v, n, v, n, dv));
+        MSP_CHECK_HIP(hipMemcpyAsync(nn.data(), dv, sizeof(double), hipMemcpyDeviceToHost, st));
+        MSP_CHECK_HIP(hipStreamSynchronize(st));
+        s2 = std::sqrt(nn[0]);  // |A^T A v| with |v| = 1
+      }
+      const double smax = std::sqrt(std::max(s2, 1e-300)) * 1.01;
+      const double eps_q = 1e-4;
+      const double ls = 2.0 * std::log(smax);
+      u_lo = ls + (2.0 / p) * std::log(eps_q / (double)n);
+      u_hi = ls + (2.0 / (2.0 - p)) * std::log(1.0 / eps_q);
+    }
+    REQUIRE(u_hi >= u_lo, "u_hi < u_lo");
+    // A g for every probe, once
+    int nb = 0;
+    MSP_CHECK_HIP(launch_gemv(st, A_hi, hi_t, n, n, lda, G, ldg, AG, n, N, 0.0, false, nullptr, nullptr, &nb));
+    const int count = (int)std::floor((u_hi - u_lo) / h + 1e-9) + 1;
+    const double lam_save = P->lam;
+    for (int jn = 0; jn < count; ++jn) {
+      const double u = u_lo + h * jn;
+      const double t = std::exp(u);
+      const double w = h * std::sin(M_PI * p / 2.0) / M_PI * std::exp(0.5 * p * u);
+      TRY(msp_precond_set_lambda(stream, P, t));
+      msp_solve_info i{};
+      msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
+      if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) return s_;
+      add_info(i);
+      if (log_on())
+        fprintf(stderr, "[msp] schatten node %d/%d t=%.3e outer=%d inner=%lld level3=%lld relres=%.2e\n", jn + 1,
+                count, t, i.outer_iters, (long long)i.inner_iters, (long long)i.level3_iters, i.rel_residual_max);
+      MSP_CHECK_HIP(launch_gemv(st, A_hi, hi_t, n, n, lda, X, n, AX, n, N, 0.0, false, nullptr, nullptr, &nb));
+      MSP_CHECK_HIP(launch_coldots(st, n, N, AG, n, AX, n, dv));
+      MSP_CHECK_HIP(hipMemcpyAsync(d.data(), dv, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+      MSP_CHECK_HIP(hipStreamSynchronize(st));
+      for (int64_t j = 0; j < N; ++j) per[j] += w * d[j];
+    }
+    TRY(msp_precond_set_lambda(stream, P, lam_save));
+  }
+  double mean = 0.0;
+  for (double v : per) mean += v;
+  mean /= (double)N;
+  double var = 0.0;
+  for (double v : per) var += (v - mean) * (v - mean);
+  *estimate = mean;
+  if (std_err) *std_err = N > 1 ? std::sqrt(var / (double)(N - 1) / (double)N) : NAN;
+  acc.status = MSP_OK;
+  if (info) *info = acc;
+  return MSP_OK;
 }

@@ -153,6 +153,13 @@ hipError_t fcg_alpha_dot(hipStream_t st, FcgState S, int64_t len, const double* 
 hipError_t fcg_update(hipStream_t st, FcgState S, int64_t len, double* x, double* r, double* r_old,
                       const double* p, const double* q, double tol, int32_t max_iter, int32_t* mirror,
                       const double* pq_part = nullptr, int nparts = 0);
+hipError_t fcg_update_nodecide(hipStream_t st, FcgState S, int64_t len, double* x, double* r, double* r_old,
+                               const double* p, const double* q);
+// rho -= alpha t with the stop decision on |rho| (A x = b through the normal equations)
+hipError_t fcg_rho_update(hipStream_t st, FcgState S, int64_t len, double* rho, const double* t, double tol,
+                          int32_t max_iter, int32_t* mirror);
+// S.done = src (or 0 when src is null)
+hipError_t fcg_copy_done(hipStream_t st, FcgState S, const int32_t* src);
 // beta = <z, r - r_old> / rz ; rz = <r, z> ; p = z + beta p
 hipError_t fcg_direction(hipStream_t st, FcgState S, int64_t len, const double* r, const double* r_old,
                          const double* z, double* p);
@@ -193,6 +200,7 @@ struct L2Step {
   int max_iter = 0;
   int32_t* mirror = nullptr;
   const int32_t* parent_done = nullptr;
+  const double* rhs = nullptr; // l2_init: right-hand side given directly (s x k), else Y^T v partials
 };
 int l2_blocks(int64_t n);
 size_t l2_bpart_doubles(int64_t s, int64_t k);
@@ -209,6 +217,8 @@ hipError_t l2_op(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_
 hipError_t l2_init(hipStream_t st, const L2Step& a);
 // one step after l2_op(p): alpha, y/r update, convergence decision, z = Minv r, p = z + beta p
 hipError_t l2_step(hipStream_t st, const L2Step& a);
+// out[j][c] = sum of the group partials of the last rhs-mode l2_op (Y^T v), s x k
+hipError_t l2_reduce_to(hipStream_t st, const L2Step& a, double* out, const int32_t* skip);
 
 // ---------------------------------------------------------------------------------
 // The preconditioner handle

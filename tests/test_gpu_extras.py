@@ -1,0 +1,142 @@
+"""GPU checks of mixed precision with FP64 refinement, the adjoint (and its autograd
+wrapper), and the spectral-sum drivers, all against the oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_05865_amd as msp
+import workloads as W
+from oracle import dense, trace
+from oracle import msp as omsp
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _psd(n=1024, k=32, s=64, lam=1e-3, cid=0, dtype_lo=None, seeds=(21, 22)):
+    a, eigs, q = W.psd_outlier(n, k, config_id=cid)
+    lam0 = omsp.paper_lambda0(eigs, s // 2)
+    A = torch.from_numpy(a).to(DEV)
+    A_lo = A if dtype_lo is None else A.to(dtype_lo)
+    rows, signs, Y = msp.sketch(A_lo, s, 8, seeds[0])
+    P = msp.Precond("psd", rows, signs, Y, lam, lam0, 4 * s, 8, seeds[1])
+    return a, eigs, q, lam0, A, A_lo, P
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16])
+def test_psd_low_precision_sweeps_refined_to_fp64(dt):
+    say(f"case psd refine {dt}")
+    lam = 1e-3 if dt == torch.float32 else 0.5
+    a, eigs, _, lam0, A, A_lo, P = _psd(lam=lam, dtype_lo=dt)
+    b = W.gaussian(a.shape[0], 0)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), A_lo=A_lo, refine=1, tol=1e-10)
+    say(info)
+    x = X.cpu().numpy()
+    assert info["status"] == "MSP_OK", info
+    assert dense.rel_residual_psd(a, x, b, lam) <= 1e-10
+    xs = dense.solve_psd(a, b, lam)
+    assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+def test_rbf_f32_problem_bf16_sweeps():
+    # kernel-ridge shape: the F32 matrix is the problem, BF16 is the sweep copy
+    say("case rbf f32/bf16 n=2048")
+    n, s, lam = 2048, 128, 1e-2
+    pts = W.rbf_points(n, 4, 3)
+    a32 = W.rbf_matrix(pts, lengthscale=1.0, dtype=np.float32)
+    a = a32.astype(np.float64)
+    eigs = np.linalg.eigvalsh(a)[::-1]
+    lam0 = omsp.paper_lambda0(eigs, s // 2)
+    A = torch.from_numpy(a32).to(DEV)
+    A_lo = A.to(torch.bfloat16)
+    rows, signs, Y = msp.sketch(A_lo, s, 8, 5)
+    P = msp.Precond("psd", rows, signs, Y, lam, lam0, 4 * s, 8, 6)
+    B = W.gaussian((4, n), 3)
+    X, info = msp.solve(P, A, torch.from_numpy(B).to(DEV), A_lo=A_lo, refine=1, tol=1e-8)
+    say(info)
+    x = X.cpu().numpy()
+    assert info["status"] == "MSP_OK", info
+    for j in range(4):
+        assert dense.rel_residual_psd(a, x[j], B[j], lam) <= 1e-8
+        xs = dense.solve_psd(a, B[j], lam)
+        assert np.linalg.norm(x[j] - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_adjoint_matches_dense_gradients():
+    say("case adjoint n=512 k=2")
+    n, s, lam = 512, 32, 1e-2
+    a, eigs, _, lam0, A, _, P = _psd(n=n, k=16, s=s, lam=lam, cid=301)
+    B = W.gaussian((2, n), 301)
+    X, _ = msp.solve(P, A, torch.from_numpy(B).to(DEV), tol=1e-12, inner_tol=1e-13)
+    G = 2.0 * X  # L = sum |x|^2
+    dB, dlam, dA, info = msp.solve_backward(P, A, X, G.contiguous(), want_dA=True, tol=1e-12, inner_tol=1e-13)
+    x = X.cpu().numpy().T
+    db_o, da_o, dl_o = dense.gradients(a, lam, x, 2.0 * x)
+    assert np.linalg.norm(dB.cpu().numpy().T - db_o) <= 1e-9 * np.linalg.norm(db_o)
+    assert dlam == pytest.approx(dl_o, rel=1e-9)
+    assert np.linalg.norm(dA.cpu().numpy() - da_o) <= 1e-9 * np.linalg.norm(da_o)
+
+
+def test_autograd_function_and_finite_differences():
+    say("case autograd n=256")
+    n, s, lam = 256, 32, 0.1
+    a, eigs, _, lam0, A, _, P = _psd(n=n, k=8, s=s, lam=lam, cid=302)
+    B = torch.from_numpy(W.gaussian(n, 302)).to(DEV).requires_grad_(True)
+    Ar = A.clone().requires_grad_(True)
+    lamt = torch.tensor(lam, dtype=torch.float64, device=DEV, requires_grad=True)
+    X = msp.MSPSolve.apply(Ar, B, lamt, P, {"tol": 1e-12, "inner_tol": 1e-13})
+    loss = (X * X).sum()
+    loss.backward()
+    b = B.detach().cpu().numpy()
+    x = np.linalg.solve(a + lam * np.eye(n), b)
+    db, da, dl = dense.gradients(a, lam, x, 2.0 * x)
+    assert np.linalg.norm(B.grad.cpu().numpy() - db) <= 1e-9 * np.linalg.norm(db)
+    assert np.linalg.norm(Ar.grad.cpu().numpy() - da) <= 1e-9 * np.linalg.norm(da)
+    assert lamt.grad.item() == pytest.approx(dl, rel=1e-9)
+    # central finite difference in lam of the oracle's dense loss
+    h = 1e-6
+    f = lambda l_: float(np.sum(np.linalg.solve(a + l_ * np.eye(n), b) ** 2))
+    assert lamt.grad.item() == pytest.approx((f(lam + h) - f(lam - h)) / (2 * h), rel=1e-6)
+
+
+def test_schatten1_matches_oracle_estimator(monkeypatch):
+    say("case schatten-1 n=200 N=32")
+    monkeypatch.setenv("MSP_LOG", "1")
+    n, s, N = 200, 32, 32
+    a, sig, _ = W.schatten_psd(n, config_id=200)
+    g = W.gaussian((N, n), 200)
+    lam0 = omsp.paper_lambda0(sig ** 2, s // 2)
+    A = torch.from_numpy(a).to(DEV)
+    rows, signs, Y = msp.sketch(A, s, 8, 7)
+    P = msp.Precond("general", rows, signs, Y, 1.0, lam0, 4 * s, 8, 8)
+    u_lo, u_hi = trace.default_range(1.0, n, eps_q=1e-2)
+    h = 2.0
+    est, se, info = msp.schatten(P, A, torch.from_numpy(g).to(DEV), p=1.0, h=h, u_lo=u_lo, u_hi=u_hi,
+                                 tol=1e-8, inner_tol=1e-10, level3_tol=1e-10)
+    nodes, w = trace.quadrature(1.0, h, u_lo, u_hi)
+    ridge = lambda t, G: np.linalg.solve(a.T @ a + t * np.eye(n), G)
+    est_o, se_o, _ = trace.schatten_estimate(a, g.T, 1.0, nodes, w, ridge)
+    say(est, se, est_o, se_o, info)
+    assert est == pytest.approx(est_o, rel=1e-6)
+    assert se == pytest.approx(se_o, rel=1e-4)
+    exact = dense.schatten_p(sig, 1.0)
+    # Hutchinson sd for PSD A plus the quadrature error of the coarse, narrow node set
+    assert abs(est - exact) < 4 * math.sqrt(2.0 * np.sum(sig ** 2) / N) + 2e-2 * exact
+
+
+def test_effective_dimension_matches_oracle():
+    say("case effdim n=256 N=64")
+    n, s, lam, N = 256, 32, 0.05, 64
+    a, eigs, _, lam0, A, _, P = _psd(n=n, k=8, s=s, lam=lam, cid=202)
+    g = W.gaussian((N, n), 202)
+    est, se, info = msp.effective_dimension(P, A, torch.from_numpy(g).to(DEV), lam, tol=1e-12, inner_tol=1e-13)
+    est_o, per_o = trace.effective_dimension_estimate(g.T, lam, lambda G: dense.solve_psd(a, G, lam))
+    assert est == pytest.approx(est_o, rel=1e-9)
+    d = dense.effective_dimension(eigs, lam)
+    assert abs(est - d) < 4 * math.sqrt(2.0 * np.sum((eigs / (eigs + lam)) ** 2) / N)

@@ -1,0 +1,143 @@
+"""GPU parity of the three-level path for general A (Algorithms 3-5) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_05865_amd as msp
+import workloads as W
+from oracle import dense
+from oracle import msp as omsp
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _gen(a, lam, lam0, s, seeds=(41, 43), y_dtype=None, A_sk=None):
+    A = torch.from_numpy(a).to(DEV)
+    rows, signs, Y = msp.sketch(A if A_sk is None else A_sk, s, 8, seeds[0], y_dtype=y_dtype)
+    P = msp.Precond("general", rows, signs, Y, lam, lam0, 4 * s, 8, seeds[1])
+    return A, P
+
+
+def test_factors_match_oracle():
+    say("case general factors n=400 s=32")
+    n, s = 400, 32
+    a, sv, _, _ = W.general_outlier(n, 12, config_id=103, big=(1e2, 1e4))
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    A, P = _gen(a, 0.0, lam0, s)
+    _, M3a, M3b = P.factors()
+    O = omsp.GeneralMsp(a, 0.0, lam0, s, 8, 41, 4 * s, 8, 43)
+    for got, want, M in ((M3a, O.m3a_inv, O.m3a), (M3b, O.m3b_inv, O.m3b)):
+        kappa = np.linalg.cond(M)
+        g = got.cpu().numpy()
+        assert np.linalg.norm(g - want) <= kappa * 1e-12 * np.linalg.norm(want)
+
+
+def test_general_solve_matches_lu_and_oracle_iterations():
+    say("case general solve n=400 k=12 s=32")
+    n, k, s = 400, 12, 32
+    a, sv, _, _ = W.general_outlier(n, k, config_id=103, big=(1e2, 1e4))
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    b = W.gaussian(n, 103)
+    A, P = _gen(a, 0.0, lam0, s)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), tol=1e-10, inner_tol=1e-12, level3_tol=1e-12)
+    x = X.cpu().numpy()
+    say(info)
+    assert info["status"] == "MSP_OK", info
+    xs = dense.solve_general(a, b)
+    assert np.linalg.norm(a @ x - b) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
+    O = omsp.GeneralMsp(a, 0.0, lam0, s, 8, 41, 4 * s, 8, 43,
+                        omsp.MspOptions(tol=1e-10, inner_tol=1e-12, level3_tol=1e-12))
+    O.solve_system(b)
+    say("gpu", info["outer_iters"], "oracle", O.info.outer_iterations)
+    assert abs(info["outer_iters"] - O.info.outer_iterations) <= 2
+
+
+def test_lower_bound_example_one():
+    # Section 7: A = I + e_i e_j^T - e_j e_i^T, b = 1  ->  x = 1 except x_i = 0
+    say("case lower-bound example one n=96")
+    n, i, j, s = 96, 5, 70, 16
+    a = np.eye(n)
+    a[i, j] += 1.0
+    a[j, i] -= 1.0
+    sv = np.array([np.sqrt(2.0)] * 2 + [1.0] * (n - 2))
+    lam0 = omsp.paper_lambda0(sv ** 2, s // 2)
+    A, P = _gen(a, 0.0, lam0, s)
+    X, info = msp.solve(P, A, torch.ones(n, dtype=torch.float64, device=DEV), tol=1e-12, inner_tol=1e-13,
+                        level3_tol=1e-13)
+    want = np.ones(n)
+    want[i] = 0.0
+    assert np.abs(X.cpu().numpy() - want).max() <= 1e-10
+
+
+def test_lower_bound_example_two():
+    # Section 7: blockdiag(M, sigma_min(M) I) [x; y] = [c; 0]  ->  y = 0, x = M^{-1} c
+    say("case lower-bound example two n=160")
+    k, n, s = 8, 160, 32
+    r = np.random.default_rng(7).standard_normal((k, k))
+    m = r + 3 * np.eye(k)
+    smin = np.linalg.svd(m, compute_uv=False).min()
+    a = np.zeros((n, n))
+    a[:k, :k] = m
+    a[k:, k:] = smin * np.eye(n - k)
+    b = np.zeros(n)
+    b[:k] = np.random.default_rng(8).standard_normal(k)
+    sv = np.sort(np.linalg.svd(a, compute_uv=False))[::-1]
+    lam0 = omsp.paper_lambda0(sv ** 2, s // 2)
+    A, P = _gen(a, 0.0, lam0, s)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), tol=1e-12, inner_tol=1e-13, level3_tol=1e-13)
+    x = X.cpu().numpy()
+    assert np.abs(x[k:]).max() <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x[:k] - np.linalg.solve(m, b[:k])) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_ridge_normal_equations_multi_rhs():
+    say("case general normal mode n=300 k=3")
+    n, s, lam = 300, 32, 0.5
+    a, sv, _, _ = W.general_outlier(n, 6, config_id=104, big=(1e1, 1e3))
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    c = W.gaussian((3, n), 104)
+    A, P = _gen(a, lam, lam0, s)
+    X, info = msp.solve(P, A, torch.from_numpy(c).to(DEV), normal=1, tol=1e-11, inner_tol=1e-12, level3_tol=1e-12)
+    assert info["status"] == "MSP_OK", info
+    x = X.cpu().numpy()
+    for j in range(3):
+        xs = dense.solve_ridge(a, c[j], lam)
+        assert np.linalg.norm(x[j] - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_general_f32_sweeps_with_fp64_refinement():
+    # FP32-stored A inside MSP, FP64 residuals on the FP64 A
+    say("case general refine f32 n=512")
+    n, s = 512, 32
+    a, sv, _, _ = W.general_outlier(n, 8, config_id=105, big=(1e2, 1e3))
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    b = W.gaussian(n, 105)
+    A = torch.from_numpy(a).to(DEV)
+    A32 = A.float()
+    rows, signs, Y = msp.sketch(A32, s, 8, 41)
+    P = msp.Precond("general", rows, signs, Y, 0.0, lam0, 4 * s, 8, 43)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), A_lo=A32, refine=1, tol=1e-10, inner_tol=1e-8,
+                        level3_tol=1e-8)
+    say(info)
+    x = X.cpu().numpy()
+    assert info["status"] == "MSP_OK", info
+    assert np.linalg.norm(a @ x - b) <= 1e-10 * np.linalg.norm(b)
+    xs = dense.solve_general(a, b)
+    assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
+    assert info["refine_steps"] >= 1
+
+
+def test_unsupported_adjoint_for_general():
+    n, s = 64, 16
+    a, sv, _, _ = W.general_outlier(n, 4, config_id=106, big=(1e1, 1e2))
+    A, P = _gen(a, 0.0, 1.0, s)
+    X = torch.zeros(n, dtype=torch.float64, device=DEV)
+    with pytest.raises(msp.MspError) as e:
+        msp.solve_backward(P, A, X, X.clone())
+    assert e.value.status == "MSP_ERR_UNSUPPORTED"
