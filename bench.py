@@ -93,6 +93,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--inner-tol", type=float, default=1e-10)
+    ap.add_argument("--max-outer", type=int, default=None,
+                    help="cap the level-1 iterations (counter runs over a few sweeps only)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 2 GiB elementwise copy (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,6 +105,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        nbytes = 2 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 3}))
+        return
 
     import paper_2405_05865_amd as msp
     import workloads as W
@@ -125,7 +139,8 @@ def main():
     def step(profile):
         rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
         P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi)
-        X, info = msp.solve(P, A, bt, tol=w.tol, inner_tol=args.inner_tol, profile=profile)
+        X, info = msp.solve(P, A, bt, tol=w.tol, inner_tol=args.inner_tol, profile=profile,
+                            max_outer=args.max_outer)
         P.close()
         return X, info
 

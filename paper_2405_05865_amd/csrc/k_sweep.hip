@@ -84,8 +84,9 @@ __device__ __forceinline__ void load_vec(const TA* p, TC* o) {
   }
 }
 
-// Block of NT threads computes R rows of Y = A X (+ lam X) for K vectors.
-template <class TA, class TC, int VEC, int R, int K, bool ALN>
+// Block of NT threads computes R rows of Y = A X (+ lam X) for K vectors; each thread
+// keeps UNR 16-byte loads per row in flight.
+template <class TA, class TC, int VEC, int R, int K, bool ALN, int UNR>
 __global__ void __launch_bounds__(NT) k_gemv(const TA* __restrict__ A, int64_t lda, int64_t rows, int64_t cols,
                                             const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
                                             int64_t ldy, int k, int j0, double lam, int diag,
@@ -105,7 +106,32 @@ __global__ void __launch_bounds__(NT) k_gemv(const TA* __restrict__ A, int64_t l
   const TA* arow[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) arow[r] = A + min(r0 + r, rows - 1) * lda;
-  for (int64_t c = (int64_t)threadIdx.x * VEC; c < cv; c += (int64_t)NT * VEC) {
+  int64_t c = (int64_t)threadIdx.x * VEC;
+  constexpr int64_t STEP = (int64_t)NT * VEC;
+  for (; c + (UNR - 1) * STEP < cv; c += STEP * UNR) {
+    TC a[UNR][R][VEC];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) load_vec<TA, TC, VEC, ALN>(arow[r] + c + u * STEP, a[u][r]);
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      TC xv[K][VEC];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const double* xp = X + (int64_t)(j0 + (live[j] ? j : 0)) * ldx + c + u * STEP;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) xv[j][v] = (TC)xp[v];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[r][j] = fma(a[u][r][v], xv[j][v], acc[r][j]);
+    }
+  }
+  for (; c < cv; c += STEP) {
     TC xv[K][VEC];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -224,7 +250,7 @@ bool aligned16(const TA* A, int64_t lda) {
   return ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(TA)) % 16 == 0);
 }
 
-template <class TA, class TC, int VEC, int R, int K>
+template <class TA, class TC, int VEC, int R, int K, int UNR = 1>
 hipError_t gemv_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X,
                   int64_t ldx, double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip,
                   double* dot_part, int* nblocks) {
@@ -232,10 +258,10 @@ hipError_t gemv_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64
   const bool aln = aligned16(A, lda);
   for (int j0 = 0; j0 < k; j0 += K) {
     if (aln)
-      hipLaunchKernelGGL((k_gemv<TA, TC, VEC, R, K, true>), dim3((unsigned)blocks), dim3(NT), 0, st, A, lda, rows,
+      hipLaunchKernelGGL((k_gemv<TA, TC, VEC, R, K, true, UNR>), dim3((unsigned)blocks), dim3(NT), 0, st, A, lda, rows,
                          cols, X, ldx, Y, ldy, k, j0, lam, diag ? 1 : 0, skip, dot_part, k);
     else
-      hipLaunchKernelGGL((k_gemv<TA, TC, VEC, R, K, false>), dim3((unsigned)blocks), dim3(NT), 0, st, A, lda, rows,
+      hipLaunchKernelGGL((k_gemv<TA, TC, VEC, R, K, false, UNR>), dim3((unsigned)blocks), dim3(NT), 0, st, A, lda, rows,
                          cols, X, ldx, Y, ldy, k, j0, lam, diag ? 1 : 0, skip, dot_part, k);
   }
   if (nblocks) *nblocks = (int)blocks;
@@ -246,7 +272,7 @@ template <class TA, class TC, int VEC>
 hipError_t gemv_k(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X,
                   int64_t ldx, double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip,
                   double* dot_part, int* nblocks) {
-  if (k == 1) return gemv_t<TA, TC, VEC, 8, 1>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
+  if (k == 1) return gemv_t<TA, TC, VEC, 4, 1, 2>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
   if (k == 2) return gemv_t<TA, TC, VEC, 8, 2>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
   if (k <= 4) return gemv_t<TA, TC, VEC, 4, 4>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
   return gemv_t<TA, TC, VEC, 4, 8>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
