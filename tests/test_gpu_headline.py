@@ -1,0 +1,99 @@
+"""Parity at the full size of the timed RBF workload (n = 32768, s = 512, phi = 2048, FP64,
+one right-hand side), in the launch configuration the benchmark times.
+
+At this size the oracle checks sampled outputs one by one (rows of Y = A S^T), the whole
+integer sketch bit for bit, the s x s factors, the FP64 residual of the returned solution
+recomputed on the host from the same matrix, and the level-1 iteration count of the
+oracle's own two-level solve on the same sketches.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_05865_amd as msp
+import workloads as W
+from oracle import dense, rng, sketch as osk
+from oracle import msp as omsp
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+EPS = np.finfo(np.float64).eps
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def rbf():
+    w = W.config("rbf_gp_n32768")
+    lam0 = json.load(open(os.path.join(GOLDEN, f"rbf_gp_n{w.n}_lambda0.json")))["lambda0"]
+    say(f"generating RBF n={w.n}")
+    a = W.rbf_matrix(W.rbf_points(w.n, w.extra["dim"], w.config_id))
+    b = W.gaussian(w.n, w.config_id)
+    A = torch.from_numpy(a).to(DEV)
+    return w, lam0, a, b, A
+
+
+_ORACLE = {}
+
+
+def _oracle(rbf):
+    """The oracle's PsdMsp on the same matrix and seeds (built once per module)."""
+    if "P" not in _ORACLE:
+        w, lam0, a, b, A = rbf
+        _ORACLE["P"] = omsp.PsdMsp(a, w.lam, lam0, w.s, w.gamma, w.seed_s, w.phi, w.phi_gamma, w.seed_phi,
+                                   omsp.MspOptions(tol=w.tol, inner_tol=1e-10))
+    return _ORACLE["P"]
+
+
+def test_full_size_sketch_and_factors(rbf):
+    w, lam0, a, b, A = rbf
+    say(f"case full-size sketch n={w.n} s={w.s}")
+    rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
+    r_o, s_o = rng.sketch_indices(w.seed_s, w.n, w.s, w.gamma)
+    assert np.array_equal(rows.cpu().numpy(), r_o)
+    assert np.array_equal(signs.cpu().numpy(), s_o)
+    Yh = Y.cpu().numpy()
+    pick = np.random.default_rng(5).choice(w.n, 48, replace=False)
+    for i in pick:
+        want = osk.right_sketch(a[i:i + 1], r_o, s_o, w.s)[0]
+        scale = osk.right_sketch(np.abs(a[i:i + 1]), r_o, np.ones_like(s_o), w.s)[0]
+        assert np.all(np.abs(Yh[i] - want) <= 64 * EPS * scale), i
+    say("case full-size factors (oracle setup)")
+    P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi)
+    Wg, M2inv, _ = P.factors()
+    O = _oracle(rbf)
+    assert np.linalg.norm(Wg.cpu().numpy() - O.w) <= 1e-12 * np.linalg.norm(O.w)
+    kappa = np.linalg.cond(O.m2)
+    say(f"kappa(M2)={kappa:.3e}")
+    assert np.linalg.norm(M2inv.cpu().numpy() - O.m2inv) <= kappa * 1e-12 * np.linalg.norm(O.m2inv)
+    P.close()
+
+
+def test_full_size_solve_residual_and_iterations(rbf):
+    w, lam0, a, b, A = rbf
+    say(f"case full-size solve n={w.n} tol={w.tol}")
+    rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
+    P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), tol=w.tol, inner_tol=1e-10, profile=1)
+    say(info)
+    assert info["status"] == "MSP_OK", info
+    x = X.cpu().numpy()
+    rr = dense.rel_residual_psd(a, x, b, w.lam)
+    say(f"host FP64 residual {rr:.3e}")
+    assert rr <= w.tol
+    say("oracle two-level solve on the same sketches")
+    O = _oracle(rbf)
+    res = O.solve(b)
+    say(f"gpu outer {info['outer_iters']} oracle outer {O.info.outer_iterations}")
+    assert abs(info["outer_iters"] - O.info.outer_iterations) <= max(2, 0.02 * O.info.outer_iterations)
+    # both iterates satisfy the same residual bound: their difference is bounded through
+    # ||(A + lam I)^{-1}|| <= 1/lam
+    xo = res.x
+    assert np.linalg.norm(x - xo) <= 2 * w.tol * np.linalg.norm(b) / w.lam
+    P.close()
