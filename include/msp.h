@@ -181,6 +181,51 @@ msp_status msp_solve(void* stream, const msp_precond* P,
                      const msp_solve_opts* opts, void* ws, size_t ws_bytes, msp_solve_info* info /*host*/);
 
 /* ---------------------------------------------------------------------------------
+ * msp_solve_batched -- many independent PSD systems (A_i + lam_i I) X_i = B_i of
+ * uneven size in one launch (Algorithm 1 with Algorithm 2 applied to each system;
+ * the preconditioner of each system is built once and reused for all of its
+ * right-hand sides, as Section 3 does for repeated solves).
+ *
+ * Each system brings its own MSP_SYM_PSD handle (from msp_nystrom on its own sketch;
+ * n_i, s_i, lam_i and lam0_i come from the handle). All handles must store Y in the
+ * same dtype. One workgroup solves one system: level-1 flexible PCG, SolveM1 with the
+ * level-2 flexible PCG preconditioned by M2^{-1}, where the level-2 operator
+ * (C^T C + lam~ W) is applied as one s x s matrix formed once per call (the same
+ * operator; s^2 instead of n s work per inner step).
+ * Supported (lo_t, hi_t, Y dtype): (F64, F64, F64), (F32 or BF16, F32 or F64, F32).
+ * Without refinement (or lo_t == F64) the level-1 stop |B - (A + lam I) X| <= tol |B| is
+ * confirmed on A_hi in FP64 (restart otherwise). With refine != 0 and lo_t != F64 the
+ * solve is FP64 Krylov refinement on A_hi (flexible PCG) whose preconditioner is the
+ * MSP solve on A_lo to refine_inner_tol; the refinement stops on the residual of A_hi,
+ * confirmed by a recomputation.
+ * Options used: tol, max_outer, inner_tol, max_inner, refine, refine_inner_tol,
+ * max_refine. Right-hand sides are processed 16 per launch.
+ *
+ *   sys      [host] nsys descriptors; matrices row-major, vectors contiguous
+ *   info     [host] out, nsys records (may be NULL): status, outer_iters (level-1 steps
+ *            summed over inner solves), inner_iters, refine_steps, restarts,
+ *            rel_residual_max (confirmed FP64 residual on A_hi)
+ * Returns MSP_OK when every system met tol, else the first failure's status.
+ * Synchronises the stream before returning.
+ * ------------------------------------------------------------------------------ */
+typedef struct {
+  const msp_precond* P;  /* MSP_SYM_PSD handle of this system */
+  const void* A_hi;      /* n x n, ld lda, dtype hi_t */
+  const void* A_lo;      /* n x n, ld lda, dtype lo_t (may equal A_hi) */
+  int64_t lda;
+  const double* B;       /* n x k, vector j at B + j * ldb */
+  int64_t ldb;
+  double* X;             /* out, n x k, vector j at X + j * ldx */
+  int64_t ldx;
+} msp_system;
+
+msp_status msp_solve_batched_workspace(int32_t nsys, const msp_system* sys /*host*/, int64_t k,
+                                       const msp_solve_opts* opts, size_t* bytes /*host*/);
+msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_system* sys /*host*/, msp_dtype hi_t,
+                             msp_dtype lo_t, int64_t k, const msp_solve_opts* opts, void* ws, size_t ws_bytes,
+                             msp_solve_info* info /*host, nsys records*/);
+
+/* ---------------------------------------------------------------------------------
  * msp_solve_backward -- adjoint of X = (A + lam I)^{-1} B for symmetric PSD A.
  *
  * Given G = dL/dX: dB = (A + lam I)^{-T} G = (A + lam I)^{-1} G (A symmetric), solved

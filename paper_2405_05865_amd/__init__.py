@@ -18,7 +18,7 @@ import torch
 from . import _binding as B
 from ._binding import MspError, SolveInfo, SolveOpts  # noqa: F401
 
-__all__ = ["sketch", "Precond", "nystrom", "solve", "solve_backward", "schatten", "effective_dimension",
+__all__ = ["sketch", "Precond", "nystrom", "solve", "solve_batched", "solve_backward", "schatten", "effective_dimension",
            "MSPSolve", "msp_solve", "library", "MspError", "SolveOpts"]
 
 _DT = {torch.float64: B.MSP_F64, torch.float32: B.MSP_F32, torch.bfloat16: B.MSP_BF16}
@@ -194,6 +194,54 @@ def solve(P: Precond, A_hi: torch.Tensor, Bv: torch.Tensor, A_lo: torch.Tensor |
     d = info.as_dict()
     d["code"] = B.STATUS.get(code, code)
     return X, d
+
+
+def solve_batched(systems, **opts):
+    """Many independent PSD systems in one launch (msp_solve_batched).
+
+    systems: sequence of (P, A_hi, A_lo or None, Bv) with P a "psd" Precond of that
+    system, A_hi / A_lo its (n, n) row-major matrices (one leading dimension), Bv of
+    shape (k, n) with the same k for every system. Returns (list of X (k, n), list of
+    info dicts)."""
+    L = library()
+    o = _opts(**opts)
+    nsys = len(systems)
+    if nsys == 0:
+        raise ValueError("no systems")
+    arr = (B.System * nsys)()
+    xs, keep = [], []
+    k = None
+    hi_t = lo_t = None
+    dev = None
+    for i, (P, A_hi, A_lo, Bv) in enumerate(systems):
+        if P.structure != "psd":
+            raise ValueError("batched solves take 'psd' handles")
+        A_lo = A_hi if A_lo is None else A_lo
+        _rowmajor(A_hi, "A_hi")
+        _rowmajor(A_lo, "A_lo")
+        if A_hi.stride(0) != A_lo.stride(0):
+            raise ValueError("A_hi and A_lo must share the leading dimension")
+        if Bv.dim() != 2:
+            raise ValueError("Bv must be (k, n)")
+        kk, ldb = _vectors(Bv, P.n, "B")
+        if k is None:
+            k, hi_t, lo_t, dev = kk, _code(A_hi), _code(A_lo), Bv.device
+        elif kk != k or _code(A_hi) != hi_t or _code(A_lo) != lo_t:
+            raise ValueError("every system needs the same k and matrix dtypes")
+        X = torch.empty((k, P.n), dtype=torch.float64, device=Bv.device)
+        xs.append(X)
+        keep.append((A_hi, A_lo, Bv))
+        arr[i] = B.System(P.handle.value, A_hi.data_ptr(), A_lo.data_ptr(), A_hi.stride(0), Bv.data_ptr(), ldb,
+                          X.data_ptr(), P.n)
+    need = B.size_out()
+    B.check(L.msp_solve_batched_workspace(nsys, arr, k, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, dev)
+    infos = (SolveInfo * nsys)()
+    code = L.msp_solve_batched(_stream(dev), nsys, arr, hi_t, lo_t, k, ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                               infos)
+    if code not in (0, 3, 4, 5):
+        B.check(code)
+    return xs, [infos[i].as_dict() for i in range(nsys)]
 
 
 def solve_backward(P: Precond, A_hi, X, G, A_lo=None, want_dA: bool = False, **opts):

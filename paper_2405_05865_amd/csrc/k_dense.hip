@@ -13,7 +13,8 @@ constexpr int TILE = 64;
 constexpr int KCH = 16;
 
 // Gram partial: G_part[z] = X[rows of split z]^T X[rows of split z], lower tiles, mirrored
-__global__ void __launch_bounds__(256) k_gram(const double* __restrict__ X, int64_t rows, int64_t s, int64_t ldx,
+template <class T>
+__global__ void __launch_bounds__(256) k_gram(const T* __restrict__ X, int64_t rows, int64_t s, int64_t ldx,
                                               int64_t rows_per_split, double* __restrict__ Gp) {
   // map blockIdx.x to a lower tile (ti >= tj)
   int t = blockIdx.x, ti = 0;
@@ -30,8 +31,8 @@ __global__ void __launch_bounds__(256) k_gram(const double* __restrict__ X, int6
     for (int e = threadIdx.x; e < KCH * TILE; e += 256) {
       const int kk = e / TILE, c = e % TILE;
       const int64_t r = k0 + kk;
-      As[kk][c] = (r < re && i0 + c < s) ? X[r * ldx + i0 + c] : 0.0;
-      Bs[kk][c] = (r < re && j0 + c < s) ? X[r * ldx + j0 + c] : 0.0;
+      As[kk][c] = (r < re && i0 + c < s) ? (double)X[r * ldx + i0 + c] : 0.0;
+      Bs[kk][c] = (r < re && j0 + c < s) ? (double)X[r * ldx + j0 + c] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -209,18 +210,29 @@ __global__ void k_sym_avg(int64_t s, double* M) {
 
 }  // namespace
 
-hipError_t launch_gram(hipStream_t st, const double* X, int64_t rows, int64_t s, int64_t ldx, double* G,
-                       double* part, int splits) {
+template <class T>
+hipError_t gram_t(hipStream_t st, const T* X, int64_t rows, int64_t s, int64_t ldx, double* G, double* part,
+                  int splits) {
   const int nt = (int)((s + TILE - 1) / TILE);
   const int tiles = nt * (nt + 1) / 2;
   const int64_t rps = ((rows + splits - 1) / splits + KCH - 1) / KCH * KCH;
   double* dst = (splits == 1) ? G : part;
-  hipLaunchKernelGGL(k_gram, dim3(tiles, splits), dim3(256), 0, st, X, rows, s, ldx, rps, dst);
+  hipLaunchKernelGGL(k_gram<T>, dim3(tiles, splits), dim3(256), 0, st, X, rows, s, ldx, rps, dst);
   if (splits > 1) {
     const int64_t len = s * s;
     hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, part, splits, len, G);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_gram(hipStream_t st, const double* X, int64_t rows, int64_t s, int64_t ldx, double* G,
+                       double* part, int splits) {
+  return gram_t<double>(st, X, rows, s, ldx, G, part, splits);
+}
+
+hipError_t launch_gram_f32(hipStream_t st, const float* X, int64_t rows, int64_t s, int64_t ldx, double* G,
+                           double* part, int splits) {
+  return gram_t<float>(st, X, rows, s, ldx, G, part, splits);
 }
 
 int gram_splits(int64_t rows, int64_t s) {

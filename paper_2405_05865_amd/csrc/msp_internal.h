@@ -63,6 +63,9 @@ hipError_t launch_gather_rows(hipStream_t st, const void* X, msp_dtype x_t, int6
 int gram_splits(int64_t rows, int64_t s);
 hipError_t launch_gram(hipStream_t st, const double* X, int64_t rows, int64_t s, int64_t ldx, double* G,
                        double* part, int splits);
+// the same for an F32-stored X (FP64 arithmetic)
+hipError_t launch_gram_f32(hipStream_t st, const float* X, int64_t rows, int64_t s, int64_t ldx, double* G,
+                           double* part, int splits);
 // out = sym(a*P + b*Q) + c*I  (P, Q may alias out; Q may be null)
 hipError_t launch_combine_sym(hipStream_t st, int64_t s, double a, const double* P, double b, const double* Q,
                               double c, double* out);

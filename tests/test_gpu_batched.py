@@ -1,0 +1,138 @@
+"""GPU parity of the batched solve (one launch for many PSD systems of uneven size)
+against dense LAPACK solves and the oracle's two-level iteration counts."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_05865_amd as msp
+import workloads as W
+from oracle import dense
+from oracle import msp as omsp
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _system(n, cid, lam=1e-2, dtype=np.float64, lengthscale=1.0, seeds=(11, 12)):
+    """One RBF kernel system of the batched-GP shape (points in 4 dimensions)."""
+    pts = W.rbf_points(n, 4, cid)
+    a = W.rbf_matrix(pts, lengthscale=lengthscale, dtype=dtype)
+    a64 = a.astype(np.float64)
+    s = max(8, min(64, n // 2))
+    lam0 = omsp.paper_lambda0(np.linalg.eigvalsh(a64)[::-1], s // 2)
+    return dict(n=n, a=a, a64=a64, s=s, phi=min(4 * s, n), lam=lam, lam0=lam0, seeds=(seeds[0] + cid, seeds[1] + cid))
+
+
+def _padded(a, dt, pad):
+    """Device copy of a with leading dimension n + pad (row-major view of a wider buffer)."""
+    n = a.shape[0]
+    buf = torch.zeros((n, n + pad), dtype=dt, device=DEV)
+    buf[:, :n] = torch.from_numpy(a).to(DEV).to(dt)
+    return buf[:, :n]
+
+
+def _build(sy, A, y_dtype=None):
+    rows, signs, Y = msp.sketch(A, sy["s"], 8, sy["seeds"][0], y_dtype=y_dtype)
+    return msp.Precond("psd", rows, signs, Y, sy["lam"], sy["lam0"], sy["phi"], 8, sy["seeds"][1])
+
+
+def test_batched_f64_matches_dense_and_oracle():
+    sizes = [130, 257, 400, 64, 515, 333, 97]
+    k = 3
+    say(f"case batched f64 sizes={sizes} k={k}")
+    syss, args, Bs = [], [], []
+    for i, n in enumerate(sizes):
+        sy = _system(n, 500 + i, lengthscale=0.5 + 0.25 * i)
+        A = _padded(sy["a"], torch.float64, pad=i % 3)
+        P = _build(sy, A)
+        Bm = W.gaussian((k, n), 500 + i)
+        Bm[1] = 0.0  # a zero right-hand side
+        syss.append((sy, P))
+        Bs.append(Bm)
+        args.append((P, A, None, torch.from_numpy(Bm).to(DEV)))
+    Xs, infos = msp.solve_batched(args, tol=1e-10, inner_tol=1e-10)
+    for (sy, P), Bm, X, info in zip(syss, Bs, Xs, infos):
+        say(sy["n"], info["status"], info["outer_iters"], info["inner_iters"], info["rel_residual_max"])
+        assert info["status"] == "MSP_OK", info
+        x = X.cpu().numpy()
+        assert np.all(x[1] == 0.0)
+        for j in (0, 2):
+            assert dense.rel_residual_psd(sy["a64"], x[j], Bm[j], sy["lam"]) <= 1e-10
+            xs = dense.solve_psd(sy["a64"], Bm[j], sy["lam"])
+            assert np.linalg.norm(x[j] - xs) <= 1e-7 * np.linalg.norm(xs)
+        # level-1 steps: the oracle's two-level solve on the same sketches, per column
+        O = omsp.PsdMsp(sy["a64"], sy["lam"], sy["lam0"], sy["s"], 8, sy["seeds"][0], sy["phi"], 8, sy["seeds"][1],
+                        omsp.MspOptions(tol=1e-10, inner_tol=1e-10))
+        its = []
+        for j in (0, 2):
+            O.solve(Bm[j])
+            its.append(O.info.outer_iterations)
+        assert abs(info["outer_iters"] - max(its)) <= max(2, 0.03 * max(its)), (info["outer_iters"], its)
+
+
+@pytest.mark.parametrize("lo,hi", [(torch.float32, torch.float32), (torch.bfloat16, torch.float32),
+                                   (torch.float32, torch.float64), (torch.bfloat16, torch.float64)])
+def test_batched_low_precision_refined(lo, hi):
+    sizes = [300, 96, 513, 200]
+    k = 4
+    say(f"case batched refine lo={lo} hi={hi}")
+    syss, args, Bs = [], [], []
+    for i, n in enumerate(sizes):
+        # BF16 sweeps pay off only where lam dominates the rounding perturbation of A
+        lam = 0.5 if lo == torch.bfloat16 else 1e-2
+        sy = _system(n, 600 + i, lam=lam, dtype=np.float32, lengthscale=1.0 + 0.3 * i)
+        A_hi = _padded(sy["a"], hi, pad=(8 if i % 2 else 0))
+        A_lo = torch.empty_strided(A_hi.shape, A_hi.stride(), dtype=lo, device=DEV)
+        A_lo.copy_(A_hi)
+        # the preconditioner comes from the problem matrix (BF16 rounding is not PSD);
+        # the low-precision copy is what the inner MSP sweeps
+        P = _build(sy, torch.from_numpy(sy["a"]).to(DEV))
+        Bm = W.gaussian((k, n), 600 + i)
+        syss.append(sy)
+        Bs.append(Bm)
+        args.append((P, A_hi, A_lo, torch.from_numpy(Bm).to(DEV)))
+    Xs, infos = msp.solve_batched(args, tol=1e-8, refine=1)
+    for sy, Bm, X, info in zip(syss, Bs, Xs, infos):
+        say(sy["n"], info)
+        assert info["status"] == "MSP_OK", info
+        x = X.cpu().numpy()
+        for j in range(k):
+            assert dense.rel_residual_psd(sy["a64"], x[j], Bm[j], sy["lam"]) <= 1e-8
+        assert info["refine_steps"] >= 1
+
+
+def test_batched_deterministic_and_chunks_of_16():
+    sizes = [150, 77, 260]
+    k = 20  # two launches: 16 + 4 right-hand sides
+    say(f"case batched determinism k={k}")
+    args, syss = [], []
+    for i, n in enumerate(sizes):
+        sy = _system(n, 700 + i)
+        A = torch.from_numpy(sy["a"]).to(DEV)
+        P = _build(sy, A)
+        syss.append(sy)
+        args.append((P, A, None, torch.from_numpy(W.gaussian((k, n), 700 + i)).to(DEV)))
+    X1, i1 = msp.solve_batched(args, tol=1e-9)
+    X2, i2 = msp.solve_batched(args, tol=1e-9)
+    for a_, b_, inf in zip(X1, X2, i1):
+        assert inf["status"] == "MSP_OK", inf
+        assert torch.equal(a_, b_)
+    for (P, A, _, Bv), X, sy in zip(args, X1, syss):
+        x = X.cpu().numpy()
+        b = Bv.cpu().numpy()
+        for j in range(k):
+            assert dense.rel_residual_psd(sy["a64"], x[j], b[j], sy["lam"]) <= 1e-9
+
+
+def test_batched_iteration_cap_reports_no_convergence():
+    say("case batched cap")
+    sy = _system(300, 800)
+    A = torch.from_numpy(sy["a"]).to(DEV)
+    P = _build(sy, A)
+    Bv = torch.from_numpy(W.gaussian((2, 300), 800)).to(DEV)
+    _, infos = msp.solve_batched([(P, A, None, Bv)], tol=1e-12, max_outer=2)
+    assert infos[0]["status"] == "MSP_ERR_NO_CONVERGENCE"
