@@ -97,6 +97,13 @@ def main():
                     help="cap the level-1 iterations (counter runs over a few sweeps only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 2 GiB elementwise copy (calibrates the HBM byte counters) and exit")
+    ap.add_argument("--workload", default="rbf_gp_n32768", choices=["rbf_gp_n32768", "batched_rbf_256"],
+                    help="rbf_gp_n32768: the single n=32768 FP64 solve (default); batched_rbf_256: 256 uneven "
+                         "F32 RBF systems x 16 right-hand sides in one batched launch")
+    ap.add_argument("--count", type=int, default=None, help="batched: number of systems (default 256)")
+    ap.add_argument("--lo", default="f32", choices=["f32", "bf16"], help="batched: sweep precision inside MSP")
+    ap.add_argument("--fp64-sample", type=int, default=4,
+                    help="batched: systems timed with the plain FP64 single-RHS solve for comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -118,6 +125,10 @@ def main():
 
     import paper_2405_05865_amd as msp
     import workloads as W
+
+    if args.workload == "batched_rbf_256":
+        bench_batched(args)
+        return
 
     name = "rbf_gp_n32768"
     w = W.config(name) if args.n is None else W.config(name, n=args.n, s=max(8, args.n // 64))
@@ -195,6 +206,144 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(a, b, w, lam0, infos[-1]["outer_iters"], args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def bench_batched(args):
+    """256 uneven RBF systems (n_j ~ U{512..8192}, points in 4 dimensions, lengthscale
+    l_j ~ U(0.5, 2)), lam = 1e-2, 16 right-hand sides each, the F32 matrix is the problem:
+    FP64 Krylov refinement on the F32 matrix around the MSP solve with F32 (or BF16) sweeps,
+    all systems in one msp_solve_batched launch. A step = sketch + Nystrom factors of every
+    system + the batched solve to relative residual 1e-8."""
+    import numpy as np
+    import torch
+
+    import paper_2405_05865_amd as msp
+    import workloads as W
+
+    w = W.config("batched_rbf_256")
+    count = args.count or w.extra["count"]
+    nrhs = w.nrhs
+    dev = torch.device("cuda:0")
+    msp.library()
+    sizes, ls = W.batched_rbf_sizes(count, w.config_id)
+    log(f"[bench] batched: {count} systems, sum n^2 = {float(np.sum(sizes.astype(np.float64) ** 2)):.3e}")
+    t = time.time()
+    systems = []
+    for j in range(count):
+        n = int(sizes[j])
+        a, b = W.batched_rbf_system(j, n, float(ls[j]), w.extra["dim"], nrhs, w.config_id)
+        ld = (n + 7) // 8 * 8  # 32-byte rows for the F32 and BF16 copies
+        buf = torch.zeros((n, ld), dtype=torch.float32, device=dev)
+        buf[:, :n] = torch.from_numpy(a).to(dev)
+        A = buf[:, :n]
+        A_lo = A
+        if args.lo == "bf16":
+            lb = torch.zeros((n, ld), dtype=torch.bfloat16, device=dev)
+            lb[:, :n] = A
+            A_lo = lb[:, :n]
+        s = min(w.s, n // 2)
+        phi = min(4 * s, n)
+        # the paper's lam0 = (2/l) sum_{i>l} lambda_i, l = s/2, from the spectrum of the F32 matrix
+        ev = torch.linalg.eigvalsh(A.double()).flip(0)
+        lam0 = float(2.0 / (s // 2) * ev[s // 2:].clamp_min(0).sum())
+        systems.append(dict(n=n, A=A, A_lo=A_lo, B=torch.from_numpy(b).to(dev), s=s, phi=phi, lam0=lam0,
+                            seed=w.seed_s + 97 * j, seed_phi=w.seed_s + 97 * j + 8))
+        if j % 32 == 31:
+            log(f"[bench] generated {j + 1}/{count} systems ({time.time() - t:.0f} s)")
+    torch.cuda.synchronize()
+    log(f"[bench] inputs resident in HBM ({time.time() - t:.1f} s)")
+
+    def step():
+        t0 = time.perf_counter()
+        Ps = []
+        for q in systems:
+            rows, signs, Y = msp.sketch(q["A"], q["s"], w.gamma, q["seed"])
+            Ps.append(msp.Precond("psd", rows, signs, Y, w.lam, q["lam0"], q["phi"], w.phi_gamma, q["seed_phi"]))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Xs, infos = msp.solve_batched([(P, q["A"], q["A_lo"], q["B"]) for P, q in zip(Ps, systems)], tol=w.tol,
+                                      refine=1, profile=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for P in Ps:
+            P.close()
+        return infos, t1 - t0, t2 - t1
+
+    for i in range(args.warmup):
+        infos, ts, tv = step()
+        log(f"[bench] warmup {i}: setup {ts * 1e3:.0f} ms, solve {tv * 1e3:.0f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    setup_t = solve_t = 0.0
+    for i in range(args.steps):
+        infos, ts, tv = step()
+        setup_t += ts
+        solve_t += tv
+        bad = [k for k, d in enumerate(infos) if d["status"] != "MSP_OK"]
+        log(f"[bench] step {i}: setup {ts * 1e3:.0f} ms, solve {tv * 1e3:.0f} ms, not converged: {len(bad)}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / args.steps
+    value = count * nrhs / (el / args.steps)
+    worst = max(d["rel_residual_max"] for d in infos)
+    ok = all(d["status"] == "MSP_OK" for d in infos) and worst <= w.tol
+    # A bytes streamed by the batched kernel: level-1 steps on A_lo plus refinement steps
+    # (and their confirmations) on the F32 matrix, per 16-column launch
+    lo_bytes = 2 if args.lo == "bf16" else 4
+    a_bytes = sum(float(q["n"]) ** 2 * (d["outer_iters"] * lo_bytes + (d["refine_steps"] + 2) * 4)
+                  for q, d in zip(systems, infos))
+    eff = a_bytes / (solve_t / args.steps) / 1e9
+
+    # the plain FP64 single-RHS form on a sample of the same systems, same accuracy
+    fp64 = None
+    if args.fp64_sample > 0:
+        idx = np.linspace(0, count - 1, min(args.fp64_sample, count)).astype(int)
+        tt, nn = 0.0, 0
+        for j in idx:
+            q = systems[j]
+            A64 = q["A"].double().contiguous()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rows, signs, Y = msp.sketch(A64, q["s"], w.gamma, q["seed"])
+            P = msp.Precond("psd", rows, signs, Y, w.lam, q["lam0"], q["phi"], w.phi_gamma, q["seed_phi"])
+            X, info = msp.solve(P, A64, q["B"][0].contiguous(), tol=w.tol)
+            torch.cuda.synchronize()
+            tt += time.perf_counter() - t1
+            nn += 1
+            P.close()
+            del A64
+        per_rhs = tt / nn
+        fp64 = {"value": round(1.0 / per_rhs, 3), "unit": "RHS-solves/s",
+                "sample": f"{nn} of the systems, one right-hand side each, msp_solve FP64 (sketch + factors + solve)"}
+
+    line = {
+        "metric": "RHS-solves/sec at rel. residual 1e-8, batched mixed precision (256 uneven RBF systems x 16 RHS)",
+        "value": round(value, 2),
+        "unit": "RHS-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.lo == "f32" else "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"batched_rbf_{count}", "count": count, "nrhs": nrhs, "n_range": [512, 8192],
+                   "sum_n2": float(np.sum(sizes.astype(np.float64) ** 2)), "s": "min(256, n/2)", "gamma": w.gamma,
+                   "phi": "min(4s, n)", "lambda": w.lam, "tol": w.tol, "matrix": "f32", "sweeps": args.lo,
+                   "refinement": "fp64 krylov"},
+        "setup_ms_per_step": round(1e3 * setup_t / args.steps, 2),
+        "solve_ms_per_step": round(1e3 * solve_t / args.steps, 2),
+        "a_sweep_bytes_per_step": a_bytes,
+        "effective_gbs_of_batched_kernel": round(eff, 1),
+        "outer_iters_max": max(d["outer_iters"] for d in infos),
+        "refine_steps_max": max(d["refine_steps"] for d in infos),
+        "rel_residual_max": worst,
+        "converged": ok,
+        "fp64_single_rhs": fp64,
+    }
     print(json.dumps(line), flush=True)
 
 

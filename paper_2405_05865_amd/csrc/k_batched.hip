@@ -70,6 +70,13 @@ __device__ __forceinline__ double wsum(double v) {
 __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
+// Global-memory view of a pointer (the pointers reach the kernel through a descriptor
+// table, so the compiler cannot infer the address space and would emit flat accesses)
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gv(const void* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+
 // Loads of VEC consecutive matrix elements (one 16-byte access when aligned), converted
 // to the arithmetic type TC.
 template <class TA, class TC>
@@ -80,8 +87,8 @@ struct Ld<double, double> {
   template <bool NTL>
   __device__ static void vec(const double* p, double* o) {
     nd2 v;
-    if constexpr (NTL) v = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(p));
-    else v = *reinterpret_cast<const nd2*>(p);
+    if constexpr (NTL) v = __builtin_nontemporal_load(gv<nd2>(p));
+    else v = *gv<nd2>(p);
     o[0] = v.x;
     o[1] = v.y;
   }
@@ -93,8 +100,8 @@ struct Ld<float, float> {
   template <bool NTL>
   __device__ static void vec(const float* p, float* o) {
     nf4 v;
-    if constexpr (NTL) v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(p));
-    else v = *reinterpret_cast<const nf4*>(p);
+    if constexpr (NTL) v = __builtin_nontemporal_load(gv<nf4>(p));
+    else v = *gv<nf4>(p);
     o[0] = v.x;
     o[1] = v.y;
     o[2] = v.z;
@@ -108,8 +115,8 @@ struct Ld<float, double> {
   template <bool NTL>
   __device__ static void vec(const float* p, double* o) {
     nf4 v;
-    if constexpr (NTL) v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(p));
-    else v = *reinterpret_cast<const nf4*>(p);
+    if constexpr (NTL) v = __builtin_nontemporal_load(gv<nf4>(p));
+    else v = *gv<nf4>(p);
     o[0] = v.x;
     o[1] = v.y;
     o[2] = v.z;
@@ -123,8 +130,8 @@ struct Ld<__hip_bfloat16, float> {
   template <bool NTL>
   __device__ static void vec(const __hip_bfloat16* p, float* o) {
     nu4 v;
-    if constexpr (NTL) v = __builtin_nontemporal_load(reinterpret_cast<const nu4*>(p));
-    else v = *reinterpret_cast<const nu4*>(p);
+    if constexpr (NTL) v = __builtin_nontemporal_load(gv<nu4>(p));
+    else v = *gv<nu4>(p);
     o[0] = bf_lo(v.x);
     o[1] = bf_hi(v.x);
     o[2] = bf_lo(v.y);
@@ -143,7 +150,7 @@ __device__ __forceinline__ void ld_b(const TC* p, TC* o) {
   if constexpr (sizeof(TC) == 4) {
 #pragma unroll
     for (int q = 0; q < VEC / 4; ++q) {
-      const nf4 v = *reinterpret_cast<const nf4*>(p + 4 * q);
+      const nf4 v = *gv<nf4>(p + 4 * q);
       o[4 * q] = v.x;
       o[4 * q + 1] = v.y;
       o[4 * q + 2] = v.z;
@@ -152,7 +159,7 @@ __device__ __forceinline__ void ld_b(const TC* p, TC* o) {
   } else {
 #pragma unroll
     for (int q = 0; q < VEC / 2; ++q) {
-      const nd2 v = *reinterpret_cast<const nd2*>(p + 2 * q);
+      const nd2 v = *gv<nd2>(p + 2 * q);
       o[2 * q] = v.x;
       o[2 * q + 1] = v.y;
     }
@@ -185,6 +192,45 @@ __device__ __forceinline__ void mm_rows(const TA* __restrict__ A, int64_t lda, i
   }
   int c0 = 0;
   if constexpr (ALN) {
+    // trips of UN steps, double-buffered: the loads of trip t + 1 are in flight while
+    // the MFMAs of trip t run
+    constexpr int REGS = RT * VEC * (int)sizeof(TC) / 4;
+    constexpr int UN = REGS >= 32 ? 1 : (REGS >= 16 ? 2 : (REGS >= 8 ? 4 : 8));
+    constexpr int TRIP = UN * STEP;
+    struct Buf {
+      TC a[UN][RT][VEC];
+      TC b[UN][VEC];
+    };
+    auto load = [&](Buf& x, int cb) {
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) L::template vec<NTL>(ap[t] + cb + u * STEP, x.a[u][t]);
+        ld_b<TC, VEC>(bp + cb + u * STEP, x.b[u]);
+      }
+    };
+    auto run = [&](const Buf& x) {
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int m = 0; m < VEC; ++m)
+#pragma unroll
+          for (int t = 0; t < RT; ++t) acc[t] = mfma(x.a[u][t][m], x.b[u][m], acc[t]);
+    };
+    const int T = ncols / TRIP;
+    if (T > 0) {
+      Buf x0, x1;
+      load(x0, 0);
+      int t = 0;
+      for (; t + 2 <= T; t += 2) {
+        load(x1, (t + 1) * TRIP);
+        run(x0);
+        if (t + 2 < T) load(x0, (t + 2) * TRIP);
+        run(x1);
+      }
+      if (t < T) run(x0);
+      c0 = T * TRIP;
+    }
     for (; c0 + STEP <= ncols; c0 += STEP) {
       TC a[RT][VEC], b[VEC];
 #pragma unroll
@@ -255,6 +301,20 @@ struct Ctx {
   double* red;   // [NW][256]
   double* part;  // [NW][KB]
   int outer, inner, refine, restarts;
+  uint64_t ticks[BT_NPHASE];  // thread 0, when P.profile
+};
+
+// wall-clock phase timer (thread 0 of the workgroup; phases end on a barrier)
+struct PhaseTimer {
+  Ctx& c;
+  int ph;
+  uint64_t t0;
+  __device__ PhaseTimer(Ctx& cc, int p) : c(cc), ph(p), t0(0) {
+    if (c.P.profile && threadIdx.x == 0) t0 = wall_clock64();
+  }
+  __device__ ~PhaseTimer() {
+    if (c.P.profile && threadIdx.x == 0) c.ticks[ph] += wall_clock64() - t0;
+  }
 };
 
 __device__ __forceinline__ int wave_id() { return threadIdx.x / WAVE; }
@@ -288,6 +348,7 @@ struct Batch {
   // ---- matrix products -----------------------------------------------------------
   // q1 = (A_lo + lam_lo I) p1 and C1->pq = <p1, q1>
   static __device__ void op_lo(Ctx& c) {
+    PhaseTimer tm(c, BT_SWEEP_LO);
     const int w = wave_id(), lane = lane_id();
     const double lam = c.lam_lo;
     double pq = 0.0;
@@ -301,7 +362,7 @@ struct Batch {
       rows_pass<TLO, double, 4, true>((const TLO*)c.S.A_lo, c.S.lda, c.n, c.n, c.S.aln_lo, c.p1, c.ldn, c.k, epi);
     } else {
       if (w < c.k)
-        for (int i = lane; i < c.n; i += WAVE) c.pf[(int64_t)w * c.ldn + i] = (float)c.p1[(int64_t)w * c.ldn + i];
+        _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) c.pf[(int64_t)w * c.ldn + i] = (float)c.p1[(int64_t)w * c.ldn + i];
       __syncthreads();
       rows_pass<TLO, float, 4, true>((const TLO*)c.S.A_lo, c.S.lda, c.n, c.n, c.S.aln_lo, c.pf, c.ldn, c.k, epi);
     }
@@ -311,6 +372,7 @@ struct Batch {
   // FP64 products with A_hi: mode 0: qh = (A_hi + lam I) ph, CH->pq = <ph, qh>;
   // mode 1: out = rhs - (A_hi + lam I) x
   static __device__ void op_hi(Ctx& c, int mode, const double* x, const double* rhs, int64_t ldr, double* out) {
+    PhaseTimer tm(c, BT_SWEEP_HI);
     const double lam = c.S.lam;
     double pq = 0.0;
     auto epi = [&](int j, int row, double v) {
@@ -337,6 +399,7 @@ struct Batch {
 
   // z1 = (r1 - Y y2) / lam~ for the columns active at level 1
   static __device__ void y_z(Ctx& c) {
+    PhaseTimer tm(c, BT_YZ);
     const double inv = 1.0 / c.S.lt;
     const Cols* C1 = c.C1;
     auto epi = [&](int j, int row, double v) {
@@ -351,6 +414,7 @@ struct Batch {
   // b2 = Y^T r1: column tiles of Y (16 columns) as MFMA rows, rows of Y as the reduction;
   // with fewer tiles than wavefronts the rows are split and the splits summed in order
   static __device__ void yt_r(Ctx& c) {
+    PhaseTimer tm(c, BT_YT);
     const int w = wave_id(), lane = lane_id(), i = lane & 15, g = lane >> 4;
     const int T = (c.s + 15) / 16;
     const int RS = T >= NW ? 1 : NW / T;
@@ -365,7 +429,19 @@ struct Batch {
       const int col = min(c0 + i, c.s - 1);
       const int rb = split * per, re = min(c.n, rb + per);
       v4d acc = {0, 0, 0, 0};
-      for (int r = rb; r < re; r += 16) {
+      int r = rb;
+      for (; r + 64 <= re; r += 64) {
+        double a[16], b[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int row = r + 4 * u + g;
+          a[u] = (double)Y[(int64_t)row * ldy + col];
+          b[u] = V[row];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = mfma(a[u], b[u], acc);
+      }
+      for (; r < re; r += 16) {
         double a[4], b[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -436,7 +512,7 @@ struct Batch {
     if (w < c.k) {
       const bool act = c.C1->done[w] == 0;
       double acc = 0.0;
-      for (int i = lane; i < c.s; i += WAVE) {
+      _Pragma("unroll 4") for (int i = lane; i < c.s; i += WAVE) {
         const int64_t o = (int64_t)w * c.lds + i;
         const double v = act ? c.b2[o] : 0.0;
         c.r2[o] = v;
@@ -452,10 +528,11 @@ struct Batch {
       }
     }
     __syncthreads();
+    const uint64_t l2t0 = (c.P.profile && threadIdx.x == 0) ? wall_clock64() : 0;
     smv(c, c.S.Minv, c.r2, c.z2);
     if (w < c.k && D->done[w] == 0) {
       double acc = 0.0;
-      for (int i = lane; i < c.s; i += WAVE) {
+      _Pragma("unroll 4") for (int i = lane; i < c.s; i += WAVE) {
         const int64_t o = (int64_t)w * c.lds + i;
         const double z = c.z2[o];
         c.p2[o] = z;
@@ -471,7 +548,7 @@ struct Batch {
       smv(c, c.S.H, c.p2, c.q2);
       if (w < c.k && D->done[w] == 0) {
         double pq = 0.0;
-        for (int i = lane; i < c.s; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.s; i += WAVE) {
           const int64_t o = (int64_t)w * c.lds + i;
           pq = fma(c.p2[o], c.q2[o], pq);
         }
@@ -479,7 +556,7 @@ struct Batch {
         const bool brk = !(pq > 0.0);
         const double al = brk ? 0.0 : D->rz[w] / pq;
         double acc = 0.0;
-        for (int i = lane; i < c.s; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.s; i += WAVE) {
           const int64_t o = (int64_t)w * c.lds + i;
           c.y2[o] = fma(al, c.p2[o], c.y2[o]);
           const double rv = c.r2[o];
@@ -504,7 +581,7 @@ struct Batch {
       smv(c, c.S.Minv, c.r2, c.z2);
       if (w < c.k && D->done[w] == 0) {
         double zr = 0.0, zro = 0.0;
-        for (int i = lane; i < c.s; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.s; i += WAVE) {
           const int64_t o = (int64_t)w * c.lds + i;
           const double z = c.z2[o];
           zr = fma(z, c.r2[o], zr);
@@ -513,14 +590,17 @@ struct Batch {
         zr = wsum(zr);
         zro = wsum(zro);
         const double beta = (zr - zro) / D->rz[w];
-        for (int i = lane; i < c.s; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.s; i += WAVE) {
           const int64_t o = (int64_t)w * c.lds + i;
           c.p2[o] = fma(beta, c.p2[o], c.z2[o]);
         }
         if (lane == 0) D->rz[w] = zr;
       }
     }
-    if (threadIdx.x == 0) c.inner += it;
+    if (threadIdx.x == 0) {
+      c.inner += it;
+      if (c.P.profile) c.ticks[BT_LEVEL2] += wall_clock64() - l2t0;
+    }
     __syncthreads();
     y_z(c);
   }
@@ -534,7 +614,7 @@ struct Batch {
     if (w < c.k) {
       const bool sk = skip && skip[w] != 0;
       double acc = 0.0;
-      for (int i = lane; i < c.n; i += WAVE) {
+      _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
         const int64_t o = (int64_t)w * c.ldn + i;
         const double v = sk ? 0.0 : rhs[(int64_t)w * ldr + i];
         c.r1[o] = v;
@@ -558,7 +638,7 @@ struct Batch {
         solve_m1(c);
         if (w < c.k && C->done[w] == 0) {
           double acc = 0.0;
-          for (int i = lane; i < c.n; i += WAVE) {
+          _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
             const int64_t o = (int64_t)w * c.ldn + i;
             const double z = c.z1[o];
             c.p1[o] = z;
@@ -576,7 +656,7 @@ struct Batch {
         op_hi(c, 1, c.zh, rhs, ldr, c.q1);
         if (w < c.k && C->done[w] == 1) {
           double acc = 0.0;
-          for (int i = lane; i < c.n; i += WAVE) {
+          _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
             const double v = c.q1[(int64_t)w * c.ldn + i];
             acc = fma(v, v, acc);
           }
@@ -584,7 +664,7 @@ struct Batch {
           const double rel = bn > 0.0 ? sqrt(wsum(acc)) / bn : 0.0;
           const bool ok = rel <= tol;
           if (!ok)
-            for (int i = lane; i < c.n; i += WAVE) c.r1[(int64_t)w * c.ldn + i] = c.q1[(int64_t)w * c.ldn + i];
+            _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) c.r1[(int64_t)w * c.ldn + i] = c.q1[(int64_t)w * c.ldn + i];
           if (lane == 0) {
             C->rel[w] = rel;
             C->done[w] = ok ? 4 : 0;
@@ -612,7 +692,7 @@ struct Batch {
         const bool brk = !(pq > 0.0);
         const double al = brk ? 0.0 : C->rz[w] / pq;
         double acc = 0.0;
-        for (int i = lane; i < c.n; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
           const int64_t o = (int64_t)w * c.ldn + i;
           c.zh[o] = fma(al, c.p1[o], c.zh[o]);
           const double rv = c.r1[o];
@@ -636,7 +716,7 @@ struct Batch {
       solve_m1(c);
       if (w < c.k && C->done[w] == 0) {
         double zr = 0.0, zro = 0.0;
-        for (int i = lane; i < c.n; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
           const int64_t o = (int64_t)w * c.ldn + i;
           const double z = c.z1[o];
           zr = fma(z, c.r1[o], zr);
@@ -645,7 +725,7 @@ struct Batch {
         zr = wsum(zr);
         zro = wsum(zro);
         const double beta = (zr - zro) / C->rz[w];
-        for (int i = lane; i < c.n; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
           const int64_t o = (int64_t)w * c.ldn + i;
           c.p1[o] = fma(beta, c.p1[o], c.z1[o]);
         }
@@ -667,7 +747,7 @@ struct Batch {
     const int64_t ldb = c.S.ldb;
     if (w < c.k) {
       double acc = 0.0;
-      for (int i = lane; i < c.n; i += WAVE) {
+      _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
         const int64_t o = (int64_t)w * c.ldn + i;
         const double v = B[(int64_t)w * ldb + i];
         c.rh[o] = v;
@@ -691,7 +771,7 @@ struct Batch {
         level1(c, c.rh, c.ldn, c.P.refine_tol, R->done, false);
         if (w < c.k && R->done[w] == 0) {
           double acc = 0.0;
-          for (int i = lane; i < c.n; i += WAVE) {
+          _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
             const int64_t o = (int64_t)w * c.ldn + i;
             const double z = c.zh[o];
             c.ph[o] = z;
@@ -707,7 +787,7 @@ struct Batch {
         op_hi(c, 1, c.xh, B, ldb, c.qh);
         if (w < c.k && R->done[w] == 1) {
           double acc = 0.0;
-          for (int i = lane; i < c.n; i += WAVE) {
+          _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
             const double v = c.qh[(int64_t)w * c.ldn + i];
             acc = fma(v, v, acc);
           }
@@ -715,7 +795,7 @@ struct Batch {
           const double rel = bn > 0.0 ? sqrt(wsum(acc)) / bn : 0.0;
           const bool ok = rel <= c.P.tol;
           if (!ok)
-            for (int i = lane; i < c.n; i += WAVE) c.rh[(int64_t)w * c.ldn + i] = c.qh[(int64_t)w * c.ldn + i];
+            _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) c.rh[(int64_t)w * c.ldn + i] = c.qh[(int64_t)w * c.ldn + i];
           if (lane == 0) {
             R->rel[w] = rel;
             R->done[w] = ok ? 4 : 0;
@@ -743,7 +823,7 @@ struct Batch {
         const bool brk = !(pq > 0.0);
         const double al = brk ? 0.0 : R->rz[w] / pq;
         double acc = 0.0;
-        for (int i = lane; i < c.n; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
           const int64_t o = (int64_t)w * c.ldn + i;
           c.xh[o] = fma(al, c.ph[o], c.xh[o]);
           const double rv = c.rh[o];
@@ -767,7 +847,7 @@ struct Batch {
       level1(c, c.rh, c.ldn, c.P.refine_tol, R->done, false);
       if (w < c.k && R->done[w] == 0) {
         double zr = 0.0, zro = 0.0;
-        for (int i = lane; i < c.n; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
           const int64_t o = (int64_t)w * c.ldn + i;
           const double z = c.zh[o];
           zr = fma(z, c.rh[o], zr);
@@ -776,7 +856,7 @@ struct Batch {
         zr = wsum(zr);
         zro = wsum(zro);
         const double beta = (zr - zro) / R->rz[w];
-        for (int i = lane; i < c.n; i += WAVE) {
+        _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
           const int64_t o = (int64_t)w * c.ldn + i;
           c.ph[o] = fma(beta, c.ph[o], c.zh[o]);
         }
@@ -833,6 +913,8 @@ __global__ void __launch_bounds__(NTB) k_batch_psd(const BatchSys* __restrict__ 
   c.red = red;
   c.part = part;
   c.outer = c.inner = c.refine = c.restarts = 0;
+  for (int q = 0; q < BT_NPHASE; ++q) c.ticks[q] = 0;
+  const uint64_t tstart = (prm.profile && threadIdx.x == 0) ? wall_clock64() : 0;
   using BT = Batch<TLO, THI, TY>;
   const bool do_refine = prm.refine != 0;
   // Under refinement the inner MSP sweeps A_lo + (lam + delta) I with
@@ -850,7 +932,7 @@ __global__ void __launch_bounds__(NTB) k_batch_psd(const BatchSys* __restrict__ 
   const double* xs = do_refine ? c.xh : c.zh;
   const int w = wave_id(), lane = lane_id();
   if (w < k)
-    for (int i = lane; i < c.n; i += WAVE) c.S.X[(int64_t)w * c.S.ldx + i] = xs[(int64_t)w * c.ldn + i];
+    _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) c.S.X[(int64_t)w * c.S.ldx + i] = xs[(int64_t)w * c.ldn + i];
   if (threadIdx.x == 0) {
     BatchOut o;
     int worst = 0;  // 0 ok, 1 cap, 2 breakdown, 3 non-finite
@@ -869,6 +951,8 @@ __global__ void __launch_bounds__(NTB) k_batch_psd(const BatchSys* __restrict__ 
     o.refine = c.refine;
     o.restarts = c.restarts;
     o.relres = rel;
+    if (prm.profile) c.ticks[BT_TOTAL] = wall_clock64() - tstart;
+    for (int q = 0; q < BT_NPHASE; ++q) o.ticks[q] = c.ticks[q];
     out[c.S.id] = o;
   }
 }

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <numeric>
 #include <vector>
@@ -15,6 +17,11 @@
   } while (0)
 
 namespace {
+
+bool batch_log_on() {
+  const char* e = getenv("MSP_LOG");
+  return e && e[0] && e[0] != '0';
+}
 
 size_t esize(msp_dtype t) { return t == MSP_F64 ? 8 : (t == MSP_F32 ? 4 : 2); }
 int64_t round8(int64_t v) { return (v + 7) / 8 * 8; }
@@ -148,6 +155,13 @@ extern "C" msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_sy
   prm.max_refine = o->max_refine;
   prm.refine = (o->refine && lo_t != MSP_F64) ? 1 : 0;
   prm.kcap = kcap;
+  prm.profile = o->profile ? 1 : 0;
+  int clock_khz = 0;
+  if (prm.profile) {
+    int dev = 0;
+    MSP_CHECK_HIP(hipGetDevice(&dev));
+    MSP_CHECK_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
+  }
 
   std::vector<BatchSys> hs(nsys);
   std::vector<BatchOut> ho(nsys);
@@ -205,6 +219,17 @@ extern "C" msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_sy
       a.krylov_refine = prm.refine;
       a.rel_residual_max = std::max(a.rel_residual_max, r.relres);
       a.sweeps += (int64_t)r.outer + r.refine;
+      if (prm.profile && clock_khz > 0) {
+        // sweep_ms: the level-1 sweeps of this system; the other phases go to the log
+        const double ms = 1.0 / clock_khz;
+        a.sweep_ms += r.ticks[BT_SWEEP_LO] * ms;
+        a.timed_sweeps += r.outer;
+        if (batch_log_on())
+          fprintf(stderr, "[msp] batch system %d n=%d: total %.2f ms | sweep_lo %.2f  sweep_hi %.2f  Y^T r %.2f  "
+                          "level-2 %.2f  Y y %.2f | outer %d inner %d refine %d\n",
+                  i, (int)sys[i].P->n, r.ticks[BT_TOTAL] * ms, r.ticks[BT_SWEEP_LO] * ms, r.ticks[BT_SWEEP_HI] * ms,
+                  r.ticks[BT_YT] * ms, r.ticks[BT_LEVEL2] * ms, r.ticks[BT_YZ] * ms, r.outer, r.inner, r.refine);
+      }
     }
   }
   msp_status ret = MSP_OK;

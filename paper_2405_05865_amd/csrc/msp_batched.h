@@ -30,13 +30,16 @@ struct BatchPrm {
   double tol, inner_tol, refine_tol;
   int32_t max_outer, max_inner, max_refine, refine;
   int32_t kcap;       // columns allocated per vector
-  int32_t pad;
+  int32_t profile;    // record wall-clock time per phase (BatchOut.ticks)
 };
+
+enum { BT_SWEEP_LO = 0, BT_SWEEP_HI, BT_YT, BT_LEVEL2, BT_YZ, BT_TOTAL, BT_NPHASE };
 
 struct BatchOut {
   int32_t code;       // 0 ok, 1 tolerance not reached, 2 breakdown, 3 non-finite
   int32_t outer, inner, refine, restarts, pad;
   double relres;      // largest confirmed relative residual on A_hi
+  uint64_t ticks[BT_NPHASE];  // profile: wall-clock ticks per phase (thread 0's view)
 };
 
 bool batch_types_supported(msp_dtype lo_t, msp_dtype hi_t, msp_dtype y_t);

@@ -17,6 +17,8 @@ from .generators import (  # noqa: F401
     householder_apply,
     schatten_psd,
     batched_rbf_sizes,
+    batched_rbf_system,
+    system_rng,
     gaussian,
     config,
     CONFIGS,

@@ -111,6 +111,20 @@ def batched_rbf_sizes(count: int, config_id: int, lo: int = 512, hi: int = 8192,
     return sizes, ls
 
 
+def system_rng(config_id: int, stream: int, index: int) -> np.random.Generator:
+    """The generator of one system of a batch (its own seed per index)."""
+    return np.random.default_rng(np.random.SeedSequence([BASE_SEED, int(config_id), int(stream), int(index)]))
+
+
+def batched_rbf_system(index: int, n: int, lengthscale: float, dim: int, nrhs: int, config_id: int):
+    """System `index` of a batch: the F32 RBF matrix (formed in FP64, rounded to nearest
+    F32: the F32 matrix is the problem) and nrhs standard normal right-hand sides."""
+    pts = system_rng(config_id, _POINTS, index).standard_normal((n, dim))
+    a = rbf_matrix(pts, lengthscale=lengthscale, dtype=np.float32)
+    b = system_rng(config_id, _RHS, index).standard_normal((nrhs, n))
+    return a, b
+
+
 # ----------------------------------------------------------------------------------
 # Householder-product orthogonal factors
 # ----------------------------------------------------------------------------------
