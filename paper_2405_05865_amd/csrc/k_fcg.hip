@@ -365,6 +365,27 @@ __global__ void k_outer_neg(int64_t n, int k, const double* __restrict__ dB, int
     }
 }
 
+// out[0] = max_i sum_j |A[i, j]| (FP64; one block, fixed order)
+template <class TA>
+__global__ void __launch_bounds__(NT) k_row_abs_max(const TA* __restrict__ A, int64_t rows, int64_t cols, int64_t lda,
+                                                   double* out) {
+  __shared__ double sh[NT / WAVE];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  double mx = 0.0;
+  for (int64_t r = w; r < rows; r += NT / WAVE) {
+    double t = 0.0;
+    for (int64_t c = lane; c < cols; c += WAVE) t += fabs((double)A[r * lda + c]);
+    mx = fmax(mx, wave_sum(t));
+  }
+  if (lane == 0) sh[w] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int q = 0; q < NT / WAVE; ++q) m = fmax(m, sh[q]);
+    out[0] = m;
+  }
+}
+
 unsigned grid_x(int64_t len) {
   int64_t b = (len + NT * 2 - 1) / (NT * 2);
   if (b < 1) b = 1;
@@ -511,6 +532,17 @@ hipError_t launch_outer_neg(hipStream_t st, int64_t n, int64_t k, const double* 
                      dim3(256), 0, st, n, (int)k, dB, lddb, X, ldx, dA, ldda);
   return hipGetLastError();
 }
+hipError_t launch_row_abs_max(hipStream_t st, const void* A, msp_dtype t, int64_t rows, int64_t cols, int64_t lda,
+                              double* out) {
+  if (t == MSP_F64)
+    hipLaunchKernelGGL(k_row_abs_max<double>, dim3(1), dim3(NT), 0, st, (const double*)A, rows, cols, lda, out);
+  else if (t == MSP_F32)
+    hipLaunchKernelGGL(k_row_abs_max<float>, dim3(1), dim3(NT), 0, st, (const float*)A, rows, cols, lda, out);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_block(hipStream_t st, int64_t len, int64_t k, const double* x, int64_t ldx, double* y,
                              int64_t ldy) {
   return launch_axpby(st, len, k, 1.0, x, ldx, 0.0, nullptr, 0, y, ldy, nullptr);

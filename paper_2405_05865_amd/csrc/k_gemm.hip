@@ -1,0 +1,273 @@
+// Block A-sweep for many right-hand sides on the matrix cores:
+//   Y[:, j] = A X[:, j] (+ lam X[:, j]) for j < k (k >= 8),
+// the level-1 operator of Algorithms 1 and 3 applied to a block of k vectors at once
+// (the block execution of the method for many right-hand sides or trace probes).
+//
+// Work unit: one wavefront computes a 16*RT-row x 16*KT-column output tile with
+// 16x16x4 MFMA (F32 arithmetic for F32/BF16 storage, F64 for F64 storage and for the
+// FP64-on-F32 residual form). Lane l supplies row (l % 16) of each 16-row tile and the
+// reduction slice [c0 + VEC (l / 16), +VEC) of each step, for both operands, so one
+// 16-byte load per row feeds VEC MFMAs. Neighbouring wavefronts take the column groups
+// of the same rows, so A is read from HBM about once per 4*16*KT columns and reused
+// from cache by the others. Per-column dot partials <X_j, Y_j> per row set feed the
+// level-1 step length (the same layout as the single-vector sweep).
+#include "msp_internal.h"
+
+#include <hip/hip_bf16.h>
+
+namespace {
+
+constexpr int WAVE = 64;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef uint32_t nu4 __attribute__((ext_vector_type(4)));
+
+template <class TC>
+struct V4;
+template <>
+struct V4<float> {
+  typedef v4f t;
+};
+template <>
+struct V4<double> {
+  typedef v4d t;
+};
+
+__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// element e of lane l holds tile row out_row(l / 16, e), column l % 16
+template <class TC>
+__device__ __forceinline__ int out_row(int g, int e) {
+  return sizeof(TC) == 4 ? 4 * g + e : 4 * e + g;
+}
+
+__device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+template <class TA, class TC>
+struct Ld;
+template <>
+struct Ld<double, double> {
+  static constexpr int VEC = 2;
+  __device__ static void vec(const double* p, double* o) {
+    const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(p));
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+  __device__ static double one(const double* p) { return *p; }
+};
+template <>
+struct Ld<float, float> {
+  static constexpr int VEC = 4;
+  __device__ static void vec(const float* p, float* o) {
+    const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(p));
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+  __device__ static float one(const float* p) { return *p; }
+};
+template <>
+struct Ld<float, double> {
+  static constexpr int VEC = 4;
+  __device__ static void vec(const float* p, double* o) {
+    const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(p));
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+  __device__ static double one(const float* p) { return (double)*p; }
+};
+template <>
+struct Ld<__hip_bfloat16, float> {
+  static constexpr int VEC = 8;
+  __device__ static void vec(const __hip_bfloat16* p, float* o) {
+    const nu4 v = __builtin_nontemporal_load(reinterpret_cast<const nu4*>(p));
+    o[0] = bf_lo(v.x);
+    o[1] = bf_hi(v.x);
+    o[2] = bf_lo(v.y);
+    o[3] = bf_hi(v.y);
+    o[4] = bf_lo(v.z);
+    o[5] = bf_hi(v.z);
+    o[6] = bf_lo(v.w);
+    o[7] = bf_hi(v.w);
+  }
+  __device__ static float one(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+};
+
+// VEC consecutive FP64 vector entries (16-byte aligned when the vector's rows are),
+// converted to the arithmetic type
+template <class TC, int VEC, bool ALN>
+__device__ __forceinline__ void ld_x(const double* p, TC* o) {
+  if constexpr (ALN) {
+#pragma unroll
+    for (int q = 0; q < VEC / 2; ++q) {
+      const nd2 v = *reinterpret_cast<const nd2*>(p + 2 * q);
+      o[2 * q] = (TC)v.x;
+      o[2 * q + 1] = (TC)v.y;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) o[q] = (TC)p[q];
+  }
+}
+
+template <class TA, class TC, int RT, int KT, bool ALN>
+__global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t lda, int rows, int cols,
+                                             const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
+                                             int64_t ldy, int k, double lam, int diag,
+                                             const int32_t* __restrict__ skip, double* __restrict__ dot_part,
+                                             int nrs, int ncs) {
+  using L = Ld<TA, TC>;
+  constexpr int VEC = L::VEC;
+  constexpr int STEP = 4 * VEC;
+  const int wg = blockIdx.x * 4 + threadIdx.x / WAVE;  // global wavefront index
+  if (wg >= nrs * ncs) return;                           // whole wavefronts only
+  const int rs = wg / ncs, cs = wg % ncs;
+  const int lane = threadIdx.x & (WAVE - 1), i = lane & 15, g = lane >> 4;
+  const int r0 = rs * 16 * RT;
+  const int gbase = cs * KT;  // first 16-column group of this wavefront
+  // X is read in aligned pairs only when the vectors' rows are 16-byte aligned
+  const TA* ap[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) ap[t] = A + (int64_t)min(r0 + 16 * t + i, rows - 1) * lda + VEC * g;
+  const double* bp[KT];
+#pragma unroll
+  for (int q = 0; q < KT; ++q) {
+    const int j = min(16 * (gbase + q) + i, k - 1);
+    bp[q] = X + (int64_t)j * ldx + VEC * g;
+  }
+  typename V4<TC>::t acc[RT][KT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int q = 0; q < KT; ++q) acc[t][q] = typename V4<TC>::t{0, 0, 0, 0};
+  int c0 = 0;
+  if constexpr (ALN) {
+    for (; c0 + STEP <= cols; c0 += STEP) {
+      TC a[RT][VEC], b[KT][VEC];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) L::vec(ap[t] + c0, a[t]);
+#pragma unroll
+      for (int q = 0; q < KT; ++q) ld_x<TC, VEC, true>(bp[q] + c0, b[q]);
+#pragma unroll
+      for (int m = 0; m < VEC; ++m)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int q = 0; q < KT; ++q) acc[t][q] = mfma(a[t][m], b[q][m], acc[t][q]);
+    }
+  }
+  for (; c0 < cols; c0 += STEP) {
+    TC a[RT][VEC], b[KT][VEC];
+#pragma unroll
+    for (int m = 0; m < VEC; ++m) {
+      const bool ok = c0 + VEC * g + m < cols;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) a[t][m] = ok ? L::one(ap[t] + c0 + m) : (TC)0;
+#pragma unroll
+      for (int q = 0; q < KT; ++q) b[q][m] = ok ? (TC)bp[q][c0 + m] : (TC)0;
+    }
+#pragma unroll
+    for (int m = 0; m < VEC; ++m)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int q = 0; q < KT; ++q) acc[t][q] = mfma(a[t][m], b[q][m], acc[t][q]);
+  }
+  // epilogue: Y = acc (+ lam X), per-column dot partials over this row set
+#pragma unroll
+  for (int q = 0; q < KT; ++q) {
+    const int j = 16 * (gbase + q) + i;
+    const bool live = j < k && !(skip && skip[j]);
+    double dp = 0.0;
+    if (live) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = r0 + 16 * t + out_row<TC>(g, e);
+          if (row < rows) {
+            const double xr = (diag || dot_part) ? X[(int64_t)j * ldx + row] : 0.0;
+            const double y = (double)acc[t][q][e] + (diag ? lam * xr : 0.0);
+            Y[(int64_t)j * ldy + row] = y;
+            dp = fma(xr, y, dp);
+          }
+        }
+    }
+    if (dot_part) {
+      // the four lanes of column j (l / 16 = 0..3) hold disjoint rows
+      dp += __shfl_xor(dp, 16, WAVE);
+      dp += __shfl_xor(dp, 32, WAVE);
+      if (g == 0 && j < k) dot_part[(int64_t)rs * k + j] = dp;
+    }
+  }
+}
+
+template <class TA, class TC, int RT, int KT>
+hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X,
+                  int64_t ldx, double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip,
+                  double* dot_part, int* nblocks) {
+  const int nrs = (int)((rows + 16 * RT - 1) / (16 * RT));
+  const int ngroups = (k + 15) / 16;
+  const int ncs = (ngroups + KT - 1) / KT;
+  const int64_t waves = (int64_t)nrs * ncs;
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  const bool aln = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(TA)) % 16 == 0) && ((uintptr_t)X % 16 == 0) &&
+                   (ldx % 2 == 0);
+  if (aln)
+    hipLaunchKernelGGL((k_gemm<TA, TC, RT, KT, true>), dim3(blocks), dim3(256), 0, st, A, lda, (int)rows, (int)cols,
+                       X, ldx, Y, ldy, k, lam, diag ? 1 : 0, skip, dot_part, nrs, ncs);
+  else
+    hipLaunchKernelGGL((k_gemm<TA, TC, RT, KT, false>), dim3(blocks), dim3(256), 0, st, A, lda, (int)rows, (int)cols,
+                       X, ldx, Y, ldy, k, lam, diag ? 1 : 0, skip, dot_part, nrs, ncs);
+  if (nblocks) *nblocks = nrs;
+  return hipGetLastError();
+}
+
+// column groups per wavefront: enough to cover k in one or two passes over A while
+// keeping the accumulators in registers
+template <class TA, class TC>
+hipError_t gemm_k(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X, int64_t ldx,
+                  double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip, double* dot_part,
+                  int* nblocks) {
+  if (k <= 16) return gemm_t<TA, TC, 4, 1>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
+  if (sizeof(TC) == 8 || k <= 32)
+    return gemm_t<TA, TC, 4, 2>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
+  return gemm_t<TA, TC, 4, 4>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
+}
+
+}  // namespace
+
+int gemm_row_sets(int64_t rows) { return (int)((rows + 63) / 64); }
+
+hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows, int64_t cols,
+                       int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
+                       bool diag, const int32_t* skip, double* dot_part, int* nblocks) {
+  const int kk = (int)k;
+  switch (a_t) {
+    case MSP_F64:
+      return gemm_k<double, double>(st, (const double*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam, diag, skip,
+                                    dot_part, nblocks);
+    case MSP_F32:
+      if (fp64_arith)
+        return gemm_k<float, double>(st, (const float*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam, diag, skip,
+                                     dot_part, nblocks);
+      return gemm_k<float, float>(st, (const float*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam, diag, skip, dot_part,
+                                  nblocks);
+    case MSP_BF16:
+      return gemm_k<__hip_bfloat16, float>(st, (const __hip_bfloat16*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam,
+                                           diag, skip, dot_part, nblocks);
+  }
+  return hipErrorInvalidValue;
+}

@@ -390,6 +390,7 @@ struct SolveCtx {
   msp_dtype cf_t;
   int64_t lda;
   double lam;
+  double lam_sw;  // shift of the sweeps of A_sw (lam, plus delta under PSD refinement)
   Level L0, L1, L2, L3;
   double *rhs2, *wp, *pqw, *tmp_s, *relres, *dots, *gpart, *l2part, *l2pq, *l2b;
   double *rho, *tvec, *mvec, *mvec2, *nvec;  // general path: m x k (4) and n x k
@@ -505,11 +506,15 @@ msp_status sweep(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t 
   hipEvent_t stop = nullptr;
   if (timed) TRY(ev_begin(c, &stop));
   hipError_t e;
-  if (fp64 && t == MSP_F32)
-    e = launch_gemv_f32_as_f64(c.st, (const float*)A, rows, cols, c.lda, X, ldx, Y, ldy, c.k, c.lam, diag, skip,
+  const double lam = (A == c.A_sw) ? c.lam_sw : c.lam;
+  if (c.k >= kGemmMinK)
+    e = launch_gemm(c.st, A, t, fp64 && t == MSP_F32, rows, cols, c.lda, X, ldx, Y, ldy, c.k, lam, diag, skip,
+                    parts ? c.gpart : nullptr, &nb);
+  else if (fp64 && t == MSP_F32)
+    e = launch_gemv_f32_as_f64(c.st, (const float*)A, rows, cols, c.lda, X, ldx, Y, ldy, c.k, lam, diag, skip,
                                parts ? c.gpart : nullptr, &nb);
   else
-    e = launch_gemv(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k, c.lam, diag, skip, parts ? c.gpart : nullptr,
+    e = launch_gemv(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k, lam, diag, skip, parts ? c.gpart : nullptr,
                     &nb);
   MSP_CHECK_HIP(e);
   if (stop) MSP_CHECK_HIP(hipEventRecord(stop, c.st));
@@ -899,6 +904,17 @@ msp_status solve_into(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const doubl
   if (do_refine) {
     c.A_cf = c.A_sw;  // the inner solves confirm on the matrix they sweep
     c.cf_t = c.sw_t;
+    if (c.P->structure == MSP_SYM_PSD && c.A_sw != A_hi) {
+      // inner operator A_lo + (lam + delta) I with delta = u_lo ||A_hi||_inf >= ||A_lo - A_hi||_2
+      // (elementwise rounding of a symmetric matrix): it dominates A_hi + lam I, so the
+      // low-precision MSP stays a positive definite preconditioner of the FP64 refinement
+      MSP_CHECK_HIP(launch_row_abs_max(c.st, A_hi, hi_t, c.n, c.n, c.lda, c.relres));
+      double ninf = 0.0;
+      MSP_CHECK_HIP(hipMemcpyAsync(&ninf, c.relres, sizeof(double), hipMemcpyDeviceToHost, c.st));
+      MSP_CHECK_HIP(hipStreamSynchronize(c.st));
+      const double u_lo = c.sw_t == MSP_BF16 ? 0x1p-8 : 0x1p-24;
+      c.lam_sw = c.lam + u_lo * ninf;
+    }
     TRY(refine(c, A_hi, hi_t, B, ldb, o->tol, rel));
     MSP_CHECK_HIP(launch_copy_block(c.st, c.n, c.k, c.xh, c.n, X, ldx));
   } else {
@@ -952,6 +968,7 @@ msp_status make_ctx(SolveCtx& c, void* stream, const msp_precond* P, const void*
   c.cf_t = hi_t;
   c.lda = lda;
   c.lam = P->lam;
+  c.lam_sw = P->lam;
   c.hf = P->host_flags;
   c.df = P->dev_view_flags;
   c.evpool = (std::vector<hipEvent_t>*)P->events;
@@ -1142,7 +1159,9 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
     REQUIRE(u_hi >= u_lo, "u_hi < u_lo");
     // A g for every probe, once
     int nb = 0;
-    MSP_CHECK_HIP(launch_gemv(st, A_hi, hi_t, n, n, lda, G, ldg, AG, n, N, 0.0, false, nullptr, nullptr, &nb));
+    MSP_CHECK_HIP(N >= kGemmMinK
+                      ? launch_gemm(st, A_hi, hi_t, false, n, n, lda, G, ldg, AG, n, N, 0.0, false, nullptr, nullptr, &nb)
+                      : launch_gemv(st, A_hi, hi_t, n, n, lda, G, ldg, AG, n, N, 0.0, false, nullptr, nullptr, &nb));
     const int count = (int)std::floor((u_hi - u_lo) / h + 1e-9) + 1;
     const double lam_save = P->lam;
     for (int jn = 0; jn < count; ++jn) {
@@ -1157,7 +1176,9 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
       if (log_on())
         fprintf(stderr, "[msp] schatten node %d/%d t=%.3e outer=%d inner=%lld level3=%lld relres=%.2e\n", jn + 1,
                 count, t, i.outer_iters, (long long)i.inner_iters, (long long)i.level3_iters, i.rel_residual_max);
-      MSP_CHECK_HIP(launch_gemv(st, A_hi, hi_t, n, n, lda, X, n, AX, n, N, 0.0, false, nullptr, nullptr, &nb));
+      MSP_CHECK_HIP(N >= kGemmMinK
+                        ? launch_gemm(st, A_hi, hi_t, false, n, n, lda, X, n, AX, n, N, 0.0, false, nullptr, nullptr, &nb)
+                        : launch_gemv(st, A_hi, hi_t, n, n, lda, X, n, AX, n, N, 0.0, false, nullptr, nullptr, &nb));
       MSP_CHECK_HIP(launch_coldots(st, n, N, AG, n, AX, n, dv));
       MSP_CHECK_HIP(hipMemcpyAsync(d.data(), dv, sizeof(double) * N, hipMemcpyDeviceToHost, st));
       MSP_CHECK_HIP(hipStreamSynchronize(st));

@@ -88,6 +88,13 @@ hipError_t spd_inverse(hipStream_t st, int64_t s, double* M, double* tmp, double
 hipError_t launch_gemv(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,
                        const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
                        bool diag_shift, const int32_t* skip, double* dot_part, int* nblocks);
+// Blocks of k >= kGemmMinK vectors take the matrix-core block sweep (k_gemm.hip) with the
+// same contract; its dot partials come per 64-row set (gemm_row_sets(rows) of them).
+constexpr int64_t kGemmMinK = 8;
+int gemm_row_sets(int64_t rows);
+hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows, int64_t cols,
+                       int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
+                       bool diag, const int32_t* skip, double* dot_part, int* nblocks);
 // Y[:, j] = A^T X[:, j]  (A rows x cols row-major; X length rows; Y length cols)
 // part: scratch of gemv_t_part_doubles(rows, cols, k) doubles
 size_t gemv_t_part_doubles(int64_t rows, int64_t cols, int64_t k);
@@ -179,6 +186,9 @@ hipError_t launch_coldots(hipStream_t st, int64_t len, int64_t k, const double* 
 // dA = -dB X^T (n x n dense, ld ldda)
 hipError_t launch_outer_neg(hipStream_t st, int64_t n, int64_t k, const double* dB, int64_t lddb, const double* X,
                             int64_t ldx, double* dA, int64_t ldda);
+// out[0] = max_i sum_j |A[i, j]| for an F64 or F32 matrix (one block; device scalar)
+hipError_t launch_row_abs_max(hipStream_t st, const void* A, msp_dtype t, int64_t rows, int64_t cols, int64_t lda,
+                              double* out);
 // copy len x k block between leading dimensions
 hipError_t launch_copy_block(hipStream_t st, int64_t len, int64_t k, const double* x, int64_t ldx, double* y,
                              int64_t ldy);

@@ -141,3 +141,19 @@ def test_unsupported_adjoint_for_general():
     with pytest.raises(msp.MspError) as e:
         msp.solve_backward(P, A, X, X.clone())
     assert e.value.status == "MSP_ERR_UNSUPPORTED"
+
+
+def test_general_block_rhs_matrix_core_sweeps():
+    # k >= 8: both A and A^T products of the three-level path on blocks
+    say("case general block rhs n=300 k=9")
+    n, s, k = 300, 32, 9
+    a, sv, _, _ = W.general_outlier(n, 6, config_id=107, big=(1e1, 1e3))
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    bm = W.gaussian((k, n), 107)
+    A, P = _gen(a, 0.0, lam0, s)
+    X, info = msp.solve(P, A, torch.from_numpy(bm).to(DEV), tol=1e-10, inner_tol=1e-12, level3_tol=1e-12)
+    say(info)
+    assert info["status"] == "MSP_OK", info
+    x = X.cpu().numpy()
+    for j in range(k):
+        assert np.linalg.norm(a @ x[j] - bm[j]) <= 1e-10 * np.linalg.norm(bm[j])

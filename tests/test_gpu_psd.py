@@ -198,3 +198,47 @@ def test_iteration_cap_reports_no_convergence():
     X, info = msp.solve(P, A, torch.from_numpy(W.gaussian(n, 302)).to(DEV), tol=1e-12, max_outer=3)
     assert info["code"] == "MSP_ERR_NO_CONVERGENCE"
     assert info["outer_iters"] == 3
+
+
+@pytest.mark.parametrize("k", [20, 40])
+def test_block_rhs_matrix_core_sweep_f64(k):
+    # k >= 8 right-hand sides take the matrix-core block sweep; ragged n, a zero column
+    say(f"case block rhs f64 n=777 k={k}")
+    n, s, lam = 777, 48, 1e-2
+    a, eigs, lam0 = _psd_case(n, 10, s, 310, lam)
+    bm = W.gaussian((k, n), 310)
+    bm[3] = 0.0
+    A = torch.from_numpy(a).to(DEV)
+    rows, signs, Y = msp.sketch(A, s, 8, 33)
+    P = msp.Precond("psd", rows, signs, Y, lam, lam0, 4 * s, 8, 34)
+    X, info = msp.solve(P, A, torch.from_numpy(bm).to(DEV), tol=1e-10, inner_tol=1e-12)
+    say(info)
+    assert info["status"] == "MSP_OK", info
+    x = X.cpu().numpy()
+    assert np.all(x[3] == 0.0)
+    for j in range(k):
+        if j == 3:
+            continue
+        assert dense.rel_residual_psd(a, x[j], bm[j], lam) <= 1e-10
+        xs = dense.solve_psd(a, bm[j], lam)
+        assert np.linalg.norm(x[j] - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16])
+def test_block_rhs_low_precision_refined(dt):
+    # F32 / BF16 block sweeps inside MSP, FP64 residuals on the FP64 matrix (k >= 8)
+    say(f"case block rhs refine {dt} n=640 k=12")
+    n, s, k = 640, 48, 12
+    lam = 1e-2 if dt == torch.float32 else 0.5
+    a, eigs, lam0 = _psd_case(n, 10, s, 320, lam)
+    bm = W.gaussian((k, n), 320)
+    A = torch.from_numpy(a).to(DEV)
+    A_lo = A.to(dt)
+    rows, signs, Y = msp.sketch(A.float(), s, 8, 35)
+    P = msp.Precond("psd", rows, signs, Y, lam, lam0, 4 * s, 8, 36)
+    X, info = msp.solve(P, A, torch.from_numpy(bm).to(DEV), A_lo=A_lo, refine=1, tol=1e-10)
+    say(info)
+    assert info["status"] == "MSP_OK", info
+    x = X.cpu().numpy()
+    for j in range(k):
+        assert dense.rel_residual_psd(a, x[j], bm[j], lam) <= 1e-10
