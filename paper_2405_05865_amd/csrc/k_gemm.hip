@@ -15,6 +15,8 @@
 
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
 namespace {
 
 constexpr int WAVE = 64;
@@ -247,9 +249,133 @@ hipError_t gemm_k(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64
   return gemm_t<TA, TC, 4, 4>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
 }
 
+// Transposed block product Y[:, j] = A^T X[:, j] (A rows x cols row-major; the
+// normal-equation operator of Algorithm 3). Lane l loads VEC consecutive columns
+// [c0 + VEC (l % 16), +VEC) of row r + l / 16 in one 16-byte access; MFMA m takes
+// element m, so output tile m holds the A-columns c0 + m + VEC * (0..15). A step covers
+// 4 rows x 16 VEC columns. Waves with neighbouring indices share the same A columns and
+// rows and differ in the right-hand-side group, so A is reused from cache. Row ranges
+// are split when there are too few column tiles to fill the chip; the splits are summed
+// in fixed order afterwards.
+template <class TA, class TC, int KT, bool ALN>
+__global__ void __launch_bounds__(256) k_gemm_t(const TA* __restrict__ A, int64_t lda, int rows, int cols,
+                                               const double* __restrict__ X, int64_t ldx, int k, int nct, int ncs,
+                                               int nsplit, int rows_per_split, double* __restrict__ out, int64_t ldo,
+                                               const int32_t* __restrict__ skip, int direct) {
+  using L = Ld<TA, TC>;
+  constexpr int VEC = L::VEC;
+  const int wg = blockIdx.x * 4 + threadIdx.x / WAVE;
+  if (wg >= nct * ncs * nsplit) return;
+  const int cs = wg % ncs, ct = (wg / ncs) % nct, sp = wg / (ncs * nct);
+  const int lane = threadIdx.x & (WAVE - 1), i = lane & 15, g = lane >> 4;
+  const int c0 = ct * 16 * VEC;
+  const int cl = c0 + VEC * i;  // this lane's first A-column
+  const int rb = sp * rows_per_split, re = min(rows, rb + rows_per_split);
+  const bool full = ALN && (cl + VEC <= cols);
+  const double* xp[KT];
+#pragma unroll
+  for (int q = 0; q < KT; ++q) xp[q] = X + (int64_t)min(16 * (cs * KT + q) + i, k - 1) * ldx;
+  typename V4<TC>::t acc[VEC][KT];
+#pragma unroll
+  for (int m = 0; m < VEC; ++m)
+#pragma unroll
+    for (int q = 0; q < KT; ++q) acc[m][q] = typename V4<TC>::t{0, 0, 0, 0};
+  for (int r = rb; r < re; r += 4) {
+    const int row = r + g;
+    const bool ok = row < re;
+    TC a[VEC], b[KT];
+    if (ok && full) {
+      L::vec(A + (int64_t)row * lda + cl, a);
+    } else {
+#pragma unroll
+      for (int m = 0; m < VEC; ++m) a[m] = (ok && cl + m < cols) ? L::one(A + (int64_t)row * lda + cl + m) : (TC)0;
+    }
+#pragma unroll
+    for (int q = 0; q < KT; ++q) b[q] = ok ? (TC)xp[q][row] : (TC)0;
+#pragma unroll
+    for (int m = 0; m < VEC; ++m)
+#pragma unroll
+      for (int q = 0; q < KT; ++q) acc[m][q] = mfma(a[m], b[q], acc[m][q]);
+  }
+#pragma unroll
+  for (int q = 0; q < KT; ++q) {
+    const int j = 16 * (cs * KT + q) + i;
+    if (j >= k) continue;
+    if (direct && skip && skip[j]) continue;
+#pragma unroll
+    for (int m = 0; m < VEC; ++m)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int col = c0 + m + VEC * out_row<TC>(g, e);
+        if (col >= cols) continue;
+        if (direct) out[(int64_t)j * ldo + col] = (double)acc[m][q][e];
+        else out[((int64_t)sp * k + j) * cols + col] = (double)acc[m][q][e];
+      }
+  }
+}
+
+__global__ void k_sum_splits_t(const double* __restrict__ part, int nsplit, int64_t cols, int k,
+                               const int32_t* __restrict__ skip, double* __restrict__ Y, int64_t ldy) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t len = cols * k;
+  if (idx >= len) return;
+  const int j = (int)(idx / cols);
+  const int64_t c = idx % cols;
+  if (skip && skip[j]) return;
+  double acc = 0.0;
+  for (int t = 0; t < nsplit; ++t) acc += part[(int64_t)t * len + idx];
+  Y[(int64_t)j * ldy + c] = acc;
+}
+
+template <class TA, class TC, int KT>
+hipError_t gemmT_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X,
+                   int64_t ldx, double* Y, int64_t ldy, int k, const int32_t* skip, double* part) {
+  constexpr int VEC = Ld<TA, TC>::VEC;
+  const int nct = (int)((cols + 16 * VEC - 1) / (16 * VEC));
+  const int ncs = ((k + 15) / 16 + KT - 1) / KT;
+  int nsplit = (int)((2048 + (int64_t)nct * ncs - 1) / ((int64_t)nct * ncs));
+  nsplit = std::max(1, std::min<int>(nsplit, std::min<int64_t>(64, (rows + 255) / 256)));
+  const int rps = (int)(((rows + nsplit - 1) / nsplit + 3) / 4 * 4);
+  nsplit = (int)((rows + rps - 1) / rps);
+  const int64_t waves = (int64_t)nct * ncs * nsplit;
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  const bool aln = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(TA)) % 16 == 0);
+  const int direct = nsplit == 1;
+  double* out = direct ? Y : part;
+  const int64_t ldo = direct ? ldy : 0;
+  if (aln)
+    hipLaunchKernelGGL((k_gemm_t<TA, TC, KT, true>), dim3(blocks), dim3(256), 0, st, A, lda, (int)rows, (int)cols, X,
+                       ldx, k, nct, ncs, nsplit, rps, out, ldo, skip, direct);
+  else
+    hipLaunchKernelGGL((k_gemm_t<TA, TC, KT, false>), dim3(blocks), dim3(256), 0, st, A, lda, (int)rows, (int)cols, X,
+                       ldx, k, nct, ncs, nsplit, rps, out, ldo, skip, direct);
+  if (!direct) {
+    const int64_t len = cols * k;
+    hipLaunchKernelGGL(k_sum_splits_t, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, part, nsplit, cols, k,
+                       skip, Y, ldy);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int gemm_row_sets(int64_t rows) { return (int)((rows + 63) / 64); }
+
+hipError_t launch_gemm_t(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,
+                         const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip,
+                         double* part) {
+  const int kk = (int)k;
+  switch (a_t) {
+    case MSP_F64:
+      return gemmT_t<double, double, 2>(st, (const double*)A, rows, cols, lda, X, ldx, Y, ldy, kk, skip, part);
+    case MSP_F32:
+      return gemmT_t<float, float, 2>(st, (const float*)A, rows, cols, lda, X, ldx, Y, ldy, kk, skip, part);
+    case MSP_BF16:
+      return gemmT_t<__hip_bfloat16, float, 2>(st, (const __hip_bfloat16*)A, rows, cols, lda, X, ldx, Y, ldy, kk,
+                                                skip, part);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows, int64_t cols,
                        int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,

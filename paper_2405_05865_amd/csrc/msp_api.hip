@@ -527,7 +527,10 @@ msp_status sweep(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t 
 // Y = A^T X for A rows x cols (X length rows, Y length cols)
 msp_status sweep_t(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t cols, const double* X, int64_t ldx,
                    double* Y, int64_t ldy, const int32_t* skip) {
-  MSP_CHECK_HIP(launch_gemv_t(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k, skip, c.gpart));
+  if (c.k >= kGemmMinK)
+    MSP_CHECK_HIP(launch_gemm_t(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k, skip, c.gpart));
+  else
+    MSP_CHECK_HIP(launch_gemv_t(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k, skip, c.gpart));
   c.acc.sweeps += 1;
   c.acc.sweep_bytes += (double)rows * (double)cols * (double)dsize(t);
   return MSP_OK;
@@ -730,7 +733,8 @@ msp_status gen_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int m
       if (normal) {
         // rtrue = B - (A^T A + lam I) x
         TRY(sweep(c, c.A_cf, c.cf_t, m, n, L.x, n, c.tvec, m, false, nullptr, false, true, false));
-        MSP_CHECK_HIP(launch_gemv_t(c.st, c.A_cf, c.cf_t, m, n, c.lda, c.tvec, m, L.q, n, k, nullptr, c.gpart));
+        MSP_CHECK_HIP((k >= kGemmMinK ? launch_gemm_t : launch_gemv_t)(c.st, c.A_cf, c.cf_t, m, n, c.lda, c.tvec, m,
+                                                                        L.q, n, k, nullptr, c.gpart));
         if (c.lam != 0.0) MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, L.q, n, c.lam, L.x, n, L.q, n, nullptr));
         MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, B, ldb, -1.0, L.q, n, L.q, n, nullptr));
         MSP_CHECK_HIP(fcg_confirm(c.st, L.S, n, L.q, L.r, tol, c.relres, c.df + SLOT_L1));
@@ -782,7 +786,8 @@ msp_status hi_residual(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const doub
     MSP_CHECK_HIP(launch_axpby(c.st, m, k, 1.0, B, ldb, -1.0, out, m, out, m, nullptr));
   } else {
     TRY(sweep(c, A_hi, hi_t, m, n, c.xh, n, c.tvec, m, false, nullptr, false, true, false));
-    MSP_CHECK_HIP(launch_gemv_t(c.st, A_hi, hi_t, m, n, c.lda, c.tvec, m, out, n, k, nullptr, c.gpart));
+    MSP_CHECK_HIP((k >= kGemmMinK ? launch_gemm_t : launch_gemv_t)(c.st, A_hi, hi_t, m, n, c.lda, c.tvec, m, out, n,
+                                                                    k, nullptr, c.gpart));
     if (c.lam != 0.0) MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, out, n, c.lam, c.xh, n, out, n, nullptr));
     MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, B, ldb, -1.0, out, n, out, n, nullptr));
   }

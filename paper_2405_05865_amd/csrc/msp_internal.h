@@ -95,6 +95,11 @@ int gemm_row_sets(int64_t rows);
 hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows, int64_t cols,
                        int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
                        bool diag, const int32_t* skip, double* dot_part, int* nblocks);
+// Y[:, j] = A^T X[:, j] on the matrix cores for k >= kGemmMinK (same contract as
+// launch_gemv_t; part: gemv_t_part_doubles(rows, cols, k) doubles)
+hipError_t launch_gemm_t(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,
+                         const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip,
+                         double* part);
 // Y[:, j] = A^T X[:, j]  (A rows x cols row-major; X length rows; Y length cols)
 // part: scratch of gemv_t_part_doubles(rows, cols, k) doubles
 size_t gemv_t_part_doubles(int64_t rows, int64_t cols, int64_t k);
