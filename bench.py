@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--inner-tol", type=float, default=1e-10)
+    ap.add_argument("--level2-form", type=int, default=1, choices=[0, 1],
+                    help="inner operator through the sketch each step (0) or through C^T C + lam~ W formed "
+                         "once (1, default); the same iteration")
     ap.add_argument("--max-outer", type=int, default=None,
                     help="cap the level-1 iterations (counter runs over a few sweeps only)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -151,7 +154,7 @@ def main():
         rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
         P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi)
         X, info = msp.solve(P, A, bt, tol=w.tol, inner_tol=args.inner_tol, profile=profile,
-                            max_outer=args.max_outer)
+                            max_outer=args.max_outer, level2_form=args.level2_form)
         P.close()
         return X, info
 
@@ -192,7 +195,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"rbf_gp_n{w.n}_fp64_1rhs", "n": w.n, "s": w.s, "gamma": w.gamma, "phi": w.phi,
                    "lambda": w.lam, "lambda0": lam0, "tol": w.tol, "inner_tol": args.inner_tol, "nrhs": 1,
-                   "levels": 2},
+                   "levels": 2, "level2_form": args.level2_form},
         "hbm_gbs_per_sweep": round(achieved, 1),
         "outer_iters": infos[-1]["outer_iters"],
         "inner_iters": infos[-1]["inner_iters"],

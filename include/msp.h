@@ -156,6 +156,13 @@ typedef struct {
   double refine_inner_tol; /* inner MSP target per refinement step (default 1e-4) */
   int32_t max_refine;      /* refinement step cap (default 30) */
   int32_t profile;         /* record HIP events around every level-1 sweep (sweep_ms in info) */
+  int32_t level2_form;     /* how the inner operators are applied (default 1):
+                              0: through the sketch each inner step (PSD: C^T (C y) + lam~ W y;
+                                 general: passes over A~ and two A-sweeps), the paper's cost model;
+                              1: through s x s matrices formed once per solve (PSD:
+                                 C^T C + lam~ W; general: B^T B + lam~ A~^T A~ with B = A^T A~,
+                                 and A~^T A~ for level 3). The same operators and iterations;
+                                 s^2 instead of n s (or n^2) work per inner step. */
 } msp_solve_opts;
 
 typedef struct {

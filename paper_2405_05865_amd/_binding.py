@@ -55,6 +55,7 @@ class SolveOpts(ctypes.Structure):
         ("refine_inner_tol", ctypes.c_double),
         ("max_refine", ctypes.c_int32),
         ("profile", ctypes.c_int32),
+        ("level2_form", ctypes.c_int32),
     ]
 
 

@@ -327,16 +327,25 @@ __global__ void k_sum_splits_t(const double* __restrict__ part, int nsplit, int6
   Y[(int64_t)j * ldy + c] = acc;
 }
 
+// row splits of the transposed product: enough wavefronts to fill the chip
+void gemmT_split(int64_t rows, int64_t cols, int k, int vec, int kt, int* nsplit_out, int* rps_out) {
+  const int64_t nct = (cols + 16 * vec - 1) / (16 * vec);
+  const int64_t ncs = ((k + 15) / 16 + kt - 1) / kt;
+  int64_t nsplit = (2048 + nct * ncs - 1) / (nct * ncs);
+  nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(64, (rows + 255) / 256)));
+  const int64_t rps = ((rows + nsplit - 1) / nsplit + 3) / 4 * 4;
+  *nsplit_out = (int)((rows + rps - 1) / rps);
+  *rps_out = (int)rps;
+}
+
 template <class TA, class TC, int KT>
 hipError_t gemmT_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X,
                    int64_t ldx, double* Y, int64_t ldy, int k, const int32_t* skip, double* part) {
   constexpr int VEC = Ld<TA, TC>::VEC;
   const int nct = (int)((cols + 16 * VEC - 1) / (16 * VEC));
   const int ncs = ((k + 15) / 16 + KT - 1) / KT;
-  int nsplit = (int)((2048 + (int64_t)nct * ncs - 1) / ((int64_t)nct * ncs));
-  nsplit = std::max(1, std::min<int>(nsplit, std::min<int64_t>(64, (rows + 255) / 256)));
-  const int rps = (int)(((rows + nsplit - 1) / nsplit + 3) / 4 * 4);
-  nsplit = (int)((rows + rps - 1) / rps);
+  int nsplit = 1, rps = 4;
+  gemmT_split(rows, cols, k, VEC, KT, &nsplit, &rps);
   const int64_t waves = (int64_t)nct * ncs * nsplit;
   const unsigned blocks = (unsigned)((waves + 3) / 4);
   const bool aln = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(TA)) % 16 == 0);
@@ -360,6 +369,16 @@ hipError_t gemmT_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int6
 }  // namespace
 
 int gemm_row_sets(int64_t rows) { return (int)((rows + 63) / 64); }
+
+size_t gemm_t_part_doubles(int64_t rows, int64_t cols, int64_t k) {
+  size_t worst = 0;
+  for (int vec : {2, 4, 8}) {
+    int ns = 1, rps = 4;
+    gemmT_split(rows, cols, (int)k, vec, 2, &ns, &rps);
+    if (ns > 1) worst = std::max(worst, (size_t)ns * k * cols);
+  }
+  return worst + 64;
+}
 
 hipError_t launch_gemm_t(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,
                          const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip,

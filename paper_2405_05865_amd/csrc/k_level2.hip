@@ -479,8 +479,9 @@ hipError_t op_tk(hipStream_t st, const TY* Y, int64_t n, int s, int64_t ldy, con
   // buffer layout (see l2_op_part_doubles): block partials, then group sums
   double* gpart = part + (size_t)nbC * k * s;
   double* gpq = pqpart ? pqpart + (size_t)nbC * k : nullptr;
-  hipLaunchKernelGGL(k_l2_gsum, dim3(ngroups(nbC), k), dim3(256), 0, st, part, MODE == 0 ? pqpart : nullptr, nbC,
-                     k, s, gpart, gpq);
+  if (nbC > 0)
+    hipLaunchKernelGGL(k_l2_gsum, dim3(ngroups(nbC), k), dim3(256), 0, st, part, MODE == 0 ? pqpart : nullptr, nbC,
+                       k, s, gpart, gpq);
   return hipGetLastError();
 }
 
@@ -598,6 +599,13 @@ hipError_t l2_op(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_
   }
   if (rhs_mode) return op_dispatch<float, 1>(st, (const float*)Y, n, si, ldy, v, ldv, ki, done, part, pqpart, W, wp, pqw, nbC);
   return op_dispatch<float, 0>(st, (const float*)Y, n, si, ldy, v, ldv, ki, done, part, pqpart, W, wp, pqw, nbC);
+}
+
+// the inner operator through an explicit s x s matrix M: wp = M v and pqw = v .* (M v)
+// (the W-row part of the Y pass alone; steps built on it use nbC = 0)
+hipError_t l2_op_matrix(hipStream_t st, const double* M, int64_t s, const double* v, int64_t k, const int32_t* done,
+                        double* wp, double* pqw) {
+  return op_dispatch<double, 0>(st, nullptr, 0, (int)s, 0, v, s, (int)k, done, nullptr, nullptr, M, wp, pqw, 0);
 }
 
 // rhs reduction, then the first preconditioner application (p = z = Minv r)

@@ -283,3 +283,37 @@ hipError_t launch_small_mv(hipStream_t st, int64_t s64, const double* M, const d
 #undef MV
   return hipGetLastError();
 }
+
+namespace {
+
+// 32 x 32 tiles through shared memory (padded against bank conflicts)
+template <class TX>
+__global__ void __launch_bounds__(256) k_transpose_f64(const TX* __restrict__ X, int64_t rows, int64_t cols,
+                                                      int64_t ldx, double* __restrict__ out, int64_t ldo) {
+  __shared__ double t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t r = r0 + q, c = c0 + tx;
+    t[q][tx] = (r < rows && c < cols) ? (double)X[r * ldx + c] : 0.0;
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t c = c0 + q, r = r0 + tx;
+    if (c < cols && r < rows) out[c * ldo + r] = t[tx][q];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_transpose_f64(hipStream_t st, const void* X, msp_dtype x_t, int64_t rows, int64_t cols,
+                                int64_t ldx, double* out, int64_t ldo) {
+  dim3 grd((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  if (x_t == MSP_F64)
+    hipLaunchKernelGGL(k_transpose_f64<double>, grd, dim3(256), 0, st, (const double*)X, rows, cols, ldx, out, ldo);
+  else if (x_t == MSP_F32)
+    hipLaunchKernelGGL(k_transpose_f64<float>, grd, dim3(256), 0, st, (const float*)X, rows, cols, ldx, out, ldo);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}

@@ -354,6 +354,7 @@ extern "C" void msp_solve_opts_default(msp_solve_opts* o) {
   o->refine_inner_tol = 1e-4;
   o->max_refine = 30;
   o->profile = 0;
+  o->level2_form = 1;
 }
 
 
@@ -395,6 +396,10 @@ struct SolveCtx {
   double *rhs2, *wp, *pqw, *tmp_s, *relres, *dots, *gpart, *l2part, *l2pq, *l2b;
   double *rho, *tvec, *mvec, *mvec2, *nvec;  // general path: m x k (4) and n x k
   double *xh, *rh, *bn;                      // refinement
+  int form = 0;                              // level2_form
+  double *H2 = nullptr, *H3 = nullptr;       // explicit inner operators (s x s)
+  double *B2t = nullptr, *Act = nullptr;     // general: (A^T A~)^T (s x n), A~^T (s x m)
+  double* gtmp = nullptr;                    // Gram split partials
   int32_t* hf;
   int32_t* df;
   int last_inner = 4, last_l3a = 4, last_l3b = 4;
@@ -404,7 +409,7 @@ struct SolveCtx {
   size_t evused = 0;
 };
 
-size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c) {
+size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, int form) {
   const int64_t n = P->n, m = P->m, s = P->s;
   const int64_t mx = std::max(n, m);
   const int64_t nb_gemv = (mx + 3) / 4;  // upper bound of gemv blocks (R >= 4)
@@ -433,7 +438,25 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c) {
   double* xh = w.take<double>(n * k);
   double* rh = w.take<double>(mx * k);
   double* bn = w.take<double>(k);
+  double *H2 = nullptr, *H3 = nullptr, *B2t = nullptr, *Act = nullptr, *gtmp = nullptr;
+  if (form == 1) {
+    H2 = w.take<double>(s * s);
+    if (P->structure == MSP_SYM_PSD) {
+      gtmp = w.take<double>((size_t)gram_splits(n, s) * s * s + 1);
+    } else {
+      H3 = w.take<double>(s * s);
+      B2t = w.take<double>(s * n);
+      Act = w.take<double>(s * m);
+      gtmp = w.take<double>(gemm_t_part_doubles(m, n, s));
+    }
+  }
   if (c) {
+    c->form = form;
+    c->H2 = H2;
+    c->H3 = H3;
+    c->B2t = B2t;
+    c->Act = Act;
+    c->gtmp = gtmp;
     c->L0 = L0;
     c->L1 = L1;
     c->L2 = L2;
@@ -565,7 +588,9 @@ L2Step l2step_for(SolveCtx& c, Level& L, const double* Minv, const double* W, do
 }
 
 // iterations of an inner FCG on the sketch: chunk = predicted count, then pairs
-msp_status run_l2(SolveCtx& c, const L2Step& a, const double* W, int slotid, int* last, int64_t* counter) {
+// M != null: the operator is the explicit s x s matrix M (a.nbC = 0, wscale = 1)
+msp_status run_l2(SolveCtx& c, const L2Step& a, const double* W, int slotid, int* last, int64_t* counter,
+                  const double* M = nullptr) {
   const msp_precond* P = c.P;
   const int64_t rows = P->structure == MSP_SYM_PSD ? c.n : c.m;
   int issued = 0;
@@ -573,8 +598,11 @@ msp_status run_l2(SolveCtx& c, const L2Step& a, const double* W, int slotid, int
   const int cap = a.max_iter;
   while (true) {
     for (int i = 0; i < chunk && issued < cap; ++i, ++issued) {
-      MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, rows, c.s, P->ldy, a.p, c.s, c.k, a.S.done, a.part, a.pqpart, W, a.wp,
-                          a.pqw, false));
+      if (M)
+        MSP_CHECK_HIP(l2_op_matrix(c.st, M, c.s, a.p, c.k, a.S.done, a.wp, a.pqw));
+      else
+        MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, rows, c.s, P->ldy, a.p, c.s, c.k, a.S.done, a.part, a.pqpart, W,
+                            a.wp, a.pqw, false));
       MSP_CHECK_HIP(l2_step(c.st, a));
     }
     TRY(sync(c));
@@ -584,6 +612,59 @@ msp_status run_l2(SolveCtx& c, const L2Step& a, const double* W, int slotid, int
   const int taken = *slot(c, slotid + 1);
   *counter += taken;
   if (taken > 0) *last = taken;
+  return MSP_OK;
+}
+
+// out[:, j] = M v_j for an FP64 rows x cols row-major M (block product for k >= 8)
+msp_status dense_mv(SolveCtx& c, const double* M, int64_t rows, int64_t cols, const double* v, int64_t ldv,
+                    double* out, int64_t ldo, const int32_t* skip) {
+  int nb = 0;
+  if (c.k >= kGemmMinK)
+    MSP_CHECK_HIP(launch_gemm(c.st, M, MSP_F64, false, rows, cols, cols, v, ldv, out, ldo, c.k, 0.0, false, skip,
+                              nullptr, &nb));
+  else
+    MSP_CHECK_HIP(launch_gemv(c.st, M, MSP_F64, rows, cols, cols, v, ldv, out, ldo, c.k, 0.0, false, skip, nullptr,
+                              &nb));
+  return MSP_OK;
+}
+
+// out[:, j] = M^T v_j for an FP64 rows x cols row-major M
+msp_status dense_mv_t(SolveCtx& c, const double* M, int64_t rows, int64_t cols, const double* v, int64_t ldv,
+                      double* out, int64_t ldo, const int32_t* skip) {
+  MSP_CHECK_HIP((c.k >= kGemmMinK ? launch_gemm_t : launch_gemv_t)(c.st, M, MSP_F64, rows, cols, cols, v, ldv, out,
+                                                                    ldo, c.k, skip, c.gpart));
+  return MSP_OK;
+}
+
+// level2_form 1: the explicit inner operators, formed once per solve.
+// PSD: H2 = C^T C + lam~ W. General: A~^T (transposed copy), B^T = (A^T A~)^T by one
+// block product over A with s right-hand sides, H3 = A~^T A~ and H2 = B^T B + lam~ H3.
+msp_status build_explicit(SolveCtx& c) {
+  if (c.form != 1) return MSP_OK;
+  const msp_precond* P = c.P;
+  const int64_t n = c.n, m = c.m, s = c.s;
+  if (P->structure == MSP_SYM_PSD) {
+    const int sp = gram_splits(n, s);
+    if (P->y_t == MSP_F64)
+      MSP_CHECK_HIP(launch_gram(c.st, (const double*)P->Y, n, s, P->ldy, c.H2, c.gtmp, sp));
+    else
+      MSP_CHECK_HIP(launch_gram_f32(c.st, (const float*)P->Y, n, s, P->ldy, c.H2, c.gtmp, sp));
+    MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H2, P->lt, P->Wm, 0.0, c.H2));
+    return MSP_OK;
+  }
+  int nb = 0;
+  MSP_CHECK_HIP(launch_transpose_f64(c.st, P->Y, P->y_t, m, s, P->ldy, c.Act, m));
+  // B^T rows: (A^T A~)[:, j] = A^T (A~ e_j), the block transposed product with s columns
+  if (s >= kGemmMinK)
+    MSP_CHECK_HIP(launch_gemm_t(c.st, c.A_sw, c.sw_t, m, n, c.lda, c.Act, m, c.B2t, n, s, nullptr, c.gtmp));
+  else
+    MSP_CHECK_HIP(launch_gemv_t(c.st, c.A_sw, c.sw_t, m, n, c.lda, c.Act, m, c.B2t, n, s, nullptr, c.gpart));
+  MSP_CHECK_HIP(launch_gemm(c.st, c.Act, MSP_F64, false, s, m, m, c.Act, m, c.H3, s, s, 0.0, false, nullptr, nullptr,
+                            &nb));
+  MSP_CHECK_HIP(launch_gemm(c.st, c.B2t, MSP_F64, false, s, n, n, c.B2t, n, c.H2, s, s, 0.0, false, nullptr, nullptr,
+                            &nb));
+  MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H2, P->lt, c.H3, 0.0, c.H2));
+  MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H3, 0.0, nullptr, 0.0, c.H3));
   return MSP_OK;
 }
 
@@ -597,7 +678,16 @@ msp_status psd_solve_m1(SolveCtx& c, const double* r, double* z) {
   MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, n, s, P->ldy, r, n, k, pdone, a.part, nullptr, nullptr, nullptr, nullptr,
                       true));
   MSP_CHECK_HIP(l2_init(c.st, a));
-  TRY(run_l2(c, a, P->Wm, SLOT_L2, &c.last_inner, &c.acc.inner_iters));
+  if (c.form == 1) {
+    L2Step b = a;  // steps on H = C^T C + lam~ W
+    b.nbC = 0;
+    b.wscale = 1.0;
+    b.wp = c.wp;
+    b.pqw = c.pqw;
+    TRY(run_l2(c, b, nullptr, SLOT_L2, &c.last_inner, &c.acc.inner_iters, c.H2));
+  } else {
+    TRY(run_l2(c, a, P->Wm, SLOT_L2, &c.last_inner, &c.acc.inner_iters));
+  }
   MSP_CHECK_HIP(launch_y_z(c.st, P->Y, P->y_t, n, s, P->ldy, c.L2.x, k, 1.0 / P->lt, r, n, -1.0 / P->lt, pdone, z, n));
   return MSP_OK;
 }
@@ -641,8 +731,14 @@ msp_status gen_level3(SolveCtx& c, const double* rhs, double* out, double sigma,
                       const int32_t* parent_done, int* last) {
   L2Step a = l2step_for(c, c.L3, Minv, nullptr, 0.0, sigma, c.o->level3_tol, c.o->max_level3, SLOT_L3, parent_done);
   a.rhs = rhs;
+  if (c.form == 1) {  // (A~^T A~ + sigma I) through the explicit A~^T A~
+    a.nbC = 0;
+    a.wscale = 1.0;
+    a.wp = c.wp;
+    a.pqw = c.pqw;
+  }
   MSP_CHECK_HIP(l2_init(c.st, a));
-  TRY(run_l2(c, a, nullptr, SLOT_L3, last, &c.acc.level3_iters));
+  TRY(run_l2(c, a, nullptr, SLOT_L3, last, &c.acc.level3_iters, c.form == 1 ? c.H3 : nullptr));
   MSP_CHECK_HIP(launch_copy_block(c.st, c.s, c.k, c.L3.x, c.s, out, c.s));
   return MSP_OK;
 }
@@ -659,6 +755,10 @@ msp_status gen_solve_m2(SolveCtx& c, const double* r, double* z, const int32_t* 
 msp_status gen_op2(SolveCtx& c, const double* p2, double* q2, const int32_t* skip) {
   const msp_precond* P = c.P;
   const int64_t m = c.m, n = c.n, s = c.s, k = c.k;
+  if (c.form == 1) {  // the explicit B^T B + lam~ A~^T A~
+    MSP_CHECK_HIP(launch_small_mv(c.st, s, c.H2, p2, k, skip, q2));
+    return MSP_OK;
+  }
   MSP_CHECK_HIP(launch_y_z(c.st, P->Y, P->y_t, m, s, P->ldy, p2, k, 0.0, nullptr, 0, 1.0, skip, c.mvec, m));
   TRY(sweep_t(c, c.A_sw, c.sw_t, m, n, c.mvec, m, c.nvec, n, skip));
   TRY(sweep(c, c.A_sw, c.sw_t, m, n, c.nvec, n, c.mvec2, m, false, skip, false, false, false));
@@ -677,11 +777,15 @@ msp_status gen_solve_m1(SolveCtx& c, const double* r, double* z) {
   Level& L = c.L2;
   const int64_t m = c.m, n = c.n, s = c.s, k = c.k;
   const int32_t* pdone = c.L1.S.done;
-  TRY(sweep(c, c.A_sw, c.sw_t, m, n, r, n, c.mvec, m, false, pdone, false, false, false));
-  L2Step a = l2step_for(c, L, nullptr, nullptr, 0.0, 0.0, 0.0, 1, SLOT_L2, nullptr);
-  MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, m, s, P->ldy, c.mvec, m, k, pdone, a.part, nullptr, nullptr, nullptr,
-                      nullptr, true));
-  MSP_CHECK_HIP(l2_reduce_to(c.st, a, c.rhs2, pdone));
+  if (c.form == 1) {  // A~^T A r = B^T r with B = A^T A~ (s x n rows of B^T)
+    TRY(dense_mv(c, c.B2t, s, n, r, n, c.rhs2, s, pdone));
+  } else {
+    TRY(sweep(c, c.A_sw, c.sw_t, m, n, r, n, c.mvec, m, false, pdone, false, false, false));
+    L2Step a = l2step_for(c, L, nullptr, nullptr, 0.0, 0.0, 0.0, 1, SLOT_L2, nullptr);
+    MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, m, s, P->ldy, c.mvec, m, k, pdone, a.part, nullptr, nullptr, nullptr,
+                        nullptr, true));
+    MSP_CHECK_HIP(l2_reduce_to(c.st, a, c.rhs2, pdone));
+  }
   MSP_CHECK_HIP(fcg_init(c.st, L.S, s, c.rhs2, s, L.r, L.x, pdone, c.df + SLOT_L2));
   TRY(gen_solve_m2(c, L.r, L.z, L.S.done));
   MSP_CHECK_HIP(fcg_first_dir(c.st, L.S, s, L.r, L.z, L.p));
@@ -697,8 +801,12 @@ msp_status gen_solve_m1(SolveCtx& c, const double* r, double* z) {
   TRY(sync(c));
   c.acc.inner_iters += *slot(c, SLOT_L2 + 1);
   // w^ = (r - A^T (A~ y^)) / lam~
-  MSP_CHECK_HIP(launch_y_z(c.st, P->Y, P->y_t, m, s, P->ldy, L.x, k, 0.0, nullptr, 0, 1.0, pdone, c.mvec, m));
-  TRY(sweep_t(c, c.A_sw, c.sw_t, m, n, c.mvec, m, c.nvec, n, pdone));
+  if (c.form == 1) {  // A^T A~ y = B y
+    TRY(dense_mv_t(c, c.B2t, s, n, L.x, s, c.nvec, n, pdone));
+  } else {
+    MSP_CHECK_HIP(launch_y_z(c.st, P->Y, P->y_t, m, s, P->ldy, L.x, k, 0.0, nullptr, 0, 1.0, pdone, c.mvec, m));
+    TRY(sweep_t(c, c.A_sw, c.sw_t, m, n, c.mvec, m, c.nvec, n, pdone));
+  }
   MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0 / P->lt, r, n, -1.0 / P->lt, c.nvec, n, z, n, pdone));
   return MSP_OK;
 }
@@ -906,6 +1014,7 @@ msp_status solve_into(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const doubl
   msp_status st = MSP_OK;
   std::vector<double> rel;
   const bool do_refine = o->refine && (c.sw_t != MSP_F64);
+  TRY(build_explicit(c));
   if (do_refine) {
     c.A_cf = c.A_sw;  // the inner solves confirm on the matrix they sweep
     c.cf_t = c.sw_t;
@@ -978,8 +1087,10 @@ msp_status make_ctx(SolveCtx& c, void* stream, const msp_precond* P, const void*
   c.df = P->dev_view_flags;
   c.evpool = (std::vector<hipEvent_t>*)P->events;
   WsCarver w(ws, ws_bytes);
-  solve_layout(w, P, k, &c);
+  solve_layout(w, P, k, &c, o->level2_form);
   if (!w.ok()) return msp_fail(MSP_ERR_WORKSPACE, "workspace overflow");
+  // the explicit general operators need the block transposed product (s >= 8)
+  if (P->structure == MSP_GENERAL && P->s < kGemmMinK) c.form = 0;
   for (Level* L : {&c.L0, &c.L1, &c.L2, &c.L3}) MSP_CHECK_HIP(hipMemsetAsync(L->S.counter, 0, sizeof(int32_t), c.st));
   MSP_CHECK_HIP(hipMemsetAsync(c.l2b, 0, sizeof(double) * l2_bpart_doubles(c.s, k), c.st));
   return MSP_OK;
@@ -991,9 +1102,12 @@ extern "C" msp_status msp_solve_workspace(const msp_precond* P, int64_t k, const
                                           size_t* bytes) {
   REQUIRE(P && bytes, "null argument");
   REQUIRE(k >= 1 && k <= kMaxK, "need 1 <= k <= %lld", (long long)kMaxK);
-  (void)opts;
+  msp_solve_opts dflt;
+  msp_solve_opts_default(&dflt);
+  const msp_solve_opts* o = opts ? opts : &dflt;
+  REQUIRE(o->level2_form == 0 || o->level2_form == 1, "level2_form must be 0 or 1");
   WsCarver w(nullptr, 0);
-  solve_layout(w, P, k, nullptr);
+  solve_layout(w, P, k, nullptr, o->level2_form);
   *bytes = w.off;
   return MSP_OK;
 }

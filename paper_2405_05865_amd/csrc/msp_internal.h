@@ -97,6 +97,7 @@ hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_a
                        bool diag, const int32_t* skip, double* dot_part, int* nblocks);
 // Y[:, j] = A^T X[:, j] on the matrix cores for k >= kGemmMinK (same contract as
 // launch_gemv_t; part: gemv_t_part_doubles(rows, cols, k) doubles)
+size_t gemm_t_part_doubles(int64_t rows, int64_t cols, int64_t k);  // its split partials
 hipError_t launch_gemm_t(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,
                          const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip,
                          double* part);
@@ -194,6 +195,9 @@ hipError_t launch_outer_neg(hipStream_t st, int64_t n, int64_t k, const double* 
 // out[0] = max_i sum_j |A[i, j]| for an F64 or F32 matrix (one block; device scalar)
 hipError_t launch_row_abs_max(hipStream_t st, const void* A, msp_dtype t, int64_t rows, int64_t cols, int64_t lda,
                               double* out);
+// out (cols x rows, FP64, ld ldo) = transpose of X (rows x cols, F64 or F32, ld ldx)
+hipError_t launch_transpose_f64(hipStream_t st, const void* X, msp_dtype x_t, int64_t rows, int64_t cols,
+                                int64_t ldx, double* out, int64_t ldo);
 // copy len x k block between leading dimensions
 hipError_t launch_copy_block(hipStream_t st, int64_t len, int64_t k, const double* x, int64_t ldx, double* y,
                              int64_t ldy);
@@ -231,6 +235,10 @@ size_t l2_op_pq_doubles(int64_t n, int64_t k);
 hipError_t l2_op(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_t s, int64_t ldy, const double* v,
                  int64_t ldv, int64_t k, const int32_t* done, double* part, double* pqpart, const double* W,
                  double* wp, double* pqw, bool rhs_mode);
+// the same step input from an explicit s x s operator M (steps then run with nbC = 0 and
+// wscale = 1): wp = M p, pqw = p .* (M p)
+hipError_t l2_op_matrix(hipStream_t st, const double* M, int64_t s, const double* v, int64_t k, const int32_t* done,
+                        double* wp, double* pqw);
 // right-hand side (after l2_op in rhs mode): y = 0, r = rhs, |rhs|, z = Minv r, p = z
 hipError_t l2_init(hipStream_t st, const L2Step& a);
 // one step after l2_op(p): alpha, y/r update, convergence decision, z = Minv r, p = z + beta p

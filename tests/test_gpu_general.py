@@ -37,14 +37,18 @@ def test_factors_match_oracle():
         assert np.linalg.norm(g - want) <= kappa * 1e-12 * np.linalg.norm(want)
 
 
-def test_general_solve_matches_lu_and_oracle_iterations():
-    say("case general solve n=400 k=12 s=32")
+@pytest.mark.parametrize("form", [0, 1])
+def test_general_solve_matches_lu_and_oracle_iterations(form):
+    # levels 2 and 3 through passes over A and A~ (form 0) or through the explicit
+    # B^T B + lam~ A~^T A~ and A~^T A~ (form 1)
+    say(f"case general solve n=400 k=12 s=32 level2_form={form}")
     n, k, s = 400, 12, 32
     a, sv, _, _ = W.general_outlier(n, k, config_id=103, big=(1e2, 1e4))
     lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
     b = W.gaussian(n, 103)
     A, P = _gen(a, 0.0, lam0, s)
-    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), tol=1e-10, inner_tol=1e-12, level3_tol=1e-12)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), tol=1e-10, inner_tol=1e-12, level3_tol=1e-12,
+                        level2_form=form)
     x = X.cpu().numpy()
     say(info)
     assert info["status"] == "MSP_OK", info

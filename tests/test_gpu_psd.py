@@ -84,7 +84,7 @@ def test_nystrom_factors_match_oracle():
     assert np.array_equal(mi, mi.T)
 
 
-def _solve_case(n, k, s, cid, lam, tol, inner_tol, b=None, seeds=(11, 12)):
+def _solve_case(n, k, s, cid, lam, tol, inner_tol, b=None, seeds=(11, 12), **opts):
     a, eigs, lam0 = _psd_case(n, k, s, cid, lam)
     if b is None:
         b = W.gaussian(n, cid)
@@ -92,16 +92,18 @@ def _solve_case(n, k, s, cid, lam, tol, inner_tol, b=None, seeds=(11, 12)):
     bt = torch.from_numpy(np.ascontiguousarray(b)).to(DEV)
     rows, signs, Y = msp.sketch(A, s, 8, seeds[0])
     P = msp.Precond("psd", rows, signs, Y, lam, lam0, 4 * s, 8, seeds[1])
-    X, info = msp.solve(P, A, bt, tol=tol, inner_tol=inner_tol)
+    X, info = msp.solve(P, A, bt, tol=tol, inner_tol=inner_tol, **opts)
     return a, eigs, lam0, b, X.cpu().numpy(), info, P, A
 
 
-def test_solve_outlier_n1024_matches_dense_and_oracle_iterations():
-    # the plain MSP regularized solve: n = 1024, 32 outliers, lam = 1e-3, tol 1e-10
-    say("case solve psd_outlier n=1024")
+@pytest.mark.parametrize("form", [0, 1])
+def test_solve_outlier_n1024_matches_dense_and_oracle_iterations(form):
+    # the plain MSP regularized solve: n = 1024, 32 outliers, lam = 1e-3, tol 1e-10; the
+    # level-2 operator through the sketch (form 0) or through C^T C + lam~ W (form 1)
+    say(f"case solve psd_outlier n=1024 level2_form={form}")
     w = W.config("psd_outlier_n1024")
     a, eigs, lam0, b, x, info, _, _ = _solve_case(w.n, 32, w.s, w.config_id, w.lam, w.tol, 1e-12,
-                                                  seeds=(w.seed_s, w.seed_phi))
+                                                  seeds=(w.seed_s, w.seed_phi), level2_form=form)
     assert info["status"] == "MSP_OK", info
     xs = dense.solve_psd(a, b, w.lam)
     assert dense.rel_residual_psd(a, x, b, w.lam) <= w.tol
