@@ -93,9 +93,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--inner-tol", type=float, default=1e-10)
-    ap.add_argument("--level2-form", type=int, default=1, choices=[0, 1],
+    ap.add_argument("--level2-form", type=int, default=1, choices=[0, 1, 2],
                     help="inner operator through the sketch each step (0) or through C^T C + lam~ W formed "
-                         "once (1, default); the same iteration")
+                         "once (1, default; the same iteration), or the one-level variant with SolveM1 solved "
+                         "exactly through its inverse (2, a comparison, not the multi-level method)")
     ap.add_argument("--max-outer", type=int, default=None,
                     help="cap the level-1 iterations (counter runs over a few sweeps only)")
     ap.add_argument("--copy-probe", action="store_true",

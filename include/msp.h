@@ -162,7 +162,11 @@ typedef struct {
                               1: through s x s matrices formed once per solve (PSD:
                                  C^T C + lam~ W; general: B^T B + lam~ A~^T A~ with B = A^T A~,
                                  and A~^T A~ for level 3). The same operators and iterations;
-                                 s^2 instead of n s (or n^2) work per inner step. */
+                                 s^2 instead of n s (or n^2) work per inner step;
+                              2: one-level variant: SolveM1 solved exactly through the explicit
+                                 inverse of the level-2 matrix of form 1 (the standard Nystrom
+                                 preconditioner of Section 2, no level-2/3 iteration; for
+                                 comparison with the multi-level method). */
 } msp_solve_opts;
 
 typedef struct {

@@ -400,6 +400,8 @@ struct SolveCtx {
   double *H2 = nullptr, *H3 = nullptr;       // explicit inner operators (s x s)
   double *B2t = nullptr, *Act = nullptr;     // general: (A^T A~)^T (s x n), A~^T (s x m)
   double* gtmp = nullptr;                    // Gram split partials
+  double *Htmp = nullptr, *Hscal = nullptr;  // level2_form 2: inverse scratch
+  int32_t* Hstat = nullptr;
   int32_t* hf;
   int32_t* df;
   int last_inner = 4, last_l3a = 4, last_l3b = 4;
@@ -439,7 +441,14 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
   double* rh = w.take<double>(mx * k);
   double* bn = w.take<double>(k);
   double *H2 = nullptr, *H3 = nullptr, *B2t = nullptr, *Act = nullptr, *gtmp = nullptr;
-  if (form == 1) {
+  double *Htmp = nullptr, *Hscal = nullptr;
+  int32_t* Hstat = nullptr;
+  if (form == 2) {
+    Htmp = w.take<double>(s * s);
+    Hscal = w.take<double>(4);
+    Hstat = w.take<int32_t>(4);
+  }
+  if (form >= 1) {
     H2 = w.take<double>(s * s);
     if (P->structure == MSP_SYM_PSD) {
       gtmp = w.take<double>((size_t)gram_splits(n, s) * s * s + 1);
@@ -451,6 +460,9 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
     }
   }
   if (c) {
+    c->Htmp = Htmp;
+    c->Hscal = Hscal;
+    c->Hstat = Hstat;
     c->form = form;
     c->H2 = H2;
     c->H3 = H3;
@@ -639,8 +651,20 @@ msp_status dense_mv_t(SolveCtx& c, const double* M, int64_t rows, int64_t cols, 
 // level2_form 1: the explicit inner operators, formed once per solve.
 // PSD: H2 = C^T C + lam~ W. General: A~^T (transposed copy), B^T = (A^T A~)^T by one
 // block product over A with s right-hand sides, H3 = A~^T A~ and H2 = B^T B + lam~ H3.
+msp_status invert_h2(SolveCtx& c) {
+  if (c.form != 2) return MSP_OK;
+  // the one-level preconditioner: SolveM1 exactly, through (H2 + mu I)^{-1}
+  MSP_CHECK_HIP(hipMemsetAsync(c.Hstat, 0, sizeof(int32_t), c.st));
+  MSP_CHECK_HIP(spd_inverse(c.st, c.s, c.H2, c.Htmp, c.P->shift_rel, c.Hscal, c.Hstat));
+  int32_t bad = 0;
+  MSP_CHECK_HIP(hipMemcpyAsync(&bad, c.Hstat, sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
+  MSP_CHECK_HIP(hipStreamSynchronize(c.st));
+  if (bad) return msp_fail(MSP_ERR_NOT_POSDEF, "the level-2 matrix is not positive definite");
+  return MSP_OK;
+}
+
 msp_status build_explicit(SolveCtx& c) {
-  if (c.form != 1) return MSP_OK;
+  if (c.form == 0) return MSP_OK;
   const msp_precond* P = c.P;
   const int64_t n = c.n, m = c.m, s = c.s;
   if (P->structure == MSP_SYM_PSD) {
@@ -650,7 +674,7 @@ msp_status build_explicit(SolveCtx& c) {
     else
       MSP_CHECK_HIP(launch_gram_f32(c.st, (const float*)P->Y, n, s, P->ldy, c.H2, c.gtmp, sp));
     MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H2, P->lt, P->Wm, 0.0, c.H2));
-    return MSP_OK;
+    return invert_h2(c);
   }
   int nb = 0;
   MSP_CHECK_HIP(launch_transpose_f64(c.st, P->Y, P->y_t, m, s, P->ldy, c.Act, m));
@@ -665,7 +689,7 @@ msp_status build_explicit(SolveCtx& c) {
                             &nb));
   MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H2, P->lt, c.H3, 0.0, c.H2));
   MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H3, 0.0, nullptr, 0.0, c.H3));
-  return MSP_OK;
+  return invert_h2(c);
 }
 
 // ---------------------------------- PSD (Algorithms 1-2) ----------------------------
@@ -677,6 +701,14 @@ msp_status psd_solve_m1(SolveCtx& c, const double* r, double* z) {
   L2Step a = l2step_for(c, c.L2, P->Minv, P->Wm, P->lt, 0.0, c.o->inner_tol, c.o->max_inner, SLOT_L2, pdone);
   MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, n, s, P->ldy, r, n, k, pdone, a.part, nullptr, nullptr, nullptr, nullptr,
                       true));
+  if (c.form == 2) {  // y = (C^T C + lam~ W)^{-1} C^T r exactly
+    MSP_CHECK_HIP(l2_reduce_to(c.st, a, c.rhs2, pdone));
+    MSP_CHECK_HIP(launch_small_mv(c.st, s, c.H2, c.rhs2, k, pdone, c.L2.x));
+    MSP_CHECK_HIP(
+        launch_y_z(c.st, P->Y, P->y_t, n, s, P->ldy, c.L2.x, k, 1.0 / P->lt, r, n, -1.0 / P->lt, pdone, z, n));
+    TRY(sync(c));  // the level-1 mirror is read by the caller after SolveM1
+    return MSP_OK;
+  }
   MSP_CHECK_HIP(l2_init(c.st, a));
   if (c.form == 1) {
     L2Step b = a;  // steps on H = C^T C + lam~ W
@@ -785,6 +817,12 @@ msp_status gen_solve_m1(SolveCtx& c, const double* r, double* z) {
     MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, m, s, P->ldy, c.mvec, m, k, pdone, a.part, nullptr, nullptr, nullptr,
                         nullptr, true));
     MSP_CHECK_HIP(l2_reduce_to(c.st, a, c.rhs2, pdone));
+  }
+  if (c.form == 2) {  // y = (B^T B + lam~ A~^T A~)^{-1} A~^T A r exactly: no level 2 or 3
+    MSP_CHECK_HIP(launch_small_mv(c.st, s, c.H2, c.rhs2, k, pdone, L.x));
+    TRY(dense_mv_t(c, c.B2t, s, n, L.x, s, c.nvec, n, pdone));
+    MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0 / P->lt, r, n, -1.0 / P->lt, c.nvec, n, z, n, pdone));
+    return MSP_OK;
   }
   MSP_CHECK_HIP(fcg_init(c.st, L.S, s, c.rhs2, s, L.r, L.x, pdone, c.df + SLOT_L2));
   TRY(gen_solve_m2(c, L.r, L.z, L.S.done));
@@ -1105,7 +1143,7 @@ extern "C" msp_status msp_solve_workspace(const msp_precond* P, int64_t k, const
   msp_solve_opts dflt;
   msp_solve_opts_default(&dflt);
   const msp_solve_opts* o = opts ? opts : &dflt;
-  REQUIRE(o->level2_form == 0 || o->level2_form == 1, "level2_form must be 0 or 1");
+  REQUIRE(o->level2_form >= 0 && o->level2_form <= 2, "level2_form must be 0, 1 or 2");
   WsCarver w(nullptr, 0);
   solve_layout(w, P, k, nullptr, o->level2_form);
   *bytes = w.off;

@@ -37,7 +37,7 @@ def test_factors_match_oracle():
         assert np.linalg.norm(g - want) <= kappa * 1e-12 * np.linalg.norm(want)
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_general_solve_matches_lu_and_oracle_iterations(form):
     # levels 2 and 3 through passes over A and A~ (form 0) or through the explicit
     # B^T B + lam~ A~^T A~ and A~^T A~ (form 1)
@@ -59,7 +59,10 @@ def test_general_solve_matches_lu_and_oracle_iterations(form):
                         omsp.MspOptions(tol=1e-10, inner_tol=1e-12, level3_tol=1e-12))
     O.solve_system(b)
     say("gpu", info["outer_iters"], "oracle", O.info.outer_iterations)
-    assert abs(info["outer_iters"] - O.info.outer_iterations) <= 2
+    if form < 2:  # the same iteration as the oracle's Algorithms 3-5
+        assert abs(info["outer_iters"] - O.info.outer_iterations) <= 2
+    else:  # the one-level preconditioner (an explicit inverse) is a different, weaker one here
+        assert info["inner_iters"] == 0 and info["level3_iters"] == 0
 
 
 def test_lower_bound_example_one():

@@ -96,7 +96,7 @@ def _solve_case(n, k, s, cid, lam, tol, inner_tol, b=None, seeds=(11, 12), **opt
     return a, eigs, lam0, b, X.cpu().numpy(), info, P, A
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_solve_outlier_n1024_matches_dense_and_oracle_iterations(form):
     # the plain MSP regularized solve: n = 1024, 32 outliers, lam = 1e-3, tol 1e-10; the
     # level-2 operator through the sketch (form 0) or through C^T C + lam~ W (form 1)
