@@ -101,9 +101,11 @@ def main():
                     help="cap the level-1 iterations (counter runs over a few sweeps only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 2 GiB elementwise copy (calibrates the HBM byte counters) and exit")
-    ap.add_argument("--workload", default="rbf_gp_n32768", choices=["rbf_gp_n32768", "batched_rbf_256"],
+    ap.add_argument("--workload", default="rbf_gp_n32768",
+                    choices=["rbf_gp_n32768", "batched_rbf_256", "general_outlier_n65536"],
                     help="rbf_gp_n32768: the single n=32768 FP64 solve (default); batched_rbf_256: 256 uneven "
-                         "F32 RBF systems x 16 right-hand sides in one batched launch")
+                         "F32 RBF systems x 16 right-hand sides in one batched launch; general_outlier_n65536: "
+                         "the three-level solve of A x = b, n=65536, 8 right-hand sides")
     ap.add_argument("--count", type=int, default=None, help="batched: number of systems (default 256)")
     ap.add_argument("--lo", default="f32", choices=["f32", "bf16"], help="batched: sweep precision inside MSP")
     ap.add_argument("--fp64-sample", type=int, default=4,
@@ -132,6 +134,9 @@ def main():
 
     if args.workload == "batched_rbf_256":
         bench_batched(args)
+        return
+    if args.workload == "general_outlier_n65536":
+        bench_general(args)
         return
 
     name = "rbf_gp_n32768"
@@ -210,6 +215,94 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(a, b, w, lam0, infos[-1]["outer_iters"], args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def assemble_householder(u_vs, diag, v_vs, dev):
+    """U diag(d) V^T (U, V products of Householder reflections) on the GPU, by the same
+    rank-one updates as the host recipe of workloads.general_outlier (input preparation)."""
+    import torch
+    n = diag.shape[0]
+    A = torch.zeros((n, n), dtype=torch.float64, device=dev)
+    A.diagonal().copy_(torch.from_numpy(diag).to(dev))
+    for r in range(len(v_vs) - 1, -1, -1):
+        v = torch.from_numpy(v_vs[r]).to(dev)
+        A.addr_(torch.mv(A, v), v, alpha=-2.0)
+    for r in range(len(u_vs) - 1, -1, -1):
+        u = torch.from_numpy(u_vs[r]).to(dev)
+        A.addr_(u, torch.mv(A.t(), u), alpha=-2.0)
+    return A
+
+
+def bench_general(args):
+    """A x = b through the three-level method (Algorithms 3-5): A = U diag(sv) V^T,
+    n = 65536, 1024 singular values 10^U(3,6), the rest U(1,10); 8 right-hand sides;
+    FP64 problem, F32 sweeps inside MSP with FP64 refinement; s = 2048, phi = 8192."""
+    import numpy as np
+    import torch
+
+    import paper_2405_05865_amd as msp
+    import workloads as W
+
+    w = W.config("general_outlier_n65536")
+    n = args.n or w.n
+    s = w.s if args.n is None else max(64, n // 32)
+    phi = 4 * s
+    dev = torch.device("cuda:0")
+    msp.library()
+    t = time.time()
+    sv, u_vs, v_vs = W.general_outlier_factors(n, w.extra["k"] if args.n is None else max(8, n // 64), w.config_id)
+    A = assemble_householder(u_vs, sv, v_vs, dev)
+    A32 = A.float()
+    B = torch.from_numpy(W.gaussian((w.nrhs, n), w.config_id)).to(dev)
+    torch.cuda.synchronize()
+    ev = np.sort(sv)[::-1] ** 2  # eigenvalues of A^T A
+    l = s // 2
+    lam0 = float(2.0 / l * ev[l:].sum())
+    log(f"[bench] general n={n} s={s}: inputs resident in HBM ({time.time() - t:.1f} s), lam0={lam0:.4g}")
+
+    def step():
+        rows, signs, Y = msp.sketch(A32, s, w.gamma, w.seed_s)
+        P = msp.Precond("general", rows, signs, Y, 0.0, lam0, phi, w.phi_gamma, w.seed_phi)
+        X, info = msp.solve(P, A, B, A_lo=A32, refine=1, tol=w.tol, level2_form=args.level2_form)
+        P.close()
+        return X, info
+
+    for i in range(args.warmup):
+        _, info = step()
+        log(f"[bench] warmup {i}: {info}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        X, info = step()
+        log(f"[bench] step {i}: outer={info['outer_iters']} inner={info['inner_iters']} "
+            f"level3={info['level3_iters']} refine={info['refine_steps']} relres={info['rel_residual_max']:.2e} "
+            f"{info['status']}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    line = {
+        "metric": "RHS-solves/sec at rel. residual 1e-8, three-level general solve (n=65536, 8 RHS)",
+        "value": round(w.nrhs * args.steps / el, 4),
+        "unit": "RHS-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"general_outlier_n{n}", "n": n, "s": s, "phi": phi, "gamma": w.gamma,
+                   "nrhs": w.nrhs, "lambda": 0.0, "lambda0": lam0, "tol": w.tol, "matrix": "f64",
+                   "sweeps": "f32", "refinement": "fp64", "level2_form": args.level2_form, "levels": 3},
+        "outer_iters": info["outer_iters"],
+        "inner_iters": info["inner_iters"],
+        "level3_iters": info["level3_iters"],
+        "refine_steps": info["refine_steps"],
+        "rel_residual": info["rel_residual_max"],
+        "converged": info["status"] == "MSP_OK" and info["rel_residual_max"] <= w.tol,
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -159,10 +159,13 @@ typedef struct {
   int32_t level2_form;     /* how the inner operators are applied (default 1):
                               0: through the sketch each inner step (PSD: C^T (C y) + lam~ W y;
                                  general: passes over A~ and two A-sweeps), the paper's cost model;
-                              1: through s x s matrices formed once per solve (PSD:
-                                 C^T C + lam~ W; general: B^T B + lam~ A~^T A~ with B = A^T A~,
-                                 and A~^T A~ for level 3). The same operators and iterations;
-                                 s^2 instead of n s (or n^2) work per inner step;
+                              1: through matrices formed once per solve: PSD: the s x s
+                                 C^T C + lam~ W (s^2 instead of n s work per inner step);
+                                 general: level 2 as B^T (B y) + lam~ A~^T A~ y with the n x s
+                                 B = A^T A~ (two passes over B instead of two A-sweeps) and
+                                 level 3 through the s x s A~^T A~. The same operators and
+                                 iterations. Forming C^T C squares the conditioning of C;
+                                 form 0 avoids that for very ill-conditioned A;
                               2: one-level variant: SolveM1 solved exactly through the explicit
                                  inverse of the level-2 matrix of form 1 (the standard Nystrom
                                  preconditioner of Section 2, no level-2/3 iteration; for

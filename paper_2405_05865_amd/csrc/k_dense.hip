@@ -4,7 +4,8 @@
 //
 // The inverse is computed by block Gauss-Jordan sweeps without pivoting. For SPD M
 // every pivot block is a Schur complement of M, hence SPD, so no pivoting is needed;
-// a non-positive pivot flags the matrix as not positive definite.
+// each pivot block is factored by Cholesky (a non-positive pivot flags the matrix as
+// not positive definite) and the Schur complements are formed in Cholesky form.
 #include "msp_internal.h"
 
 namespace {
@@ -102,14 +103,22 @@ __global__ void k_add_diag_scaled(int64_t s, double* M, const double* tr, double
   if (i < s) M[i * s + i] += rel * (*tr) / (double)s;
 }
 
-// One block Gauss-Jordan sweep over pivots [k0, k0 + nbk). Tile of 64 x 64 per block.
+// One block Gauss-Jordan sweep over pivots K = [k0, k0 + nbk). Tile of 64 x 64 per block.
+// The pivot block is factored X_KK = L L^T (Cholesky, in shared memory; a pivot <= 0
+// flags the matrix as not positive definite) and every product with X_KK^{-1} is taken
+// through Li = L^{-1}:
+//   X_KK <- Li^T Li,  X_KJ <- Li^T (Li X_KJ),  X_IK <- -(X_IK Li^T) Li,
+//   X_IJ <- X_IJ - (X_IK Li^T)(Li X_KJ).
+// The trailing update is then the Cholesky form of the Schur complement, whose error
+// does not grow with the conditioning of X_KK (an explicit inverse of the pivot block
+// there would lose the small trailing pivots of ill-conditioned SPD matrices).
 template <int NB>
 __global__ void __launch_bounds__(256) k_bgj_step(const double* __restrict__ in, double* __restrict__ out, int s,
                                                   int k0, int32_t* status) {
-  __shared__ double P[NB][NB + 1];     // pivot block, inverted in place
-  __shared__ double Lk[TILE][NB + 1];  // in[I, K]
-  __shared__ double Uk[NB][TILE + 1];  // in[K, J], then P^{-1} in[K, J]
-  __shared__ double rowp[NB], colp[NB];
+  __shared__ double L[NB][NB + 1];     // pivot block, then its Cholesky factor
+  __shared__ double Li[NB][NB + 1];    // L^{-1}
+  __shared__ double Lk[TILE][NB + 1];  // X[I, K], then X[I, K] Li^T
+  __shared__ double Uk[NB][TILE + 1];  // X[K, J], then Li X[K, J]
   __shared__ int bad;
   const int nbk = min(NB, s - k0);
   const int I = blockIdx.y * TILE, J = blockIdx.x * TILE;
@@ -117,7 +126,8 @@ __global__ void __launch_bounds__(256) k_bgj_step(const double* __restrict__ in,
   if (t == 0) bad = 0;
   for (int e = t; e < NB * NB; e += 256) {
     const int a = e / NB, b = e % NB;
-    P[a][b] = (a < nbk && b < nbk) ? in[(int64_t)(k0 + a) * s + k0 + b] : (a == b ? 1.0 : 0.0);
+    L[a][b] = (a < nbk && b < nbk) ? in[(int64_t)(k0 + a) * s + k0 + b] : (a == b ? 1.0 : 0.0);
+    Li[a][b] = 0.0;
   }
   for (int e = t; e < TILE * NB; e += 256) {
     const int a = e / NB, b = e % NB;
@@ -130,41 +140,54 @@ __global__ void __launch_bounds__(256) k_bgj_step(const double* __restrict__ in,
     Uk[a][b] = (j < s && a < nbk) ? in[(int64_t)(k0 + a) * s + j] : 0.0;
   }
   __syncthreads();
-  // unblocked Gauss-Jordan on the pivot block
+  // Cholesky of the pivot block (lower triangle)
   for (int p = 0; p < NB; ++p) {
-    const double piv = P[p][p];
-    if (t < NB) {
-      rowp[t] = P[p][t];
-      colp[t] = P[t][p];
+    if (t == 0) {
+      const double d = L[p][p];
+      if (!(d > 0.0)) bad = 1;
+      L[p][p] = d > 0.0 ? sqrt(d) : 1.0;
     }
-    if (t == 0 && !(piv > 0.0)) bad = 1;
     __syncthreads();
-    const double ip = 1.0 / piv;
+    if (t > p && t < NB) L[t][p] /= L[p][p];
+    __syncthreads();
     for (int e = t; e < NB * NB; e += 256) {
-      const int a = e / NB, b = e % NB;
-      double v;
-      if (a == p && b == p) v = ip;
-      else if (a == p) v = rowp[b] * ip;
-      else if (b == p) v = -colp[a] * ip;
-      else v = P[a][b] - colp[a] * rowp[b] * ip;
-      P[a][b] = v;
+      const int i = e / NB, j = e % NB;
+      if (j > p && i >= j) L[i][j] -= L[i][p] * L[j][p];
     }
     __syncthreads();
   }
   if (t == 0 && bad && blockIdx.x == 0 && blockIdx.y == 0) *status = 1;
-  // Uk <- P^{-1} Uk
+  // Li = L^{-1} (column c by thread c, forward substitution)
+  if (t < NB) {
+    const int c = t;
+    for (int i = c; i < NB; ++i) {
+      double acc = (i == c) ? 1.0 : 0.0;
+      for (int j = c; j < i; ++j) acc -= L[i][j] * Li[j][c];
+      Li[i][c] = acc / L[i][i];
+    }
+  }
+  __syncthreads();
+  // Uk <- Li Uk ; Lk <- Lk Li^T   (results staged in registers)
   {
-    double tmp[(NB * TILE + 255) / 256];
+    constexpr int PER = (NB * TILE + 255) / 256;
+    double tu[PER], tl[PER];
     int q = 0;
     for (int e = t; e < NB * TILE; e += 256, ++q) {
-      const int a = e / TILE, b = e % TILE;
+      const int a = e / TILE, b = e % TILE;  // Uk row a, column b
       double acc = 0.0;
-      for (int c = 0; c < NB; ++c) acc = fma(P[a][c], Uk[c][b], acc);
-      tmp[q] = acc;
+      for (int c = 0; c <= a; ++c) acc = fma(Li[a][c], Uk[c][b], acc);
+      tu[q] = acc;
+      const int r = e / NB, cc = e % NB;  // Lk row r, column cc
+      double acl = 0.0;
+      for (int c = 0; c <= cc; ++c) acl = fma(Lk[r][c], Li[cc][c], acl);
+      tl[q] = acl;
     }
     __syncthreads();
     q = 0;
-    for (int e = t; e < NB * TILE; e += 256, ++q) Uk[e / TILE][e % TILE] = tmp[q];
+    for (int e = t; e < NB * TILE; e += 256, ++q) {
+      Uk[e / TILE][e % TILE] = tu[q];
+      Lk[e / NB][e % NB] = tl[q];
+    }
     __syncthreads();
   }
   const bool rows_hit = (I < k0 + nbk) && (I + TILE > k0);
@@ -175,19 +198,17 @@ __global__ void __launch_bounds__(256) k_bgj_step(const double* __restrict__ in,
     if (i >= s || j >= s) continue;
     const bool ik = rows_hit && i >= k0 && i < k0 + nbk;
     const bool jk = cols_hit && j >= k0 && j < k0 + nbk;
-    double v;
+    double v = 0.0;
     if (ik && jk) {
-      v = P[i - k0][j - k0];
+      for (int c = 0; c < NB; ++c) v = fma(Li[c][i - k0], Li[c][j - k0], v);
     } else if (ik) {
-      v = Uk[i - k0][b];
+      for (int c = 0; c < NB; ++c) v = fma(Li[c][i - k0], Uk[c][b], v);
     } else if (jk) {
-      double acc = 0.0;
-      for (int c = 0; c < NB; ++c) acc = fma(Lk[a][c], P[c][j - k0], acc);
-      v = -acc;
+      for (int c = 0; c < NB; ++c) v = fma(Lk[a][c], Li[c][j - k0], v);
+      v = -v;
     } else {
-      double acc = 0.0;
-      for (int c = 0; c < NB; ++c) acc = fma(Lk[a][c], Uk[c][b], acc);
-      v = in[(int64_t)i * s + j] - acc;
+      for (int c = 0; c < NB; ++c) v = fma(Lk[a][c], Uk[c][b], v);
+      v = in[(int64_t)i * s + j] - v;
     }
     out[(int64_t)i * s + j] = v;
   }

@@ -421,49 +421,81 @@ __global__ void __launch_bounds__(256) k_l2_prec(L2Args a, int decide) {
   }
 }
 
-// ---- commit the decision; beta = <z, r - r_old> / rz ; rz = <r, z> ; p = z + beta p
-// (one block), then publish the active count and the largest iteration count
+// ---- commit the decision; beta = <z, r - r_old> / rz ; rz = <r, z> ; p = z + beta p.
+// One block per column; the last block to finish publishes the active count and the
+// largest iteration count.
 __global__ void __launch_bounds__(256) k_l2_dir(L2Args a, int first) {
   __shared__ double shs[4];
-  __shared__ double bt;
-  __shared__ int cnt, mx;
+  const int j = blockIdx.x;
   const int np = pblocks(a.s);
+  const int dj = a.S.done_next[j];
+  if (dj == 0) {
+    const double zr = strided_sum<256>(a.dpart + (int64_t)j * 2 + 0, np, (int64_t)a.k * 2, shs);
+    const double zro = strided_sum<256>(a.dpart + (int64_t)j * 2 + 1, np, (int64_t)a.k * 2, shs);
+    const double beta = first ? 0.0 : (zr - zro) / a.S.rz[j];
+    for (int c = threadIdx.x; c < a.s; c += 256) {
+      const int64_t o = (int64_t)j * a.s + c;
+      a.p[o] = first ? a.z[o] : fma(beta, a.p[o], a.z[o]);
+    }
+    if (threadIdx.x == 0) {
+      a.S.beta[j] = beta;
+      a.S.rz[j] = zr;
+    }
+  }
+  if (threadIdx.x == 0) {
+    a.S.done[j] = dj;
+    a.S.iters[j] = a.S.iters_next[j];
+  }
+  // one column: no other block to wait for (and no device-scope fence)
+  if (gridDim.x > 1 && !last_block(a.S.counter)) return;
+  __shared__ int cnt, mx;
   if (threadIdx.x == 0) {
     cnt = 0;
     mx = 0;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < a.k; j += 256) {
-    const int dj = a.S.done_next[j];
-    a.S.done[j] = dj;
-    a.S.iters[j] = a.S.iters_next[j];
-    atomicAdd(&cnt, dj == 0 ? 1 : 0);
-    atomicMax(&mx, a.S.iters_next[j]);
+  for (int jj = threadIdx.x; jj < a.k; jj += 256) {
+    atomicAdd(&cnt, a.S.done_next[jj] == 0 ? 1 : 0);
+    atomicMax(&mx, a.S.iters_next[jj]);
   }
   __syncthreads();
-  for (int j = 0; j < a.k; ++j) {
-    if (a.S.done_next[j] != 0) continue;
-    const double zr = strided_sum<256>(a.dpart + (int64_t)j * 2 + 0, np, (int64_t)a.k * 2, shs);
-    const double zro = strided_sum<256>(a.dpart + (int64_t)j * 2 + 1, np, (int64_t)a.k * 2, shs);
-    if (threadIdx.x == 0) {
-      const double beta = first ? 0.0 : (zr - zro) / a.S.rz[j];
-      a.S.beta[j] = beta;
-      a.S.rz[j] = zr;
-      bt = beta;
-    }
-    __syncthreads();
-    const double beta = bt;
-    for (int c = threadIdx.x; c < a.s; c += 256) {
-      const int64_t o = (int64_t)j * a.s + c;
-      a.p[o] = first ? a.z[o] : fma(beta, a.p[o], a.z[o]);
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
     *a.S.active = cnt;
+    *a.S.counter = 0;
     if (a.mirror) {
       __hip_atomic_store(a.mirror, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       __hip_atomic_store(a.mirror + 1, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
+// ---- the inner operator through an explicit s x s matrix W, every column in one pass:
+// wp = W v and pqw = v .* (W v) (a wavefront per row of W)
+template <int CPL>
+__global__ void __launch_bounds__(256) k_w_rows(const double* __restrict__ W, int s, const double* __restrict__ v,
+                                               int k, const int32_t* __restrict__ done, double* __restrict__ wp,
+                                               double* __restrict__ pqw) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= s) return;  // whole wavefronts; no block barrier below
+  double m[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = lane + q * WAVE;
+    m[q] = (c < s) ? W[(int64_t)i * s + c] : 0.0;
+  }
+  for (int j = 0; j < k; ++j) {
+    if (done && done[j]) continue;
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int c = lane + q * WAVE;
+      t = fma(m[q], (c < s) ? v[(int64_t)j * s + c] : 0.0, t);
+    }
+    t = wave_sum(t);
+    if (lane == 0) {
+      wp[(int64_t)j * s + i] = t;
+      pqw[(int64_t)j * s + i] = v[(int64_t)j * s + i] * t;
     }
   }
 }
@@ -605,7 +637,19 @@ hipError_t l2_op(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_
 // (the W-row part of the Y pass alone; steps built on it use nbC = 0)
 hipError_t l2_op_matrix(hipStream_t st, const double* M, int64_t s, const double* v, int64_t k, const int32_t* done,
                         double* wp, double* pqw) {
-  return op_dispatch<double, 0>(st, nullptr, 0, (int)s, 0, v, s, (int)k, done, nullptr, nullptr, M, wp, pqw, 0);
+  const int cpl = (int)((s + WAVE - 1) / WAVE);
+  const unsigned blocks = (unsigned)((s + 3) / 4);
+  const int si = (int)s, ki = (int)k;
+#define WR(C) hipLaunchKernelGGL(k_w_rows<C>, dim3(blocks), dim3(256), 0, st, M, si, v, ki, done, wp, pqw)
+  if (cpl <= 1) WR(1);
+  else if (cpl <= 2) WR(2);
+  else if (cpl <= 4) WR(4);
+  else if (cpl <= 8) WR(8);
+  else if (cpl <= 16) WR(16);
+  else if (cpl <= 32) WR(32);
+  else return hipErrorInvalidValue;
+#undef WR
+  return hipGetLastError();
 }
 
 // rhs reduction, then the first preconditioner application (p = z = Minv r)
@@ -613,7 +657,7 @@ hipError_t l2_init(hipStream_t st, const L2Step& a) {
   hipLaunchKernelGGL(k_l2_init, dim3((unsigned)ublocks((int)a.s), (unsigned)a.k), dim3(NTU), 0, st, make_args(a));
   hipError_t e = prec_launch(st, a, 2);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_l2_dir, dim3(1), dim3(256), 0, st, make_args(a), 1);
+  hipLaunchKernelGGL(k_l2_dir, dim3((unsigned)a.k), dim3(256), 0, st, make_args(a), 1);
   return hipGetLastError();
 }
 
@@ -628,6 +672,6 @@ hipError_t l2_step(hipStream_t st, const L2Step& a) {
   hipLaunchKernelGGL(k_l2_update, dim3((unsigned)ublocks((int)a.s), (unsigned)a.k), dim3(NTU), 0, st, make_args(a));
   hipError_t e = prec_launch(st, a, 1);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_l2_dir, dim3(1), dim3(256), 0, st, make_args(a), 0);
+  hipLaunchKernelGGL(k_l2_dir, dim3((unsigned)a.k), dim3(256), 0, st, make_args(a), 0);
   return hipGetLastError();
 }

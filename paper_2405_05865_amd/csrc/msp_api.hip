@@ -648,9 +648,11 @@ msp_status dense_mv_t(SolveCtx& c, const double* M, int64_t rows, int64_t cols, 
   return MSP_OK;
 }
 
-// level2_form 1: the explicit inner operators, formed once per solve.
+// level2_form 1: the inner operators through matrices formed once per solve.
 // PSD: H2 = C^T C + lam~ W. General: A~^T (transposed copy), B^T = (A^T A~)^T by one
-// block product over A with s right-hand sides, H3 = A~^T A~ and H2 = B^T B + lam~ H3.
+// block product over A with s right-hand sides and H3 = A~^T A~ (level 3); level 2 is
+// applied through B. Form 2 also forms H2 = B^T B + lam~ H3 (PSD: C^T C + lam~ W) and
+// inverts it.
 msp_status invert_h2(SolveCtx& c) {
   if (c.form != 2) return MSP_OK;
   // the one-level preconditioner: SolveM1 exactly, through (H2 + mu I)^{-1}
@@ -685,10 +687,12 @@ msp_status build_explicit(SolveCtx& c) {
     MSP_CHECK_HIP(launch_gemv_t(c.st, c.A_sw, c.sw_t, m, n, c.lda, c.Act, m, c.B2t, n, s, nullptr, c.gpart));
   MSP_CHECK_HIP(launch_gemm(c.st, c.Act, MSP_F64, false, s, m, m, c.Act, m, c.H3, s, s, 0.0, false, nullptr, nullptr,
                             &nb));
-  MSP_CHECK_HIP(launch_gemm(c.st, c.B2t, MSP_F64, false, s, n, n, c.B2t, n, c.H2, s, s, 0.0, false, nullptr, nullptr,
-                            &nb));
-  MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H2, P->lt, c.H3, 0.0, c.H2));
   MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H3, 0.0, nullptr, 0.0, c.H3));
+  if (c.form == 2) {  // the one-level variant needs the level-2 matrix itself
+    MSP_CHECK_HIP(launch_gemm(c.st, c.B2t, MSP_F64, false, s, n, n, c.B2t, n, c.H2, s, s, 0.0, false, nullptr,
+                              nullptr, &nb));
+    MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H2, P->lt, c.H3, 0.0, c.H2));
+  }
   return invert_h2(c);
 }
 
@@ -787,8 +791,14 @@ msp_status gen_solve_m2(SolveCtx& c, const double* r, double* z, const int32_t* 
 msp_status gen_op2(SolveCtx& c, const double* p2, double* q2, const int32_t* skip) {
   const msp_precond* P = c.P;
   const int64_t m = c.m, n = c.n, s = c.s, k = c.k;
-  if (c.form == 1) {  // the explicit B^T B + lam~ A~^T A~
-    MSP_CHECK_HIP(launch_small_mv(c.st, s, c.H2, p2, k, skip, q2));
+  if (c.form == 1) {
+    // B^T (B p2) + lam~ A~^T A~ p2 with B = A^T A~ formed once (two passes over B). The
+    // product B^T B itself is not formed: its condition number is the fourth power of
+    // A's singular-value spread and FP64 would lose the small directions.
+    TRY(dense_mv_t(c, c.B2t, s, n, p2, s, c.nvec, n, skip));
+    TRY(dense_mv(c, c.B2t, s, n, c.nvec, n, q2, s, skip));
+    TRY(dense_mv(c, c.H3, s, s, p2, s, c.tmp_s, s, skip));
+    MSP_CHECK_HIP(launch_axpby(c.st, s, k, 1.0, q2, s, P->lt, c.tmp_s, s, q2, s, skip));
     return MSP_OK;
   }
   MSP_CHECK_HIP(launch_y_z(c.st, P->Y, P->y_t, m, s, P->ldy, p2, k, 0.0, nullptr, 0, 1.0, skip, c.mvec, m));
@@ -909,6 +919,9 @@ msp_status gen_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int m
     TRY(gen_solve_m1(c, L.r, L.z));
     MSP_CHECK_HIP(fcg_direction(c.st, L.S, n, L.r, L.ro, L.z, L.p));
     ++it;
+    if (log_on() && it % 25 == 0)
+      fprintf(stderr, "[msp] level 1: %d steps, %lld level-2, %lld level-3 so far\n", it,
+              (long long)c.acc.inner_iters, (long long)c.acc.level3_iters);
   }
   c.acc.outer_iters += (int32_t)*slot(c, SLOT_L1 + 1);
   return MSP_OK;

@@ -14,8 +14,10 @@ from .generators import (  # noqa: F401
     rbf_matrix,
     rbf_rows,
     general_outlier,
+    general_outlier_factors,
     householder_apply,
     schatten_psd,
+    schatten_psd_factors,
     batched_rbf_sizes,
     batched_rbf_system,
     system_rng,

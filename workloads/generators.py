@@ -165,26 +165,39 @@ def _outer_product_matrix(u_vs, diag, v_vs, dtype, n, block=4096):
     return a.astype(dtype, copy=False)
 
 
-def general_outlier(n: int, k: int, config_id: int, reflections: int = 8,
-                    big=(1e3, 1e6), small=(1.0, 10.0)):
-    """Nonsymmetric A = U diag(sv) V^T with U, V products of Householder reflections,
-    k singular values log-uniform in ``big`` at indices 0..k-1, the rest uniform in
-    ``small``. Returns (A, sv, u_vs, v_vs)."""
+def general_outlier_factors(n: int, k: int, config_id: int, reflections: int = 8,
+                            big=(1e3, 1e6), small=(1.0, 10.0)):
+    """The factors of general_outlier without forming A: (sv, u_vs, v_vs)."""
     u_vs = householder_vectors(n, reflections, config_id, _MATRIX)
     v_vs = householder_vectors(n, reflections, config_id, _MATRIX + 10)
     rs = rng_for(config_id, _SPECTRUM)
     sv = np.empty(n)
     sv[:k] = 10.0 ** rs.uniform(math.log10(big[0]), math.log10(big[1]), size=k)
     sv[k:] = rs.uniform(small[0], small[1], size=n - k)
+    return sv, u_vs, v_vs
+
+
+def general_outlier(n: int, k: int, config_id: int, reflections: int = 8,
+                    big=(1e3, 1e6), small=(1.0, 10.0)):
+    """Nonsymmetric A = U diag(sv) V^T with U, V products of Householder reflections,
+    k singular values log-uniform in ``big`` at indices 0..k-1, the rest uniform in
+    ``small``. Returns (A, sv, u_vs, v_vs)."""
+    sv, u_vs, v_vs = general_outlier_factors(n, k, config_id, reflections, big, small)
     a = _outer_product_matrix(u_vs, sv, v_vs, np.float64, n)
     return a, sv, u_vs, v_vs
+
+
+def schatten_psd_factors(n: int, config_id: int, reflections: int = 8):
+    """The factors of schatten_psd without forming A: (sigma, q_vs)."""
+    q_vs = householder_vectors(n, reflections, config_id, _MATRIX)
+    sigma = 1.0 / np.arange(1, n + 1, dtype=np.float64)
+    return sigma, q_vs
 
 
 def schatten_psd(n: int, config_id: int, reflections: int = 8):
     """PSD A = Q diag(1/i) Q^T, Q a product of Householder reflections.
     Returns (A, sigma, q_vs)."""
-    q_vs = householder_vectors(n, reflections, config_id, _MATRIX)
-    sigma = 1.0 / np.arange(1, n + 1, dtype=np.float64)
+    sigma, q_vs = schatten_psd_factors(n, config_id, reflections)
     a = _outer_product_matrix(q_vs, sigma, q_vs, np.float64, n)
     a = 0.5 * (a + a.T)
     return a, sigma, q_vs
