@@ -124,3 +124,19 @@ def test_dense_gradients_by_finite_differences():
     ea = np.zeros_like(a)
     ea[2, 7] = h
     assert da[2, 7] == pytest.approx((loss(a + ea, bm, lam) - loss(a - ea, bm, lam)) / (2 * h), rel=1e-5)
+
+
+@pytest.mark.parametrize("dt,u", [(torch.bfloat16, 2.0 ** -8), (torch.float32, 2.0 ** -24)])
+def test_rounding_shift_dominates_the_perturbation(dt, u):
+    # The inner shift of refinement over low-precision sweeps: elementwise round-to-
+    # nearest of a symmetric A gives a symmetric E = A_lo - A_hi with |E_ij| <= u |A_ij|,
+    # so ||E||_2 <= ||E||_inf <= u ||A||_inf and A_lo + u ||A||_inf I - A_hi is PSD.
+    import workloads as W
+    for cid, n in ((61, 120), (62, 300)):
+        a = W.rbf_matrix(W.rbf_points(n, 4, cid), lengthscale=1.5)
+        lo = torch.from_numpy(a).to(dt).double().numpy()
+        e = lo - a
+        assert np.array_equal(e, e.T)
+        delta = u * np.abs(a).sum(axis=1).max()
+        assert np.linalg.norm(e, 2) <= delta
+        assert np.linalg.eigvalsh(e + delta * np.eye(n)).min() >= -1e-12 * delta
