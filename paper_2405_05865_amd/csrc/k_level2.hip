@@ -661,6 +661,12 @@ hipError_t l2_init(hipStream_t st, const L2Step& a) {
   return hipGetLastError();
 }
 
+// the right-hand-side kernel alone: r = rhs (zero for finished parent columns), y = 0
+hipError_t l2_rhs(hipStream_t st, const L2Step& a) {
+  hipLaunchKernelGGL(k_l2_init, dim3((unsigned)ublocks((int)a.s), (unsigned)a.k), dim3(NTU), 0, st, make_args(a));
+  return hipGetLastError();
+}
+
 hipError_t l2_reduce_to(hipStream_t st, const L2Step& a, double* out, const int32_t* skip) {
   hipLaunchKernelGGL(k_l2_reduce_to, dim3((unsigned)ublocks((int)a.s), (unsigned)a.k), dim3(NTU), 0, st, make_args(a),
                      out, skip);

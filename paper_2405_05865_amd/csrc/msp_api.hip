@@ -402,6 +402,12 @@ struct SolveCtx {
   double* gtmp = nullptr;                    // Gram split partials
   double *Htmp = nullptr, *Hscal = nullptr;  // level2_form 2: inverse scratch
   int32_t* Hstat = nullptr;
+  // explicit operators with k <= kL2xMaxK: one kernel per inner step through G = H Minv
+  bool use_x = false;
+  L2xArgs X{};
+  double* G2 = nullptr;                      // PSD: H2 M2^{-1}
+  double *G3a = nullptr, *G3b = nullptr;     // general: A~^T A~ M3a^{-1}, (A~^T A~ + lam~ I) M3b^{-1}
+  double* Hs = nullptr;                      // general: A~^T A~ + lam~ I
   int32_t* hf;
   int32_t* df;
   int last_inner = 4, last_l3a = 4, last_l3b = 4;
@@ -459,7 +465,27 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
       gtmp = w.take<double>(gemm_t_part_doubles(m, n, s));
     }
   }
+  // the one-kernel inner step (level2_form 1, block of at most kL2xMaxK columns)
+  const bool use_x = form == 1 && s >= kGemmMinK && s <= kL2xMaxS && k <= kL2xMaxK;
+  L2xArgs X{};
+  double *G2 = nullptr, *G3a = nullptr, *G3b = nullptr, *Hs = nullptr;
+  if (use_x) {
+    X = l2x_carve(w, s, k);
+    if (P->structure == MSP_SYM_PSD) {
+      G2 = w.take<double>(s * s);
+    } else {
+      G3a = w.take<double>(s * s);
+      G3b = w.take<double>(s * s);
+      Hs = w.take<double>(s * s);
+    }
+  }
   if (c) {
+    c->use_x = use_x;
+    c->X = X;
+    c->G2 = G2;
+    c->G3a = G3a;
+    c->G3b = G3b;
+    c->Hs = Hs;
     c->Htmp = Htmp;
     c->Hscal = Hscal;
     c->Hstat = Hstat;
@@ -627,6 +653,27 @@ msp_status run_l2(SolveCtx& c, const L2Step& a, const double* W, int slotid, int
   return MSP_OK;
 }
 
+// inner FCG with one kernel per step (explicit operator): the right-hand side is in
+// X.r[0] and X.y is zero. Issues the predicted count plus one step (a finished column
+// costs a launch that only carries its state), then pairs until every column is done.
+msp_status run_l2x(SolveCtx& c, const L2xArgs& x, int slotid, int* last, int64_t* counter) {
+  MSP_CHECK_HIP(l2x_start(c.st, x));
+  int issued = 0;
+  int chunk = std::max(1, *last + 1);
+  const int cap = x.max_iter;
+  while (true) {
+    for (int i = 0; i < chunk && issued < cap; ++i, ++issued)
+      MSP_CHECK_HIP(l2x_step(c.st, x, issued & 1, issued == 0 ? 1 : 0));
+    TRY(sync(c));
+    if (*slot(c, slotid) == 0 || issued >= cap) break;
+    chunk = 2;
+  }
+  const int taken = *slot(c, slotid + 1);
+  *counter += taken;
+  if (taken > 0) *last = taken;
+  return MSP_OK;
+}
+
 // out[:, j] = M v_j for an FP64 rows x cols row-major M (block product for k >= 8)
 msp_status dense_mv(SolveCtx& c, const double* M, int64_t rows, int64_t cols, const double* v, int64_t ldv,
                     double* out, int64_t ldo, const int32_t* skip) {
@@ -665,6 +712,15 @@ msp_status invert_h2(SolveCtx& c) {
   return MSP_OK;
 }
 
+// G = H Minv in row-major order for symmetric H and Minv: the block product Minv H
+// stores column j of Minv H, which is row j of (Minv H)^T = H Minv
+msp_status form_g(SolveCtx& c, const double* H, const double* Minv, double* G) {
+  int nb = 0;
+  MSP_CHECK_HIP(launch_gemm(c.st, Minv, MSP_F64, false, c.s, c.s, c.s, H, c.s, G, c.s, c.s, 0.0, false, nullptr,
+                            nullptr, &nb));
+  return MSP_OK;
+}
+
 msp_status build_explicit(SolveCtx& c) {
   if (c.form == 0) return MSP_OK;
   const msp_precond* P = c.P;
@@ -676,6 +732,7 @@ msp_status build_explicit(SolveCtx& c) {
     else
       MSP_CHECK_HIP(launch_gram_f32(c.st, (const float*)P->Y, n, s, P->ldy, c.H2, c.gtmp, sp));
     MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H2, P->lt, P->Wm, 0.0, c.H2));
+    if (c.use_x) TRY(form_g(c, c.H2, P->Minv, c.G2));
     return invert_h2(c);
   }
   int nb = 0;
@@ -688,6 +745,11 @@ msp_status build_explicit(SolveCtx& c) {
   MSP_CHECK_HIP(launch_gemm(c.st, c.Act, MSP_F64, false, s, m, m, c.Act, m, c.H3, s, s, 0.0, false, nullptr, nullptr,
                             &nb));
   MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H3, 0.0, nullptr, 0.0, c.H3));
+  if (c.use_x) {
+    MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H3, 0.0, nullptr, P->lt, c.Hs));
+    TRY(form_g(c, c.H3, P->Minv, c.G3a));
+    TRY(form_g(c, c.Hs, P->Minv2, c.G3b));
+  }
   if (c.form == 2) {  // the one-level variant needs the level-2 matrix itself
     MSP_CHECK_HIP(launch_gemm(c.st, c.B2t, MSP_F64, false, s, n, n, c.B2t, n, c.H2, s, s, 0.0, false, nullptr,
                               nullptr, &nb));
@@ -711,6 +773,22 @@ msp_status psd_solve_m1(SolveCtx& c, const double* r, double* z) {
     MSP_CHECK_HIP(
         launch_y_z(c.st, P->Y, P->y_t, n, s, P->ldy, c.L2.x, k, 1.0 / P->lt, r, n, -1.0 / P->lt, pdone, z, n));
     TRY(sync(c));  // the level-1 mirror is read by the caller after SolveM1
+    return MSP_OK;
+  }
+  if (c.use_x) {  // one kernel per step on H = C^T C + lam~ W through G2 = H M2^{-1}
+    L2xArgs x = c.X;
+    x.Minv = P->Minv;
+    x.G = c.G2;
+    x.y = c.L2.x;
+    x.tol = c.o->inner_tol;
+    x.max_iter = c.o->max_inner;
+    x.mirror = c.df + SLOT_L2;
+    x.parent_done = pdone;
+    a.r = x.r[0];
+    MSP_CHECK_HIP(l2_rhs(c.st, a));
+    TRY(run_l2x(c, x, SLOT_L2, &c.last_inner, &c.acc.inner_iters));
+    MSP_CHECK_HIP(
+        launch_y_z(c.st, P->Y, P->y_t, n, s, P->ldy, c.L2.x, k, 1.0 / P->lt, r, n, -1.0 / P->lt, pdone, z, n));
     return MSP_OK;
   }
   MSP_CHECK_HIP(l2_init(c.st, a));
@@ -767,6 +845,21 @@ msp_status gen_level3(SolveCtx& c, const double* rhs, double* out, double sigma,
                       const int32_t* parent_done, int* last) {
   L2Step a = l2step_for(c, c.L3, Minv, nullptr, 0.0, sigma, c.o->level3_tol, c.o->max_level3, SLOT_L3, parent_done);
   a.rhs = rhs;
+  if (c.use_x) {  // one kernel per step through G = (A~^T A~ + sigma I) Minv; y is out
+    L2xArgs x = c.X;
+    x.Minv = Minv;
+    x.G = (Minv == c.P->Minv2) ? c.G3b : c.G3a;
+    x.y = out;
+    x.tol = c.o->level3_tol;
+    x.max_iter = c.o->max_level3;
+    x.mirror = c.df + SLOT_L3;
+    x.parent_done = parent_done;
+    a.r = x.r[0];
+    a.y = out;
+    MSP_CHECK_HIP(l2_rhs(c.st, a));
+    TRY(run_l2x(c, x, SLOT_L3, last, &c.acc.level3_iters));
+    return MSP_OK;
+  }
   if (c.form == 1) {  // (A~^T A~ + sigma I) through the explicit A~^T A~
     a.nbC = 0;
     a.wscale = 1.0;

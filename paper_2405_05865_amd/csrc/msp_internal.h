@@ -241,10 +241,41 @@ hipError_t l2_op_matrix(hipStream_t st, const double* M, int64_t s, const double
                         double* wp, double* pqw);
 // right-hand side (after l2_op in rhs mode): y = 0, r = rhs, |rhs|, z = Minv r, p = z
 hipError_t l2_init(hipStream_t st, const L2Step& a);
+// the first kernel of l2_init alone: y = 0, r = rhs (0 where parent_done)
+hipError_t l2_rhs(hipStream_t st, const L2Step& a);
 // one step after l2_op(p): alpha, y/r update, convergence decision, z = Minv r, p = z + beta p
 hipError_t l2_step(hipStream_t st, const L2Step& a);
 // out[j][c] = sum of the group partials of the last rhs-mode l2_op (Y^T v), s x k
 hipError_t l2_reduce_to(hipStream_t st, const L2Step& a, double* out, const int32_t* skip);
+
+// ---------------------------------------------------------------------------------
+// Inner iterations with an explicit operator H and preconditioner Minv, one kernel per
+// step (k_l2x.hip). G = H Minv (row-major s x s). Vectors are [k][s]; arrays indexed
+// [2] alternate by step parity. The right-hand side goes into r[0] and y must be zero
+// before l2x_start; the solution accumulates in y.
+// ---------------------------------------------------------------------------------
+constexpr int kL2xMaxS = 2048;
+constexpr int kL2xMaxK = 16;
+struct L2xArgs {
+  int s, k;
+  const double* Minv;
+  const double* G;
+  double *r[2], *z[2], *g[2], *p[2], *u[2];
+  double* y;
+  double *rz[2], *al[2];
+  double* bn;
+  int32_t *done[2], *it[2];
+  double tol;
+  int max_iter;
+  int32_t* mirror;               // [2] host-mapped: active columns, largest iteration count
+  const int32_t* parent_done;    // columns already finished one level up (or null)
+};
+size_t l2x_doubles(int64_t s, int64_t k);
+L2xArgs l2x_carve(WsCarver& w, int64_t s, int64_t k);
+// |b|, the first decision, z_0 = Minv r_0 and g_0 = G r_0
+hipError_t l2x_start(hipStream_t st, const L2xArgs& a);
+// one step reading parity par; first = 1 for the step after l2x_start (par 0)
+hipError_t l2x_step(hipStream_t st, const L2xArgs& a, int par, int first);
 
 // ---------------------------------------------------------------------------------
 // The preconditioner handle
