@@ -31,19 +31,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def sweep_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2405_05865_amd", "csrc", "k_sweep.hip")
+def source_hash(fname: str) -> str:
+    p = os.path.join(ROOT, "paper_2405_05865_amd", "csrc", fname)
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def traffic_record(n: int):
+def traffic_record(n: int, sym: bool):
     """HBM bytes per sweep from the committed rocprofv3 counter summary, if it was
-    taken on the current sweep kernel source."""
-    p = os.path.join(ROOT, "profiles", f"gemv_f64_rbf_n{n}_traffic.json")
+    taken on the current source of the sweep kernel (k_symv.hip for the lower-triangle
+    sweep, k_sweep.hip for the full one)."""
+    name = f"symv_f64_rbf_n{n}_traffic.json" if sym else f"gemv_f64_rbf_n{n}_traffic.json"
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
-    if rec.get("k_sweep_sha256_16") != sweep_source_hash():
+    src = "k_symv.hip" if sym else "k_sweep.hip"
+    if rec.get("source_sha256_16", rec.get("k_sweep_sha256_16")) != source_hash(src):
         return None
     return rec.get("hbm_bytes_per_sweep")
 
@@ -93,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--inner-tol", type=float, default=1e-10)
+    ap.add_argument("--sym-sweep", type=int, default=1, choices=[0, 1],
+                    help="1: level-1 sweeps from the lower triangle of the symmetric A (n(n+1)/2 elements)")
     ap.add_argument("--level2-form", type=int, default=1, choices=[0, 1, 2],
                     help="inner operator through the sketch each step (0) or through C^T C + lam~ W formed "
                          "once (1, default; the same iteration), or the one-level variant with SolveM1 solved "
@@ -160,7 +165,7 @@ def main():
         rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
         P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi)
         X, info = msp.solve(P, A, bt, tol=w.tol, inner_tol=args.inner_tol, profile=profile,
-                            max_outer=args.max_outer, level2_form=args.level2_form)
+                            max_outer=args.max_outer, level2_form=args.level2_form, sym_sweep=args.sym_sweep)
         P.close()
         return X, info
 
@@ -181,10 +186,11 @@ def main():
     ms_per_step = 1e3 * el / args.steps
     value = args.steps / el
     sweep_ms = sum(i["sweep_ms"] for i in infos) / max(1, sum(i["timed_sweeps"] for i in infos))
-    bytes_per_sweep = float(w.n) * w.n * 8
+    sym = args.sym_sweep == 1
+    bytes_per_sweep = (0.5 * w.n * (w.n + 1) if sym else float(w.n) * w.n) * 8
     achieved = bytes_per_sweep / (sweep_ms * 1e-3) / 1e9
     ok = all(i["status"] == "MSP_OK" and i["rel_residual_max"] <= w.tol for i in infos)
-    traffic = traffic_record(w.n)
+    traffic = traffic_record(w.n, sym)
 
     line = {
         "metric": "RHS-solves/sec at rel. residual 1e-8 and HBM GB/s per A-sweep, n=32768",
@@ -201,7 +207,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"rbf_gp_n{w.n}_fp64_1rhs", "n": w.n, "s": w.s, "gamma": w.gamma, "phi": w.phi,
                    "lambda": w.lam, "lambda0": lam0, "tol": w.tol, "inner_tol": args.inner_tol, "nrhs": 1,
-                   "levels": 2, "level2_form": args.level2_form},
+                   "levels": 2, "level2_form": args.level2_form, "sym_sweep": args.sym_sweep},
         "hbm_gbs_per_sweep": round(achieved, 1),
         "outer_iters": infos[-1]["outer_iters"],
         "inner_iters": infos[-1]["inner_iters"],
@@ -209,7 +215,9 @@ def main():
         "converged": ok,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_gemv (A-sweep, FP64, 1 RHS)", "avg_sweep_ms": round(sweep_ms, 4),
+                     "kernel": ("k_symv_tiles + k_symv_reduce (lower-triangle A-sweep, FP64, 1 RHS)" if sym
+                                else "k_gemv (A-sweep, FP64, 1 RHS)"),
+                     "avg_sweep_ms": round(sweep_ms, 4),
                      "algorithmic_bytes_per_sweep": bytes_per_sweep},
     }
     if not args.no_cpu_baseline:

@@ -170,6 +170,10 @@ typedef struct {
                                  inverse of the level-2 matrix of form 1 (the standard Nystrom
                                  preconditioner of Section 2, no level-2/3 iteration; for
                                  comparison with the multi-level method). */
+  int32_t sym_sweep;       /* MSP_SYM_PSD, one right-hand side: sweep the level-1 operator from the
+                              lower triangle of A_lo only (n(n+1)/2 elements per sweep instead of
+                              n^2; A is symmetric by the problem statement). The FP64 confirmation
+                              and refinement residuals still use all of A_hi. Default 1. */
 } msp_solve_opts;
 
 typedef struct {

@@ -56,6 +56,7 @@ class SolveOpts(ctypes.Structure):
         ("max_refine", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("level2_form", ctypes.c_int32),
+        ("sym_sweep", ctypes.c_int32),
     ]
 
 

@@ -1,0 +1,259 @@
+// Symmetric A-sweep from the lower triangle: q = (A + lam I) p reads A[i][j] for j <= i
+// only, so a sweep streams n(n+1)/2 elements instead of n^2 (the level-1 operator of
+// Algorithm 1 is symmetric by the problem statement). Each element of the strict lower
+// triangle is used twice from one load: in the row dot (A p)_i and, mirrored, in the
+// column sum (A^T p)_j.
+//
+// The lower triangle is cut into 256 x 256 tiles (I, J), J <= I, one per block, numbered
+// b = I (I + 1) / 2 + J. A block has two wavefronts; wavefront w streams the 128-column
+// slab w of its tile. Inside a wavefront 8 lanes share a row (each reads 16-byte chunks,
+// 128 contiguous bytes per row and load) and the 8 lane groups take every eighth row, so
+// the row dots reduce over 8 lanes and the column sums over 8 lane groups. A tile writes
+// its row partials (ypart) and column partials (zpart); a second kernel adds, for each
+// row, the row partials of its tile row and the column partials of its tile column in a
+// fixed order, applies the shift and writes the <p, q> partials of the level-1 update.
+// Diagonal tiles mask the strict upper triangle (not loaded) and the diagonal from the
+// column sums.
+#include "msp_internal.h"
+
+#include <hip/hip_bf16.h>
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int T = 256;          // tile edge
+constexpr int NWV = 2;          // wavefronts per block
+constexpr int SLAB = T / NWV;   // columns per wavefront
+constexpr int LC = 8;           // lanes along a row
+constexpr int LR = WAVE / LC;   // lane groups along a column
+constexpr int NB = NWV * WAVE;  // threads per block
+constexpr int NR = 64;          // threads per block of the reduction
+
+typedef double sd2 __attribute__((ext_vector_type(2)));
+typedef float sf4 __attribute__((ext_vector_type(4)));
+typedef uint32_t su4 __attribute__((ext_vector_type(4)));
+
+template <class TA, class TC>
+struct Chunk;  // one 16-byte chunk of a row as VEC values of the arithmetic type
+template <>
+struct Chunk<double, double> {
+  static constexpr int VEC = 2;
+  static __device__ __forceinline__ void load(const double* p, double* o) {
+    const sd2 v = __builtin_nontemporal_load(reinterpret_cast<const sd2*>(p));
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+  static __device__ __forceinline__ double one(const double* p) { return *p; }
+};
+template <>
+struct Chunk<float, float> {
+  static constexpr int VEC = 4;
+  static __device__ __forceinline__ void load(const float* p, float* o) {
+    const sf4 v = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(p));
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+  static __device__ __forceinline__ float one(const float* p) { return *p; }
+};
+template <>
+struct Chunk<__hip_bfloat16, float> {
+  static constexpr int VEC = 8;
+  static __device__ __forceinline__ void load(const __hip_bfloat16* p, float* o) {
+    const su4 v = __builtin_nontemporal_load(reinterpret_cast<const su4*>(p));
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[2 * i] = __uint_as_float(w[i] << 16);
+      o[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
+    }
+  }
+  static __device__ __forceinline__ float one(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+};
+
+template <class TC>
+__device__ __forceinline__ TC xor_sum(TC v, int mask) {
+  return v + __shfl_xor(v, mask, WAVE);
+}
+
+__device__ __forceinline__ int tile_row(int b) {
+  int I = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(I + 1) * (I + 2) / 2 <= b) ++I;
+  while ((int64_t)I * (I + 1) / 2 > b) --I;
+  return I;
+}
+
+// rows of one tile for one wavefront. MASK: diagonal tile or a tile reaching past n
+// (per-element checks); otherwise every chunk is whole and below the diagonal.
+template <class TA, class TC, bool MASK>
+__device__ __forceinline__ void tile_rows(const TA* __restrict__ A, int64_t lda, int64_t n,
+                                          const double* __restrict__ x, int64_t r0, int64_t c0, bool diag,
+                                          TC (&xj)[SLAB / (LC * Chunk<TA, TC>::VEC)][Chunk<TA, TC>::VEC],
+                                          TC (&za)[SLAB / (LC * Chunk<TA, TC>::VEC)][Chunk<TA, TC>::VEC],
+                                          double* ys) {
+  constexpr int VEC = Chunk<TA, TC>::VEC;
+  constexpr int M = SLAB / (LC * VEC);
+  const int lane = threadIdx.x % WAVE;
+  const int kap = lane % LC, rho = lane / LC;
+#pragma unroll 2
+  for (int t = 0; t < T / LR; ++t) {
+    const int rl = rho + LR * t;
+    const int64_t gi = r0 + rl;
+    TC ysum = (TC)0;
+    if (!MASK || gi < n) {
+      const TC xi = (TC)x[gi];
+      const TA* arow = A + gi * lda;
+      TC a[M][VEC];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int64_t col = c0 + m * (LC * VEC) + kap * VEC;
+        if (!MASK) {
+          Chunk<TA, TC>::load(arow + col, a[m]);
+        } else if (col + VEC <= n && (!diag || col + VEC - 1 <= gi)) {
+          Chunk<TA, TC>::load(arow + col, a[m]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) {
+            const int64_t cc = col + v;
+            a[m][v] = (cc < n && (!diag || cc <= gi)) ? Chunk<TA, TC>::one(arow + cc) : (TC)0;
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          ysum = fma(a[m][v], xj[m][v], ysum);
+          if (MASK && diag) {
+            const int64_t cc = c0 + m * (LC * VEC) + kap * VEC + v;
+            za[m][v] = fma((cc < gi) ? a[m][v] : (TC)0, xi, za[m][v]);
+          } else {
+            za[m][v] = fma(a[m][v], xi, za[m][v]);
+          }
+        }
+    }
+    ysum = xor_sum(ysum, 1);
+    ysum = xor_sum(ysum, 2);
+    ysum = xor_sum(ysum, 4);
+    if (kap == 0) ys[rl] = (double)ysum;
+  }
+}
+
+template <class TA, class TC>
+__global__ void __launch_bounds__(NB) k_symv_tiles(const TA* __restrict__ A, int64_t lda, int64_t n,
+                                                  const double* __restrict__ x, const int32_t* __restrict__ skip,
+                                                  double* __restrict__ ypart, double* __restrict__ zpart) {
+  constexpr int VEC = Chunk<TA, TC>::VEC;
+  constexpr int M = SLAB / (LC * VEC);
+  if (skip && skip[0]) return;
+  __shared__ double ys[NWV][T];
+  const int b = blockIdx.x;
+  const int I = tile_row(b);
+  const int J = b - I * (I + 1) / 2;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int kap = lane % LC, rho = lane / LC;
+  const int64_t r0 = (int64_t)I * T, c0 = (int64_t)J * T + w * SLAB;
+  TC xj[M][VEC], za[M][VEC];
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const int64_t col = c0 + m * (LC * VEC) + kap * VEC + v;
+      xj[m][v] = (col < n) ? (TC)x[col] : (TC)0;
+      za[m][v] = (TC)0;
+    }
+  const bool diag = I == J;
+  const bool edge = r0 + T > n;  // the last tile row (and with it the last tile column)
+  if (diag || edge)
+    tile_rows<TA, TC, true>(A, lda, n, x, r0, c0, diag, xj, za, ys[w]);
+  else
+    tile_rows<TA, TC, false>(A, lda, n, x, r0, c0, diag, xj, za, ys[w]);
+  // column sums over the 8 lane groups; lane group 0 writes this slab's partials
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      TC s = za[m][v];
+      s = xor_sum(s, 8);
+      s = xor_sum(s, 16);
+      s = xor_sum(s, 32);
+      if (rho == 0) zpart[(int64_t)b * T + w * SLAB + m * (LC * VEC) + kap * VEC + v] = (double)s;
+    }
+  __syncthreads();
+  for (int r = threadIdx.x; r < T; r += NB) ypart[(int64_t)b * T + r] = ys[0][r] + ys[1][r];
+}
+
+// q_i = sum_{J <= I} ypart(I, J)_i + sum_{I' >= I} zpart(I', I)_i (+ lam p_i), and the
+// <p, q> partial of each block
+__global__ void __launch_bounds__(NR) k_symv_reduce(const double* __restrict__ ypart,
+                                                   const double* __restrict__ zpart, int64_t n, int N,
+                                                   const double* __restrict__ x, double lam, int diag,
+                                                   const int32_t* __restrict__ skip, double* __restrict__ y,
+                                                   double* __restrict__ dot_part) {
+  const int64_t r = (int64_t)blockIdx.x * NR + threadIdx.x;
+  const bool live = !(skip && skip[0]);
+  double prod = 0.0;
+  if (live && r < n) {
+    const int I = (int)(r / T), rl = (int)(r % T);
+    double acc = 0.0;
+    const int64_t rowb = (int64_t)I * (I + 1) / 2;
+    for (int J = 0; J <= I; ++J) acc += ypart[(rowb + J) * T + rl];
+    for (int I2 = I; I2 < N; ++I2) acc += zpart[((int64_t)I2 * (I2 + 1) / 2 + I) * T + rl];
+    const double xr = x[r];
+    const double q = acc + (diag ? lam * xr : 0.0);
+    y[r] = q;
+    prod = xr * q;
+  }
+  if (dot_part) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) prod += __shfl_xor(prod, off, WAVE);
+    if (threadIdx.x == 0) dot_part[blockIdx.x] = prod;
+  }
+}
+
+template <class TA, class TC>
+hipError_t symv_t(hipStream_t st, const TA* A, int64_t n, int64_t lda, const double* x, double* y, double lam,
+                  bool diag, const int32_t* skip, double* part, double* dot_part, int* nblocks) {
+  const int N = (int)((n + T - 1) / T);
+  const int64_t tiles = (int64_t)N * (N + 1) / 2;
+  double* ypart = part;
+  double* zpart = part + tiles * T;
+  hipLaunchKernelGGL((k_symv_tiles<TA, TC>), dim3((unsigned)tiles), dim3(NB), 0, st, A, lda, n, x, skip, ypart,
+                     zpart);
+  const unsigned rb = (unsigned)((n + NR - 1) / NR);
+  hipLaunchKernelGGL(k_symv_reduce, dim3(rb), dim3(NR), 0, st, ypart, zpart, n, N, x, lam, diag ? 1 : 0, skip, y,
+                     dot_part);
+  if (nblocks) *nblocks = (int)rb;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t symv_part_doubles(int64_t n) {
+  const int64_t N = (n + T - 1) / T;
+  return (size_t)(N * (N + 1)) * T + 64;  // row and column partials of every tile
+}
+
+bool symv_supported(const void* A, msp_dtype t, int64_t lda, int64_t k) {
+  if (k != 1 || ((uintptr_t)A % 16) != 0) return false;
+  const int64_t es = t == MSP_F64 ? 8 : (t == MSP_F32 ? 4 : 2);
+  return (lda * es) % 16 == 0;
+}
+
+hipError_t launch_symv(hipStream_t st, const void* A, msp_dtype a_t, int64_t n, int64_t lda, const double* x,
+                       double* y, double lam, bool diag_shift, const int32_t* skip, double* part, double* dot_part,
+                       int* nblocks) {
+  if (n < 1 || !symv_supported(A, a_t, lda, 1)) return hipErrorInvalidValue;
+  switch (a_t) {
+    case MSP_F64:
+      return symv_t<double, double>(st, (const double*)A, n, lda, x, y, lam, diag_shift, skip, part, dot_part,
+                                    nblocks);
+    case MSP_F32:
+      return symv_t<float, float>(st, (const float*)A, n, lda, x, y, lam, diag_shift, skip, part, dot_part, nblocks);
+    case MSP_BF16:
+      return symv_t<__hip_bfloat16, float>(st, (const __hip_bfloat16*)A, n, lda, x, y, lam, diag_shift, skip, part,
+                                           dot_part, nblocks);
+  }
+  return hipErrorInvalidValue;
+}

@@ -355,6 +355,7 @@ extern "C" void msp_solve_opts_default(msp_solve_opts* o) {
   o->max_refine = 30;
   o->profile = 0;
   o->level2_form = 1;
+  o->sym_sweep = 1;
 }
 
 
@@ -402,6 +403,7 @@ struct SolveCtx {
   double* gtmp = nullptr;                    // Gram split partials
   double *Htmp = nullptr, *Hscal = nullptr;  // level2_form 2: inverse scratch
   int32_t* Hstat = nullptr;
+  double* sympart = nullptr;                 // row/column partials of the lower-triangle sweep
   // explicit operators with k <= kL2xMaxK: one kernel per inner step through G = H Minv
   bool use_x = false;
   L2xArgs X{};
@@ -417,7 +419,7 @@ struct SolveCtx {
   size_t evused = 0;
 };
 
-size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, int form) {
+size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, int form, int sym) {
   const int64_t n = P->n, m = P->m, s = P->s;
   const int64_t mx = std::max(n, m);
   const int64_t nb_gemv = (mx + 3) / 4;  // upper bound of gemv blocks (R >= 4)
@@ -479,7 +481,11 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
       Hs = w.take<double>(s * s);
     }
   }
+  // the lower-triangle level-1 sweep (PSD, one right-hand side)
+  double* sympart = nullptr;
+  if (sym && P->structure == MSP_SYM_PSD && k == 1) sympart = w.take<double>(symv_part_doubles(n));
   if (c) {
+    c->sympart = sympart;
     c->use_x = use_x;
     c->X = X;
     c->G2 = G2;
@@ -568,7 +574,11 @@ msp_status sweep(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t 
   if (timed) TRY(ev_begin(c, &stop));
   hipError_t e;
   const double lam = (A == c.A_sw) ? c.lam_sw : c.lam;
-  if (c.k >= kGemmMinK)
+  // the level-1 operator of a symmetric A from its lower triangle
+  const bool sym = c.sympart && A == c.A_sw && !fp64 && rows == cols && symv_supported(A, t, c.lda, c.k);
+  if (sym)
+    e = launch_symv(c.st, A, t, rows, c.lda, X, Y, lam, diag, skip, c.sympart, parts ? c.gpart : nullptr, &nb);
+  else if (c.k >= kGemmMinK)
     e = launch_gemm(c.st, A, t, fp64 && t == MSP_F32, rows, cols, c.lda, X, ldx, Y, ldy, c.k, lam, diag, skip,
                     parts ? c.gpart : nullptr, &nb);
   else if (fp64 && t == MSP_F32)
@@ -581,7 +591,7 @@ msp_status sweep(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t 
   if (stop) MSP_CHECK_HIP(hipEventRecord(stop, c.st));
   c.nb_last = nb;
   c.acc.sweeps += 1;
-  c.acc.sweep_bytes += (double)rows * (double)cols * (double)dsize(t);
+  c.acc.sweep_bytes += (sym ? 0.5 * (double)rows * (double)(rows + 1) : (double)rows * (double)cols) * (double)dsize(t);
   return MSP_OK;
 }
 
@@ -1231,7 +1241,7 @@ msp_status make_ctx(SolveCtx& c, void* stream, const msp_precond* P, const void*
   c.df = P->dev_view_flags;
   c.evpool = (std::vector<hipEvent_t>*)P->events;
   WsCarver w(ws, ws_bytes);
-  solve_layout(w, P, k, &c, o->level2_form);
+  solve_layout(w, P, k, &c, o->level2_form, o->sym_sweep);
   if (!w.ok()) return msp_fail(MSP_ERR_WORKSPACE, "workspace overflow");
   // the explicit general operators need the block transposed product (s >= 8)
   if (P->structure == MSP_GENERAL && P->s < kGemmMinK) c.form = 0;
@@ -1251,7 +1261,7 @@ extern "C" msp_status msp_solve_workspace(const msp_precond* P, int64_t k, const
   const msp_solve_opts* o = opts ? opts : &dflt;
   REQUIRE(o->level2_form >= 0 && o->level2_form <= 2, "level2_form must be 0, 1 or 2");
   WsCarver w(nullptr, 0);
-  solve_layout(w, P, k, nullptr, o->level2_form);
+  solve_layout(w, P, k, nullptr, o->level2_form, o->sym_sweep);
   *bytes = w.off;
   return MSP_OK;
 }

@@ -95,6 +95,14 @@ int gemm_row_sets(int64_t rows);
 hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows, int64_t cols,
                        int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
                        bool diag, const int32_t* skip, double* dot_part, int* nblocks);
+// y = (A + lam I) x (lam only if diag_shift) for symmetric A from its lower triangle
+// (k_symv.hip), one vector; part: symv_part_doubles(n); dot_part: one <x, y> partial per
+// reduction block (count in *nblocks). Needs 16-byte aligned A and lda (symv_supported).
+size_t symv_part_doubles(int64_t n);
+bool symv_supported(const void* A, msp_dtype t, int64_t lda, int64_t k);
+hipError_t launch_symv(hipStream_t st, const void* A, msp_dtype a_t, int64_t n, int64_t lda, const double* x,
+                       double* y, double lam, bool diag_shift, const int32_t* skip, double* part, double* dot_part,
+                       int* nblocks);
 // Y[:, j] = A^T X[:, j] on the matrix cores for k >= kGemmMinK (same contract as
 // launch_gemv_t; part: gemv_t_part_doubles(rows, cols, k) doubles)
 size_t gemm_t_part_doubles(int64_t rows, int64_t cols, int64_t k);  // its split partials

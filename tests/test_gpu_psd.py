@@ -244,3 +244,59 @@ def test_block_rhs_low_precision_refined(dt):
     x = X.cpu().numpy()
     for j in range(k):
         assert dense.rel_residual_psd(a, x[j], bm[j], lam) <= 1e-10
+
+
+@pytest.mark.parametrize("n,pad", [(1000, 0), (1000, 2), (1000, 1), (513, 3), (256, 0)])
+def test_lower_triangle_sweep(n, pad):
+    # the level-1 sweep of a symmetric A from its lower triangle (256 x 256 tiles): ragged
+    # n, padded leading dimensions; an FP64 lda that is not a multiple of two elements is
+    # not 16-byte aligned and takes the full sweep instead. Both sweeps must give the
+    # dense solution, and the triangle sweep streams n(n+1)/2 elements per level-1 sweep.
+    say(f"case lower-triangle sweep n={n} pad={pad}")
+    s, lam, tol = 64, 1e-3, 1e-10
+    a, eigs, lam0 = _psd_case(n, 32, s, 3, lam)
+    b = W.gaussian(n, 3)
+    big = torch.zeros((n, n + pad), dtype=torch.float64, device=DEV)
+    big[:, :n] = torch.from_numpy(a).to(DEV)
+    if pad:
+        big[:, n:] = float("nan")  # padding must never be read
+    A = big[:, :n]
+    bt = torch.from_numpy(b).to(DEV)
+    rows, signs, Y = msp.sketch(A, s, 8, 41)
+    P = msp.Precond("psd", rows, signs, Y, lam, lam0, 4 * s, 8, 42)
+    xs = dense.solve_psd(a, b, lam)
+    res = {}
+    for sym in (1, 0):
+        X, info = msp.solve(P, A, bt, tol=tol, inner_tol=1e-12, sym_sweep=sym)
+        x = X.cpu().numpy()
+        assert info["status"] == "MSP_OK", info
+        assert dense.rel_residual_psd(a, x, b, lam) <= tol
+        assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
+        res[sym] = info
+    aligned = ((n + pad) * 8) % 16 == 0
+    full = res[1]["sweeps"] * float(n) * n * 8
+    if aligned:
+        assert res[1]["sweep_bytes"] < 0.6 * full
+    else:
+        assert res[1]["sweep_bytes"] == full
+    assert abs(res[1]["outer_iters"] - res[0]["outer_iters"]) <= 2
+    P.close()
+
+
+def test_lower_triangle_sweep_refined_f32():
+    # the FP32 A_lo sweep from its lower triangle inside FP64 refinement
+    say("case lower-triangle sweep f32 refinement n=1000")
+    n, s, lam, tol = 1000, 64, 1e-2, 1e-10
+    a, eigs, lam0 = _psd_case(n, 32, s, 4, lam)
+    b = W.gaussian(n, 4)
+    A = torch.from_numpy(a).to(DEV)
+    A32 = A.float()
+    rows, signs, Y = msp.sketch(A32, s, 8, 43)
+    P = msp.Precond("psd", rows, signs, Y, lam, lam0, 4 * s, 8, 44)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), A_lo=A32, refine=1, tol=tol, sym_sweep=1)
+    x = X.cpu().numpy()
+    assert info["status"] == "MSP_OK", info
+    assert dense.rel_residual_psd(a, x, b, lam) <= tol
+    xs = dense.solve_psd(a, b, lam)
+    assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
+    P.close()
