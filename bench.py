@@ -113,6 +113,8 @@ def main():
                          "the three-level solve of A x = b, n=65536, 8 right-hand sides")
     ap.add_argument("--count", type=int, default=None, help="batched: number of systems (default 256)")
     ap.add_argument("--lo", default="f32", choices=["f32", "bf16"], help="batched: sweep precision inside MSP")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="batched: skip the timed adjoint pass (forward plus adjoint under L = sum |X|^2)")
     ap.add_argument("--fp64-sample", type=int, default=4,
                     help="batched: systems timed with the plain FP64 single-RHS solve for comparison")
     args = ap.parse_args()
@@ -400,6 +402,33 @@ def bench_batched(args):
                   for q, d in zip(systems, infos))
     eff = a_bytes / (solve_t / args.steps) / 1e9
 
+    # forward plus adjoint under L = sum_i |X_i|_F^2 (G_i = 2 X_i): dB, dlambda (dA as factors)
+    adj = None
+    if not args.no_adjoint:
+        Ps = []
+        for q in systems:
+            rows, signs, Y = msp.sketch(q["A"], q["s"], w.gamma, q["seed"])
+            Ps.append(msp.Precond("psd", rows, signs, Y, w.lam, q["lam0"], q["phi"], w.phi_gamma, q["seed_phi"]))
+        sys_args = [(P, q["A"], q["A_lo"], q["B"]) for P, q in zip(Ps, systems)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Xs, finfos = msp.solve_batched(sys_args, tol=w.tol, refine=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        dBs, dls, _, binfos = msp.solve_batched_backward(sys_args, Xs, [2.0 * X for X in Xs], tol=w.tol, refine=1)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for P in Ps:
+            P.close()
+        bworst = max(d["rel_residual_max"] for d in binfos)
+        adj = {"forward_ms": round(1e3 * (t2 - t1), 2), "adjoint_ms": round(1e3 * (t3 - t2), 2),
+               "rhs_per_s_forward_plus_adjoint": round(count * nrhs / (t3 - t1), 2),
+               "adjoint_rel_residual_max": bworst,
+               "adjoint_converged": all(d["status"] == "MSP_OK" for d in binfos) and bworst <= w.tol,
+               "loss": "sum_i |X_i|_F^2", "outputs": "dB (n x 16 per system), dlambda per system; dA = -dB X^T as factors"}
+        log(f"[bench] forward {adj['forward_ms']:.0f} ms, adjoint {adj['adjoint_ms']:.0f} ms, "
+            f"adjoint residual max {bworst:.2e}")
+
     # the plain FP64 single-RHS form on a sample of the same systems, same accuracy
     fp64 = None
     if args.fp64_sample > 0:
@@ -448,6 +477,7 @@ def bench_batched(args):
         "rel_residual_max": worst,
         "converged": ok,
         "fp64_single_rhs": fp64,
+        "forward_plus_adjoint": adj,
     }
     print(json.dumps(line), flush=True)
 

@@ -244,6 +244,43 @@ msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_system* sys /
                              msp_solve_info* info /*host, nsys records*/);
 
 /* ---------------------------------------------------------------------------------
+ * msp_solve_batched_backward -- adjoints of many batched PSD solves X_i = (A_i + lam_i I)^{-1} B_i
+ * in one launch: for each system, given G_i = dL/dX_i,
+ *   dB_i = (A_i + lam_i I)^{-1} G_i           (A_i symmetric, so the transpose is itself;
+ *                                             solved by msp_solve_batched with the same handles)
+ *   dlambda_i = -sum_j <dB_ij, X_ij>
+ *   dA_i = -dB_i X_i^T                        (dense n x n, only when dA != NULL)
+ * Options, supported dtypes and processing as msp_solve_batched; X_i must be the forward
+ * solutions. The workspace query includes the batched solve's workspace.
+ *   sys      [host] nsys descriptors (matrices row-major, vectors contiguous, k each)
+ *   dlambda  [host] out, nsys values (may be NULL)
+ *   info     [host] out, nsys records of the adjoint solves (may be NULL)
+ * Returns MSP_OK when every adjoint solve met tol, else the first failure's status (the
+ * outputs of the other systems are still written). Synchronises the stream.
+ * ------------------------------------------------------------------------------ */
+typedef struct {
+  const msp_precond* P;  /* MSP_SYM_PSD handle of this system */
+  const void* A_hi;      /* n x n, ld lda, dtype hi_t */
+  const void* A_lo;      /* n x n, ld lda, dtype lo_t (may equal A_hi) */
+  int64_t lda;
+  const double* X;       /* forward solutions, vector j at X + j * ldx */
+  int64_t ldx;
+  const double* G;       /* dL/dX, vector j at G + j * ldg */
+  int64_t ldg;
+  double* dB;            /* out, vector j at dB + j * lddb */
+  int64_t lddb;
+  double* dA;            /* out (may be NULL): n x n, ld ldda */
+  int64_t ldda;
+} msp_system_grad;
+
+msp_status msp_solve_batched_backward_workspace(int32_t nsys, const msp_system_grad* sys /*host*/, int64_t k,
+                                                const msp_solve_opts* opts, size_t* bytes /*host*/);
+msp_status msp_solve_batched_backward(void* stream, int32_t nsys, const msp_system_grad* sys /*host*/,
+                                      msp_dtype hi_t, msp_dtype lo_t, int64_t k, const msp_solve_opts* opts,
+                                      void* ws, size_t ws_bytes, double* dlambda /*host, nsys*/,
+                                      msp_solve_info* info /*host, nsys records*/);
+
+/* ---------------------------------------------------------------------------------
  * msp_solve_backward -- adjoint of X = (A + lam I)^{-1} B for symmetric PSD A.
  *
  * Given G = dL/dX: dB = (A + lam I)^{-T} G = (A + lam I)^{-1} G (A symmetric), solved

@@ -18,7 +18,7 @@ import torch
 from . import _binding as B
 from ._binding import MspError, SolveInfo, SolveOpts  # noqa: F401
 
-__all__ = ["sketch", "Precond", "nystrom", "solve", "solve_batched", "solve_backward", "schatten", "effective_dimension",
+__all__ = ["sketch", "Precond", "nystrom", "solve", "solve_batched", "solve_batched_backward", "solve_backward", "schatten", "effective_dimension",
            "MSPSolve", "msp_solve", "library", "MspError", "SolveOpts"]
 
 _DT = {torch.float64: B.MSP_F64, torch.float32: B.MSP_F32, torch.bfloat16: B.MSP_BF16}
@@ -242,6 +242,58 @@ def solve_batched(systems, **opts):
     if code not in (0, 3, 4, 5):
         B.check(code)
     return xs, [infos[i].as_dict() for i in range(nsys)]
+
+
+def solve_batched_backward(systems, Xs, Gs, want_dA: bool = False, **opts):
+    """Adjoints of many batched PSD solves in one launch (msp_solve_batched_backward).
+
+    systems: the (P, A_hi, A_lo or None, ...) tuples of the forward solve (only the first
+    three entries are used); Xs the forward solutions and Gs = dL/dX, each (k, n).
+    Returns (list of dB (k, n), list of dlambda, list of dA (n, n) or None, list of info
+    dicts)."""
+    L = library()
+    o = _opts(**opts)
+    nsys = len(systems)
+    if nsys == 0 or len(Xs) != nsys or len(Gs) != nsys:
+        raise ValueError("need one X and one G per system")
+    arr = (B.SystemGrad * nsys)()
+    dbs, das, keep = [], [], []
+    k = hi_t = lo_t = dev = None
+    for i, sysd in enumerate(systems):
+        P, A_hi, A_lo = sysd[0], sysd[1], sysd[2]
+        if P.structure != "psd":
+            raise ValueError("batched adjoints take 'psd' handles")
+        A_lo = A_hi if A_lo is None else A_lo
+        _rowmajor(A_hi, "A_hi")
+        _rowmajor(A_lo, "A_lo")
+        if A_hi.stride(0) != A_lo.stride(0):
+            raise ValueError("A_hi and A_lo must share the leading dimension")
+        kx, ldx = _vectors(Xs[i], P.n, "X")
+        kg, ldg = _vectors(Gs[i], P.n, "G")
+        if kx != kg:
+            raise ValueError("X and G differ in the number of vectors")
+        if k is None:
+            k, hi_t, lo_t, dev = kx, _code(A_hi), _code(A_lo), Gs[i].device
+        elif kx != k or _code(A_hi) != hi_t or _code(A_lo) != lo_t:
+            raise ValueError("every system needs the same k and matrix dtypes")
+        dB = torch.empty((k, P.n), dtype=torch.float64, device=dev)
+        dA = torch.empty((P.n, P.n), dtype=torch.float64, device=dev) if want_dA else None
+        dbs.append(dB)
+        das.append(dA)
+        keep.append((A_hi, A_lo))
+        arr[i] = B.SystemGrad(P.handle.value, A_hi.data_ptr(), A_lo.data_ptr(), A_hi.stride(0), Xs[i].data_ptr(), ldx,
+                              Gs[i].data_ptr(), ldg, dB.data_ptr(), P.n,
+                              dA.data_ptr() if dA is not None else None, P.n)
+    need = B.size_out()
+    B.check(L.msp_solve_batched_backward_workspace(nsys, arr, k, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, dev)
+    infos = (SolveInfo * nsys)()
+    dl = (ctypes.c_double * nsys)()
+    code = L.msp_solve_batched_backward(_stream(dev), nsys, arr, hi_t, lo_t, k, ctypes.byref(o), ws.data_ptr(),
+                                        ws.numel(), dl, infos)
+    if code not in (0, 3, 4, 5):
+        B.check(code)
+    return dbs, [dl[i] for i in range(nsys)], das, [infos[i].as_dict() for i in range(nsys)]
 
 
 def solve_backward(P: Precond, A_hi, X, G, A_lo=None, want_dA: bool = False, **opts):

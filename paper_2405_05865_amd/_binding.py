@@ -30,7 +30,8 @@ STATUS = {
 EXPORTS = (
     "msp_sketch_workspace", "msp_sketch", "msp_nystrom_workspace", "msp_nystrom", "msp_precond_destroy",
     "msp_precond_set_lambda", "msp_precond_factors", "msp_solve_opts_default", "msp_solve_workspace", "msp_solve",
-    "msp_solve_batched_workspace", "msp_solve_batched", "msp_solve_backward",
+    "msp_solve_batched_workspace", "msp_solve_batched", "msp_solve_batched_backward_workspace",
+    "msp_solve_batched_backward", "msp_solve_backward",
     "msp_schatten_workspace", "msp_schatten", "msp_last_error", "msp_version",
 )
 
@@ -71,6 +72,24 @@ class System(ctypes.Structure):
         ("ldb", ctypes.c_int64),
         ("X", ctypes.c_void_p),
         ("ldx", ctypes.c_int64),
+    ]
+
+
+class SystemGrad(ctypes.Structure):
+    """msp_system_grad: one system of a batched adjoint."""
+    _fields_ = [
+        ("P", ctypes.c_void_p),
+        ("A_hi", ctypes.c_void_p),
+        ("A_lo", ctypes.c_void_p),
+        ("lda", ctypes.c_int64),
+        ("X", ctypes.c_void_p),
+        ("ldx", ctypes.c_int64),
+        ("G", ctypes.c_void_p),
+        ("ldg", ctypes.c_int64),
+        ("dB", ctypes.c_void_p),
+        ("lddb", ctypes.c_int64),
+        ("dA", ctypes.c_void_p),
+        ("ldda", ctypes.c_int64),
     ]
 
 
@@ -136,6 +155,11 @@ def load(path: str | None = None):
     L.msp_solve_batched_workspace.argtypes = [I32, ctypes.POINTER(System), I64, ctypes.POINTER(SolveOpts), SZ]
     L.msp_solve_batched.argtypes = [P, I32, ctypes.POINTER(System), ctypes.c_int, ctypes.c_int, I64,
                                     ctypes.POINTER(SolveOpts), P, ctypes.c_size_t, ctypes.POINTER(SolveInfo)]
+    L.msp_solve_batched_backward_workspace.argtypes = [I32, ctypes.POINTER(SystemGrad), I64,
+                                                       ctypes.POINTER(SolveOpts), SZ]
+    L.msp_solve_batched_backward.argtypes = [P, I32, ctypes.POINTER(SystemGrad), ctypes.c_int, ctypes.c_int, I64,
+                                             ctypes.POINTER(SolveOpts), P, ctypes.c_size_t, ctypes.POINTER(D),
+                                             ctypes.POINTER(SolveInfo)]
     L.msp_solve_backward.argtypes = [P, P, P, ctypes.c_int, P, ctypes.c_int, I64, P, I64, P, I64, I64, P, I64,
                                      ctypes.POINTER(D), P, I64, ctypes.POINTER(SolveOpts), P, ctypes.c_size_t,
                                      ctypes.POINTER(SolveInfo)]

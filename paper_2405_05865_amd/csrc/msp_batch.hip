@@ -246,3 +246,75 @@ extern "C" msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_sy
   }
   return ret;
 }
+
+// ------------------------------------------------------------------------------------
+// adjoints: the batched solve on G, then dlambda_i = -sum_j <dB_ij, X_ij> and dA_i
+// ------------------------------------------------------------------------------------
+namespace {
+
+std::vector<msp_system> adjoint_systems(int32_t nsys, const msp_system_grad* sys) {
+  std::vector<msp_system> fw(nsys);
+  for (int32_t i = 0; i < nsys; ++i) {
+    const msp_system_grad& g = sys[i];
+    fw[i] = msp_system{g.P, g.A_hi, g.A_lo, g.lda, g.G, g.ldg, g.dB, g.lddb};
+  }
+  return fw;
+}
+
+}  // namespace
+
+extern "C" msp_status msp_solve_batched_backward_workspace(int32_t nsys, const msp_system_grad* sys, int64_t k,
+                                                           const msp_solve_opts* opts, size_t* bytes) {
+  BREQUIRE(bytes && sys && nsys >= 1 && k >= 1, "invalid arguments");
+  for (int32_t i = 0; i < nsys; ++i) BREQUIRE(sys[i].P, "system %d: null handle", i);
+  const std::vector<msp_system> fw = adjoint_systems(nsys, sys);
+  size_t solve = 0;
+  msp_status s = msp_solve_batched_workspace(nsys, fw.data(), k, opts, &solve);
+  if (s != MSP_OK) return s;
+  *bytes = ((solve + 255) & ~size_t(255)) + (((size_t)nsys * k * sizeof(double) + 255) & ~size_t(255));
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_solve_batched_backward(void* stream, int32_t nsys, const msp_system_grad* sys,
+                                                 msp_dtype hi_t, msp_dtype lo_t, int64_t k,
+                                                 const msp_solve_opts* opts, void* ws, size_t ws_bytes,
+                                                 double* dlambda, msp_solve_info* info) {
+  BREQUIRE(nsys >= 1 && sys, "need at least one system");
+  for (int32_t i = 0; i < nsys; ++i) {
+    const msp_system_grad& g = sys[i];
+    BREQUIRE(g.P, "system %d: null handle", i);
+    BREQUIRE(g.X && g.G && g.dB, "system %d: null X, G or dB", i);
+    BREQUIRE(g.ldx >= g.P->n && g.ldg >= g.P->n && g.lddb >= g.P->n, "system %d: leading dimension < n", i);
+    BREQUIRE(!g.dA || g.ldda >= g.P->n, "system %d: ldda < n", i);
+  }
+  size_t need = 0;
+  msp_status s = msp_solve_batched_backward_workspace(nsys, sys, k, opts, &need);
+  if (s != MSP_OK) return s;
+  if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
+    return msp_fail(MSP_ERR_WORKSPACE, "batched adjoint workspace needs %zu bytes, 256-B aligned", need);
+  const std::vector<msp_system> fw = adjoint_systems(nsys, sys);
+  size_t solve = 0;
+  msp_solve_batched_workspace(nsys, fw.data(), k, opts, &solve);
+  solve = (solve + 255) & ~size_t(255);
+  // dB_i = (A_i + lam_i I)^{-1} G_i
+  const msp_status ret = msp_solve_batched(stream, nsys, fw.data(), hi_t, lo_t, k, opts, ws, solve, info);
+  if (ret != MSP_OK && ret != MSP_ERR_NO_CONVERGENCE) return ret;
+  hipStream_t st = (hipStream_t)stream;
+  double* dv = (double*)((char*)ws + solve);
+  for (int32_t i = 0; i < nsys; ++i) {
+    const msp_system_grad& g = sys[i];
+    const int64_t n = g.P->n;
+    MSP_CHECK_HIP(launch_coldots(st, n, k, g.dB, g.lddb, g.X, g.ldx, dv + (size_t)i * k));
+    if (g.dA) MSP_CHECK_HIP(launch_outer_neg(st, n, k, g.dB, g.lddb, g.X, g.ldx, g.dA, g.ldda));
+  }
+  std::vector<double> h((size_t)nsys * k);
+  MSP_CHECK_HIP(hipMemcpyAsync(h.data(), dv, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  MSP_CHECK_HIP(hipStreamSynchronize(st));
+  if (dlambda)
+    for (int32_t i = 0; i < nsys; ++i) {
+      double t = 0.0;
+      for (int64_t j = 0; j < k; ++j) t += h[(size_t)i * k + j];
+      dlambda[i] = -t;
+    }
+  return ret;
+}

@@ -32,6 +32,17 @@ def test_version_and_defaults():
     o = B.SolveOpts()
     L.msp_solve_opts_default(ctypes.byref(o))
     assert o.tol == 1e-8 and o.max_outer > 0 and o.inner_tol > 0
+    assert o.level2_form == 1 and o.sym_sweep == 1
+
+
+def test_batched_adjoint_rejects_empty_batch():
+    L = msp.library()
+    arr = (B.SystemGrad * 1)()
+    need = B.size_out()
+    assert B.STATUS[L.msp_solve_batched_backward_workspace(0, arr, 1, None, ctypes.byref(need))] == "MSP_ERR_INVALID_ARG"
+    dl = (ctypes.c_double * 1)()
+    code = L.msp_solve_batched_backward(None, 1, arr, 0, 0, 1, None, None, 0, dl, None)
+    assert B.STATUS[code] == "MSP_ERR_INVALID_ARG"  # null handle, rejected before any device work
 
 
 @pytest.mark.parametrize("m,n,s,gamma", [(0, 10, 4, 2), (10, 10, 0, 1), (10, 10, 4, 5), (10, 10, 11, 2),

@@ -136,3 +136,51 @@ def test_batched_iteration_cap_reports_no_convergence():
     Bv = torch.from_numpy(W.gaussian((2, 300), 800)).to(DEV)
     _, infos = msp.solve_batched([(P, A, None, Bv)], tol=1e-12, max_outer=2)
     assert infos[0]["status"] == "MSP_ERR_NO_CONVERGENCE"
+
+
+@pytest.mark.parametrize("lo", [None, torch.float32])
+def test_batched_adjoint_matches_dense_gradients(lo):
+    # forward plus adjoint of the batched GP solves under L = sum_i |X_i|_F^2: G_i = 2 X_i,
+    # dB_i = (A_i + lam I)^{-1} G_i, dlam_i = -sum_j <dB_ij, X_ij>, dA_i = -dB_i X_i^T
+    sizes = [300, 517, 128, 1024]
+    k = 4
+    say(f"case batched adjoint sizes={sizes} k={k} lo={lo}")
+    args, syss = [], []
+    for i, n in enumerate(sizes):
+        if lo is None:
+            sy = _system(n, 700 + i, lengthscale=0.6 + 0.3 * i)
+            A = _padded(sy["a"], torch.float64, pad=(i % 2) * 2)
+            A_lo, P = None, _build(sy, A)
+        else:
+            sy = _system(n, 700 + i, lengthscale=0.6 + 0.3 * i, dtype=np.float32)
+            A = _padded(sy["a"], torch.float32, pad=(i % 2) * 4)
+            A_lo, P = A, _build(sy, A, y_dtype=torch.float32)
+        Bm = W.gaussian((k, n), 700 + i)
+        syss.append((sy, Bm))
+        args.append((P, A, A_lo, torch.from_numpy(Bm).to(DEV)))
+    opts = dict(tol=1e-10, inner_tol=1e-10)
+    if lo is not None:
+        opts.update(refine=1)
+    Xs, infos = msp.solve_batched(args, **opts)
+    assert all(i["status"] == "MSP_OK" for i in infos), infos
+    Gs = [2.0 * X for X in Xs]
+    dBs, dlams, dAs, binfos = msp.solve_batched_backward(args, Xs, Gs, want_dA=True, **opts)
+    for (sy, Bm), X, dB, dl, dA, info in zip(syss, Xs, dBs, dlams, dAs, binfos):
+        say(sy["n"], info["status"], info["outer_iters"], info["rel_residual_max"], dl)
+        assert info["status"] == "MSP_OK", info
+        a, lam = sy["a64"], sy["lam"]
+        xd = np.stack([dense.solve_psd(a, Bm[j], lam) for j in range(k)])
+        gd = 2.0 * xd
+        dbd = np.stack([dense.solve_psd(a, gd[j], lam) for j in range(k)])
+        dbg = dB.cpu().numpy()
+        for j in range(k):
+            assert np.linalg.norm(dbg[j] - dbd[j]) <= 1e-7 * np.linalg.norm(dbd[j])
+        dld = -float(np.sum(dbd * xd))
+        assert abs(dl - dld) <= 1e-7 * abs(dld)
+        dad = -dbd.T @ xd
+        assert np.linalg.norm(dA.cpu().numpy() - dad) <= 1e-7 * np.linalg.norm(dad)
+        # dlam against a central difference of L(lam) = sum |(A + lam I)^{-1} B|^2
+        h = 1e-5 * lam
+        lp = sum(np.sum(dense.solve_psd(a, Bm[j], lam + h) ** 2) for j in range(k))
+        lm = sum(np.sum(dense.solve_psd(a, Bm[j], lam - h) ** 2) for j in range(k))
+        assert abs(dl - (lp - lm) / (2 * h)) <= 1e-5 * abs(dld)
