@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--inner-tol", type=float, default=1e-10)
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="right-hand sides of the RBF solve as one block (>= 8: matrix-core block sweeps)")
     ap.add_argument("--sym-sweep", type=int, default=1, choices=[0, 1],
                     help="1: level-1 sweeps from the lower triangle of the symmetric A (n(n+1)/2 elements)")
     ap.add_argument("--level2-form", type=int, default=1, choices=[0, 1, 2],
@@ -157,7 +159,8 @@ def main():
     t = time.time()
     pts = W.rbf_points(w.n, w.extra["dim"], w.config_id)
     a = W.rbf_matrix(pts)
-    b = W.gaussian(w.n, w.config_id)
+    K = max(1, args.nrhs)
+    b = W.gaussian(w.n, w.config_id) if K == 1 else W.gaussian((K, w.n), w.config_id)
     A = torch.from_numpy(a).to(dev)
     bt = torch.from_numpy(b).to(dev)
     torch.cuda.synchronize()
@@ -186,13 +189,13 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms_per_step = 1e3 * el / args.steps
-    value = args.steps / el
+    value = K * args.steps / el
     sweep_ms = sum(i["sweep_ms"] for i in infos) / max(1, sum(i["timed_sweeps"] for i in infos))
-    sym = args.sym_sweep == 1
+    sym = args.sym_sweep == 1 and K == 1
     bytes_per_sweep = (0.5 * w.n * (w.n + 1) if sym else float(w.n) * w.n) * 8
     achieved = bytes_per_sweep / (sweep_ms * 1e-3) / 1e9
     ok = all(i["status"] == "MSP_OK" and i["rel_residual_max"] <= w.tol for i in infos)
-    traffic = traffic_record(w.n, sym)
+    traffic = traffic_record(w.n, sym) if K == 1 else None
 
     line = {
         "metric": "RHS-solves/sec at rel. residual 1e-8 and HBM GB/s per A-sweep, n=32768",
@@ -207,8 +210,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"rbf_gp_n{w.n}_fp64_1rhs", "n": w.n, "s": w.s, "gamma": w.gamma, "phi": w.phi,
-                   "lambda": w.lam, "lambda0": lam0, "tol": w.tol, "inner_tol": args.inner_tol, "nrhs": 1,
+        "config": {"workload": f"rbf_gp_n{w.n}_fp64_{K}rhs", "n": w.n, "s": w.s, "gamma": w.gamma, "phi": w.phi,
+                   "lambda": w.lam, "lambda0": lam0, "tol": w.tol, "inner_tol": args.inner_tol, "nrhs": K,
                    "levels": 2, "level2_form": args.level2_form, "sym_sweep": args.sym_sweep},
         "hbm_gbs_per_sweep": round(achieved, 1),
         "outer_iters": infos[-1]["outer_iters"],
@@ -218,11 +221,18 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": ("k_symv_tiles + k_symv_reduce (lower-triangle A-sweep, FP64, 1 RHS)" if sym
-                                else "k_gemv (A-sweep, FP64, 1 RHS)"),
+                                else (f"k_gemm (block A-sweep, FP64 16x16x4 MFMA, {K} RHS)" if K >= 8
+                                      else f"k_gemv (A-sweep, FP64, {K} RHS)")),
                      "avg_sweep_ms": round(sweep_ms, 4),
                      "algorithmic_bytes_per_sweep": bytes_per_sweep},
     }
-    if not args.no_cpu_baseline:
+    if K > 1:
+        # the block sweep's arithmetic: 2 n^2 K flops per sweep against the FP64 matrix peak
+        flops = 2.0 * w.n * w.n * K
+        line["block_sweep"] = {"flops_per_sweep": flops, "achieved_tflops": round(flops / (sweep_ms * 1e-3) / 1e12, 2),
+                               "fp64_peak_tflops": 78.6,
+                               "arithmetic_intensity_flop_per_byte": round(flops / bytes_per_sweep, 3)}
+    if not args.no_cpu_baseline and K == 1:
         log("[bench] timing the CPU oracle (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(a, b, w, lam0, infos[-1]["outer_iters"], args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -235,12 +235,19 @@ __global__ void __launch_bounds__(NT) k_update(FcgState S, int64_t len, double* 
   if (!decide) return;
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) S.part[(int64_t)blockIdx.x * S.k + j] = t;
-  if (!last_block(S.counter)) return;
+}
+
+// the decision after k_update, in one block (a separate launch instead of a last-block
+// hand-off: a device-scope fence in every block of the update costs more than a launch):
+// |r| from the nblocks partials, breakdown, tolerance, iteration cap; mirror <- active
+__global__ void __launch_bounds__(NT) k_decide(FcgState S, int nblocks, double tol, int32_t max_iter,
+                                              int32_t* mirror, int check_brk) {
+  __shared__ double sh[NT / WAVE];
   for (int64_t jj = 0; jj < S.k; ++jj) {
-    if (S.done[jj] != 0) continue;
-    const double sum = strided_sum(S.part + jj, gridDim.x, S.k, sh);
+    if (S.done[jj] != 0) continue;  // uniform in the block
+    const double sum = strided_sum(S.part + jj, nblocks, S.k, sh);
     if (threadIdx.x != 0) continue;
-    if (pq_part && S.brk[jj]) {
+    if (check_brk && S.brk[jj]) {
       S.done[jj] = 2;
       continue;
     }
@@ -439,6 +446,8 @@ hipError_t fcg_update(hipStream_t st, FcgState S, int64_t len, double* x, double
                       int nparts) {
   hipLaunchKernelGGL(k_update, dim3(grid_x(len), (unsigned)S.k), dim3(NT), 0, st, S, len, x, r, r_old, p, q, tol,
                      max_iter, mirror, pq_part, nparts, 1);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(NT), 0, st, S, (int)grid_x(len), tol, max_iter, mirror,
+                     pq_part ? 1 : 0);
   return hipGetLastError();
 }
 

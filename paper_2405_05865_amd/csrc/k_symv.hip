@@ -5,15 +5,15 @@
 // column sum (A^T p)_j.
 //
 // The lower triangle is cut into 256 x 256 tiles (I, J), J <= I, one per block, numbered
-// b = I (I + 1) / 2 + J. A block has two wavefronts; wavefront w streams the 128-column
-// slab w of its tile. Inside a wavefront 8 lanes share a row (each reads 16-byte chunks,
-// 128 contiguous bytes per row and load) and the 8 lane groups take every eighth row, so
-// the row dots reduce over 8 lanes and the column sums over 8 lane groups. A tile writes
-// its row partials (ypart) and column partials (zpart); a second kernel adds, for each
-// row, the row partials of its tile row and the column partials of its tile column in a
-// fixed order, applies the shift and writes the <p, q> partials of the level-1 update.
-// Diagonal tiles mask the strict upper triangle (not loaded) and the diagonal from the
-// column sums.
+// b = I (I + 1) / 2 + J. A block has four wavefronts; wavefront w takes the tile rows
+// w + 4 (g + 4 t) (lane group g = lane / 16) and all 256 columns: 16 lanes share a row
+// (16-byte chunks, 256 contiguous bytes per row and load), so the row dots reduce over 16
+// lanes and the column sums over the 4 lane groups and then the 4 wavefronts (LDS). A
+// tile writes its row partials (ypart) and column partials (zpart); a second kernel adds,
+// for each row, the row partials of its tile row and the column partials of its tile
+// column in a fixed order, applies the shift and writes the <p, q> partials of the
+// level-1 update. Diagonal tiles mask the strict upper triangle (not loaded) and the
+// diagonal from the column sums.
 #include "msp_internal.h"
 
 #include <hip/hip_bf16.h>
@@ -22,9 +22,8 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr int T = 256;          // tile edge
-constexpr int NWV = 2;          // wavefronts per block
-constexpr int SLAB = T / NWV;   // columns per wavefront
-constexpr int LC = 8;           // lanes along a row
+constexpr int NWV = 4;          // wavefronts per block (rows interleaved)
+constexpr int LC = 16;          // lanes along a row
 constexpr int LR = WAVE / LC;   // lane groups along a column
 constexpr int NB = NWV * WAVE;  // threads per block
 constexpr int NR = 64;          // threads per block of the reduction
@@ -84,21 +83,22 @@ __device__ __forceinline__ int tile_row(int b) {
   return I;
 }
 
-// rows of one tile for one wavefront. MASK: diagonal tile or a tile reaching past n
-// (per-element checks); otherwise every chunk is whole and below the diagonal.
+// the rows of one tile that belong to this wavefront. MASK: diagonal tile or a tile
+// reaching past n (per-element checks); otherwise every chunk is whole and below the
+// diagonal.
 template <class TA, class TC, bool MASK>
 __device__ __forceinline__ void tile_rows(const TA* __restrict__ A, int64_t lda, int64_t n,
                                           const double* __restrict__ x, int64_t r0, int64_t c0, bool diag,
-                                          TC (&xj)[SLAB / (LC * Chunk<TA, TC>::VEC)][Chunk<TA, TC>::VEC],
-                                          TC (&za)[SLAB / (LC * Chunk<TA, TC>::VEC)][Chunk<TA, TC>::VEC],
+                                          TC (&xj)[T / (LC * Chunk<TA, TC>::VEC)][Chunk<TA, TC>::VEC],
+                                          TC (&za)[T / (LC * Chunk<TA, TC>::VEC)][Chunk<TA, TC>::VEC],
                                           double* ys) {
   constexpr int VEC = Chunk<TA, TC>::VEC;
-  constexpr int M = SLAB / (LC * VEC);
-  const int lane = threadIdx.x % WAVE;
+  constexpr int M = T / (LC * VEC);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int kap = lane % LC, rho = lane / LC;
 #pragma unroll 2
-  for (int t = 0; t < T / LR; ++t) {
-    const int rl = rho + LR * t;
+  for (int t = 0; t < T / (LR * NWV); ++t) {
+    const int rl = w + NWV * (rho + LR * t);
     const int64_t gi = r0 + rl;
     TC ysum = (TC)0;
     if (!MASK || gi < n) {
@@ -133,9 +133,8 @@ __device__ __forceinline__ void tile_rows(const TA* __restrict__ A, int64_t lda,
           }
         }
     }
-    ysum = xor_sum(ysum, 1);
-    ysum = xor_sum(ysum, 2);
-    ysum = xor_sum(ysum, 4);
+#pragma unroll
+    for (int o = 1; o < LC; o <<= 1) ysum = xor_sum(ysum, o);
     if (kap == 0) ys[rl] = (double)ysum;
   }
 }
@@ -145,15 +144,16 @@ __global__ void __launch_bounds__(NB) k_symv_tiles(const TA* __restrict__ A, int
                                                   const double* __restrict__ x, const int32_t* __restrict__ skip,
                                                   double* __restrict__ ypart, double* __restrict__ zpart) {
   constexpr int VEC = Chunk<TA, TC>::VEC;
-  constexpr int M = SLAB / (LC * VEC);
+  constexpr int M = T / (LC * VEC);
   if (skip && skip[0]) return;
-  __shared__ double ys[NWV][T];
+  __shared__ double ys[T];
+  __shared__ double zs[NWV][T];
   const int b = blockIdx.x;
   const int I = tile_row(b);
   const int J = b - I * (I + 1) / 2;
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int kap = lane % LC, rho = lane / LC;
-  const int64_t r0 = (int64_t)I * T, c0 = (int64_t)J * T + w * SLAB;
+  const int64_t r0 = (int64_t)I * T, c0 = (int64_t)J * T;
   TC xj[M][VEC], za[M][VEC];
 #pragma unroll
   for (int m = 0; m < M; ++m)
@@ -166,49 +166,63 @@ __global__ void __launch_bounds__(NB) k_symv_tiles(const TA* __restrict__ A, int
   const bool diag = I == J;
   const bool edge = r0 + T > n;  // the last tile row (and with it the last tile column)
   if (diag || edge)
-    tile_rows<TA, TC, true>(A, lda, n, x, r0, c0, diag, xj, za, ys[w]);
+    tile_rows<TA, TC, true>(A, lda, n, x, r0, c0, diag, xj, za, ys);
   else
-    tile_rows<TA, TC, false>(A, lda, n, x, r0, c0, diag, xj, za, ys[w]);
-  // column sums over the 8 lane groups; lane group 0 writes this slab's partials
+    tile_rows<TA, TC, false>(A, lda, n, x, r0, c0, diag, xj, za, ys);
+  // column sums over the 4 lane groups, then over the wavefronts in a fixed order
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       TC s = za[m][v];
-      s = xor_sum(s, 8);
       s = xor_sum(s, 16);
       s = xor_sum(s, 32);
-      if (rho == 0) zpart[(int64_t)b * T + w * SLAB + m * (LC * VEC) + kap * VEC + v] = (double)s;
+      if (rho == 0) zs[w][m * (LC * VEC) + kap * VEC + v] = (double)s;
     }
   __syncthreads();
-  for (int r = threadIdx.x; r < T; r += NB) ypart[(int64_t)b * T + r] = ys[0][r] + ys[1][r];
+  for (int r = threadIdx.x; r < T; r += NB) {
+    zpart[(int64_t)b * T + r] = (zs[0][r] + zs[1][r]) + (zs[2][r] + zs[3][r]);
+    ypart[(int64_t)b * T + r] = ys[r];
+  }
 }
 
 // q_i = sum_{J <= I} ypart(I, J)_i + sum_{I' >= I} zpart(I', I)_i (+ lam p_i), and the
-// <p, q> partial of each block
-__global__ void __launch_bounds__(NR) k_symv_reduce(const double* __restrict__ ypart,
-                                                   const double* __restrict__ zpart, int64_t n, int N,
-                                                   const double* __restrict__ x, double lam, int diag,
-                                                   const int32_t* __restrict__ skip, double* __restrict__ y,
-                                                   double* __restrict__ dot_part) {
-  const int64_t r = (int64_t)blockIdx.x * NR + threadIdx.x;
+// <p, q> partial of each block. A block takes 64 rows; wavefront q adds every fourth entry
+// of the row's list (row partials of its tile row, then column partials of its tile
+// column) and the four sums combine in a fixed order.
+__global__ void __launch_bounds__(4 * NR) k_symv_reduce(const double* __restrict__ ypart,
+                                                       const double* __restrict__ zpart, int64_t n, int N,
+                                                       const double* __restrict__ x, double lam, int diag,
+                                                       const int32_t* __restrict__ skip, double* __restrict__ y,
+                                                       double* __restrict__ dot_part) {
+  __shared__ double sh[4][NR];
+  const int lane = threadIdx.x % NR, q = threadIdx.x / NR;
+  const int64_t r = (int64_t)blockIdx.x * NR + lane;
   const bool live = !(skip && skip[0]);
-  double prod = 0.0;
+  double acc = 0.0;
   if (live && r < n) {
     const int I = (int)(r / T), rl = (int)(r % T);
-    double acc = 0.0;
     const int64_t rowb = (int64_t)I * (I + 1) / 2;
-    for (int J = 0; J <= I; ++J) acc += ypart[(rowb + J) * T + rl];
-    for (int I2 = I; I2 < N; ++I2) acc += zpart[((int64_t)I2 * (I2 + 1) / 2 + I) * T + rl];
+    for (int e = q; e <= N; e += 4) {
+      // e <= I: row partial of tile (I, e); e > I: column partial of tile (e - 1, I)
+      const int64_t tile = (e <= I) ? rowb + e : (int64_t)(e - 1) * e / 2 + I;
+      acc += ((e <= I) ? ypart : zpart)[tile * T + rl];
+    }
+  }
+  sh[q][lane] = acc;
+  __syncthreads();
+  if (q != 0) return;  // whole wavefronts leave; no barrier follows
+  double prod = 0.0;
+  if (live && r < n) {
     const double xr = x[r];
-    const double q = acc + (diag ? lam * xr : 0.0);
-    y[r] = q;
-    prod = xr * q;
+    const double v = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]) + (diag ? lam * xr : 0.0);
+    y[r] = v;
+    prod = xr * v;
   }
   if (dot_part) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) prod += __shfl_xor(prod, off, WAVE);
-    if (threadIdx.x == 0) dot_part[blockIdx.x] = prod;
+    if (lane == 0) dot_part[blockIdx.x] = prod;
   }
 }
 
@@ -222,7 +236,7 @@ hipError_t symv_t(hipStream_t st, const TA* A, int64_t n, int64_t lda, const dou
   hipLaunchKernelGGL((k_symv_tiles<TA, TC>), dim3((unsigned)tiles), dim3(NB), 0, st, A, lda, n, x, skip, ypart,
                      zpart);
   const unsigned rb = (unsigned)((n + NR - 1) / NR);
-  hipLaunchKernelGGL(k_symv_reduce, dim3(rb), dim3(NR), 0, st, ypart, zpart, n, N, x, lam, diag ? 1 : 0, skip, y,
+  hipLaunchKernelGGL(k_symv_reduce, dim3(rb), dim3(4 * NR), 0, st, ypart, zpart, n, N, x, lam, diag ? 1 : 0, skip, y,
                      dot_part);
   if (nblocks) *nblocks = (int)rb;
   return hipGetLastError();
