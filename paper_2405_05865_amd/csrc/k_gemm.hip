@@ -10,7 +10,11 @@
 // 16-byte load per row feeds VEC MFMAs. Neighbouring wavefronts take the column groups
 // of the same rows, so A is read from HBM about once per 4*16*KT columns and reused
 // from cache by the others. Per-column dot partials <X_j, Y_j> per row set feed the
-// level-1 step length (the same layout as the single-vector sweep).
+// level-1 step length (the same layout as the single-vector sweep). When the row sets
+// and column groups give too few wavefronts to keep HBM busy (a few right-hand sides),
+// the reduction range is split into segments: each wavefront writes its partial tile and
+// a second kernel adds the segments of every output in a fixed order, applies the shift
+// and writes the dot partials.
 #include "msp_internal.h"
 
 #include <hip/hip_bf16.h>
@@ -129,13 +133,15 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t 
                                              const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
                                              int64_t ldy, int k, double lam, int diag,
                                              const int32_t* __restrict__ skip, double* __restrict__ dot_part,
-                                             int nrs, int ncs) {
+                                             int nrs, int ncs, int nseg, int seg_cols, double* __restrict__ part) {
   using L = Ld<TA, TC>;
   constexpr int VEC = L::VEC;
   constexpr int STEP = 4 * VEC;
   const int wg = blockIdx.x * 4 + threadIdx.x / WAVE;  // global wavefront index
-  if (wg >= nrs * ncs) return;                           // whole wavefronts only
-  const int rs = wg / ncs, cs = wg % ncs;
+  if (wg >= nrs * ncs * nseg) return;                    // whole wavefronts only
+  // neighbouring wavefronts: column groups of the same rows and segment (A from cache)
+  const int cs = wg % ncs, sg = (wg / ncs) % nseg, rs = wg / (ncs * nseg);
+  const int cbeg = sg * seg_cols, cend = min(cols, cbeg + seg_cols);
   const int lane = threadIdx.x & (WAVE - 1), i = lane & 15, g = lane >> 4;
   const int r0 = rs * 16 * RT;
   const int gbase = cs * KT;  // first 16-column group of this wavefront
@@ -154,9 +160,10 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t 
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int q = 0; q < KT; ++q) acc[t][q] = typename V4<TC>::t{0, 0, 0, 0};
-  int c0 = 0;
+  int c0 = cbeg;
   if constexpr (ALN) {
-    for (; c0 + STEP <= cols; c0 += STEP) {
+#pragma unroll 2
+    for (; c0 + STEP <= cend; c0 += STEP) {
       TC a[RT][VEC], b[KT][VEC];
 #pragma unroll
       for (int t = 0; t < RT; ++t) L::vec(ap[t] + c0, a[t]);
@@ -170,11 +177,11 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t 
           for (int q = 0; q < KT; ++q) acc[t][q] = mfma(a[t][m], b[q][m], acc[t][q]);
     }
   }
-  for (; c0 < cols; c0 += STEP) {
+  for (; c0 < cend; c0 += STEP) {
     TC a[RT][VEC], b[KT][VEC];
 #pragma unroll
     for (int m = 0; m < VEC; ++m) {
-      const bool ok = c0 + VEC * g + m < cols;
+      const bool ok = c0 + VEC * g + m < cend;
 #pragma unroll
       for (int t = 0; t < RT; ++t) a[t][m] = ok ? L::one(ap[t] + c0 + m) : (TC)0;
 #pragma unroll
@@ -186,6 +193,21 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t 
       for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int q = 0; q < KT; ++q) acc[t][q] = mfma(a[t][m], b[q][m], acc[t][q]);
+  }
+  if (nseg > 1) {  // partial tile of this segment: part[sg][j][row]
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+      const int j = 16 * (gbase + q) + i;
+      if (j >= k || (skip && skip[j])) continue;
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = r0 + 16 * t + out_row<TC>(g, e);
+          if (row < rows) part[((int64_t)sg * k + j) * rows + row] = (double)acc[t][q][e];
+        }
+    }
+    return;
   }
   // epilogue: Y = acc (+ lam X), per-column dot partials over this row set
 #pragma unroll
@@ -216,23 +238,62 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t 
   }
 }
 
+// Y[:, j] = sum over the segments (fixed order) (+ lam X[:, j]); dot partials per 64 rows
+__global__ void __launch_bounds__(WAVE) k_gemm_sum(const double* __restrict__ part, int nseg, int rows, int k,
+                                                  const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
+                                                  int64_t ldy, double lam, int diag, const int32_t* __restrict__ skip,
+                                                  double* __restrict__ dot_part) {
+  const int row = blockIdx.x * WAVE + threadIdx.x, j = blockIdx.y;
+  double dp = 0.0;
+  if (!(skip && skip[j]) && row < rows) {
+    double acc = 0.0;
+    for (int s = 0; s < nseg; ++s) acc += part[((int64_t)s * k + j) * rows + row];
+    const double xr = (diag || dot_part) ? X[(int64_t)j * ldx + row] : 0.0;
+    const double y = acc + (diag ? lam * xr : 0.0);
+    Y[(int64_t)j * ldy + row] = y;
+    dp = xr * y;
+  }
+  if (dot_part) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dp += __shfl_xor(dp, off, WAVE);
+    if (threadIdx.x == 0) dot_part[(int64_t)blockIdx.x * k + j] = dp;
+  }
+}
+
+// segments of the reduction range: double until the launch has about 32 wavefronts per
+// CU, each segment keeps >= 1024 columns and the partials fit the scratch
+int gemm_segments(int64_t rows, int64_t cols, int k, int64_t waves, size_t scratch_doubles) {
+  int nseg = 1;
+  while (waves * nseg < 8192 && nseg < 64 && cols / (2 * nseg) >= 1024 &&
+         (size_t)(2 * nseg) * (size_t)k * (size_t)rows <= scratch_doubles)
+    nseg *= 2;
+  return nseg;
+}
+
 template <class TA, class TC, int RT, int KT>
 hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X,
                   int64_t ldx, double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip,
-                  double* dot_part, int* nblocks) {
+                  double* dot_part, int* nblocks, double* scratch, size_t scratch_doubles) {
+  static_assert(16 * RT == WAVE, "the segment sum takes 64-row sets");
   const int nrs = (int)((rows + 16 * RT - 1) / (16 * RT));
   const int ngroups = (k + 15) / 16;
   const int ncs = (ngroups + KT - 1) / KT;
-  const int64_t waves = (int64_t)nrs * ncs;
+  const int nseg = scratch ? gemm_segments(rows, cols, k, (int64_t)nrs * ncs, scratch_doubles) : 1;
+  constexpr int STEP = 4 * Ld<TA, TC>::VEC;
+  const int seg_cols = (int)(((cols + nseg - 1) / nseg + STEP - 1) / STEP * STEP);
+  const int64_t waves = (int64_t)nrs * ncs * nseg;
   const unsigned blocks = (unsigned)((waves + 3) / 4);
   const bool aln = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(TA)) % 16 == 0) && ((uintptr_t)X % 16 == 0) &&
                    (ldx % 2 == 0);
   if (aln)
     hipLaunchKernelGGL((k_gemm<TA, TC, RT, KT, true>), dim3(blocks), dim3(256), 0, st, A, lda, (int)rows, (int)cols,
-                       X, ldx, Y, ldy, k, lam, diag ? 1 : 0, skip, dot_part, nrs, ncs);
+                       X, ldx, Y, ldy, k, lam, diag ? 1 : 0, skip, dot_part, nrs, ncs, nseg, seg_cols, scratch);
   else
     hipLaunchKernelGGL((k_gemm<TA, TC, RT, KT, false>), dim3(blocks), dim3(256), 0, st, A, lda, (int)rows, (int)cols,
-                       X, ldx, Y, ldy, k, lam, diag ? 1 : 0, skip, dot_part, nrs, ncs);
+                       X, ldx, Y, ldy, k, lam, diag ? 1 : 0, skip, dot_part, nrs, ncs, nseg, seg_cols, scratch);
+  if (nseg > 1)
+    hipLaunchKernelGGL(k_gemm_sum, dim3((unsigned)nrs, (unsigned)k), dim3(WAVE), 0, st, scratch, nseg, (int)rows, k, X,
+                       ldx, Y, ldy, lam, diag ? 1 : 0, skip, dot_part);
   if (nblocks) *nblocks = nrs;
   return hipGetLastError();
 }
@@ -242,11 +303,15 @@ hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64
 template <class TA, class TC>
 hipError_t gemm_k(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X, int64_t ldx,
                   double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip, double* dot_part,
-                  int* nblocks) {
-  if (k <= 16) return gemm_t<TA, TC, 4, 1>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
+                  int* nblocks, double* scratch, size_t scratch_doubles) {
+  if (k <= 16)
+    return gemm_t<TA, TC, 4, 1>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
+                                scratch_doubles);
   if (sizeof(TC) == 8 || k <= 32)
-    return gemm_t<TA, TC, 4, 2>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
-  return gemm_t<TA, TC, 4, 4>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks);
+    return gemm_t<TA, TC, 4, 2>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
+                                scratch_doubles);
+  return gemm_t<TA, TC, 4, 4>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
+                              scratch_doubles);
 }
 
 // Transposed block product Y[:, j] = A^T X[:, j] (A rows x cols row-major; the
@@ -396,23 +461,33 @@ hipError_t launch_gemm_t(hipStream_t st, const void* A, msp_dtype a_t, int64_t r
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows, int64_t cols,
-                       int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
-                       bool diag, const int32_t* skip, double* dot_part, int* nblocks) {
+hipError_t launch_gemm_split(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows,
+                             int64_t cols, int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
+                             double lam, bool diag, const int32_t* skip, double* dot_part, int* nblocks,
+                             double* scratch, size_t scratch_doubles) {
   const int kk = (int)k;
   switch (a_t) {
     case MSP_F64:
       return gemm_k<double, double>(st, (const double*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam, diag, skip,
-                                    dot_part, nblocks);
+                                    dot_part, nblocks, scratch, scratch_doubles);
     case MSP_F32:
       if (fp64_arith)
         return gemm_k<float, double>(st, (const float*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam, diag, skip,
-                                     dot_part, nblocks);
+                                     dot_part, nblocks, scratch, scratch_doubles);
       return gemm_k<float, float>(st, (const float*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam, diag, skip, dot_part,
-                                  nblocks);
+                                  nblocks, scratch, scratch_doubles);
     case MSP_BF16:
       return gemm_k<__hip_bfloat16, float>(st, (const __hip_bfloat16*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam,
-                                           diag, skip, dot_part, nblocks);
+                                           diag, skip, dot_part, nblocks, scratch, scratch_doubles);
   }
   return hipErrorInvalidValue;
 }
+
+hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows, int64_t cols,
+                       int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
+                       bool diag, const int32_t* skip, double* dot_part, int* nblocks) {
+  return launch_gemm_split(st, A, a_t, fp64_arith, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part,
+                           nblocks, nullptr, 0);
+}
+
+size_t gemm_split_doubles(int64_t rows, int64_t k) { return (size_t)16 * rows * k + 64; }

@@ -404,6 +404,8 @@ struct SolveCtx {
   double *Htmp = nullptr, *Hscal = nullptr;  // level2_form 2: inverse scratch
   int32_t* Hstat = nullptr;
   double* sympart = nullptr;                 // row/column partials of the lower-triangle sweep
+  double* gemmpart = nullptr;                // segment partials of the level-1 block sweep
+  size_t gemmpart_n = 0;
   // explicit operators with k <= kL2xMaxK: one kernel per inner step through G = H Minv
   bool use_x = false;
   L2xArgs X{};
@@ -484,8 +486,13 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
   // the lower-triangle level-1 sweep (PSD, one right-hand side)
   double* sympart = nullptr;
   if (sym && P->structure == MSP_SYM_PSD && k == 1) sympart = w.take<double>(symv_part_doubles(n));
+  double* gemmpart = nullptr;
+  const size_t gemmpart_n = k >= kGemmMinK ? gemm_split_doubles(mx, k) : 0;
+  if (gemmpart_n) gemmpart = w.take<double>(gemmpart_n);
   if (c) {
     c->sympart = sympart;
+    c->gemmpart = gemmpart;
+    c->gemmpart_n = gemmpart_n;
     c->use_x = use_x;
     c->X = X;
     c->G2 = G2;
@@ -579,8 +586,8 @@ msp_status sweep(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t 
   if (sym)
     e = launch_symv(c.st, A, t, rows, c.lda, X, Y, lam, diag, skip, c.sympart, parts ? c.gpart : nullptr, &nb);
   else if (c.k >= kGemmMinK)
-    e = launch_gemm(c.st, A, t, fp64 && t == MSP_F32, rows, cols, c.lda, X, ldx, Y, ldy, c.k, lam, diag, skip,
-                    parts ? c.gpart : nullptr, &nb);
+    e = launch_gemm_split(c.st, A, t, fp64 && t == MSP_F32, rows, cols, c.lda, X, ldx, Y, ldy, c.k, lam, diag, skip,
+                          parts ? c.gpart : nullptr, &nb, c.gemmpart, c.gemmpart_n);
   else if (fp64 && t == MSP_F32)
     e = launch_gemv_f32_as_f64(c.st, (const float*)A, rows, cols, c.lda, X, ldx, Y, ldy, c.k, lam, diag, skip,
                                parts ? c.gpart : nullptr, &nb);

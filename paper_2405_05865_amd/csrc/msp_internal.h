@@ -103,6 +103,14 @@ bool symv_supported(const void* A, msp_dtype t, int64_t lda, int64_t k);
 hipError_t launch_symv(hipStream_t st, const void* A, msp_dtype a_t, int64_t n, int64_t lda, const double* x,
                        double* y, double lam, bool diag_shift, const int32_t* skip, double* part, double* dot_part,
                        int* nblocks);
+// the same with a scratch of segment partials (k_gemm splits the reduction range when the
+// launch would have too few wavefronts; gemm_split_doubles(rows, k) allows up to 16
+// segments)
+size_t gemm_split_doubles(int64_t rows, int64_t k);
+hipError_t launch_gemm_split(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows,
+                             int64_t cols, int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
+                             double lam, bool diag, const int32_t* skip, double* dot_part, int* nblocks,
+                             double* scratch, size_t scratch_doubles);
 // Y[:, j] = A^T X[:, j] on the matrix cores for k >= kGemmMinK (same contract as
 // launch_gemv_t; part: gemv_t_part_doubles(rows, cols, k) doubles)
 size_t gemm_t_part_doubles(int64_t rows, int64_t cols, int64_t k);  // its split partials
