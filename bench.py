@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-10)
     ap.add_argument("--nrhs", type=int, default=1,
                     help="right-hand sides of the RBF solve as one block (>= 8: matrix-core block sweeps)")
+    ap.add_argument("--use-graph", type=int, default=0, choices=[0, 1],
+                    help="1: replay the predicted inner steps of each SolveM1 call as one HIP graph")
     ap.add_argument("--sym-sweep", type=int, default=1, choices=[0, 1],
                     help="1: level-1 sweeps from the lower triangle of the symmetric A (n(n+1)/2 elements)")
     ap.add_argument("--level2-form", type=int, default=1, choices=[0, 1, 2],
@@ -170,7 +172,8 @@ def main():
         rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
         P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi)
         X, info = msp.solve(P, A, bt, tol=w.tol, inner_tol=args.inner_tol, profile=profile,
-                            max_outer=args.max_outer, level2_form=args.level2_form, sym_sweep=args.sym_sweep)
+                            max_outer=args.max_outer, level2_form=args.level2_form, sym_sweep=args.sym_sweep,
+                            use_graph=args.use_graph)
         P.close()
         return X, info
 
@@ -212,7 +215,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"rbf_gp_n{w.n}_fp64_{K}rhs", "n": w.n, "s": w.s, "gamma": w.gamma, "phi": w.phi,
                    "lambda": w.lam, "lambda0": lam0, "tol": w.tol, "inner_tol": args.inner_tol, "nrhs": K,
-                   "levels": 2, "level2_form": args.level2_form, "sym_sweep": args.sym_sweep},
+                   "levels": 2, "level2_form": args.level2_form, "sym_sweep": args.sym_sweep,
+                   "use_graph": args.use_graph},
         "hbm_gbs_per_sweep": round(achieved, 1),
         "outer_iters": infos[-1]["outer_iters"],
         "inner_iters": infos[-1]["inner_iters"],

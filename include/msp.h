@@ -174,6 +174,10 @@ typedef struct {
                               lower triangle of A_lo only (n(n+1)/2 elements per sweep instead of
                               n^2; A is symmetric by the problem statement). The FP64 confirmation
                               and refinement residuals still use all of A_hi. Default 1. */
+  int32_t use_graph;       /* level2_form 1 with k <= 16: issue the predicted inner steps of every
+                              SolveM1 call as one HIP graph (captured once per solve and chunk
+                              length, replayed on the solve's stream). Same kernels and results
+                              as the eager launches. Default 0. */
 } msp_solve_opts;
 
 typedef struct {

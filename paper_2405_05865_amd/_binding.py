@@ -58,6 +58,7 @@ class SolveOpts(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("level2_form", ctypes.c_int32),
         ("sym_sweep", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
     ]
 
 

@@ -6,8 +6,9 @@
 // Work unit: one wavefront computes a 16*RT-row x 16*KT-column output tile with
 // 16x16x4 MFMA (F32 arithmetic for F32/BF16 storage, F64 for F64 storage and for the
 // FP64-on-F32 residual form). Lane l supplies row (l % 16) of each 16-row tile and the
-// reduction slice [c0 + VEC (l / 16), +VEC) of each step, for both operands, so one
-// 16-byte load per row feeds VEC MFMAs. Neighbouring wavefronts take the column groups
+// reduction slice [c0 + E (l / 16), +E) of each step, for both operands (E = two 16-byte
+// chunks), so the four lanes of a row read 128 contiguous bytes (a whole cache line) per
+// step and one lane's loads feed E MFMAs. Neighbouring wavefronts take the column groups
 // of the same rows, so A is read from HBM about once per 4*16*KT columns and reused
 // from cache by the others. Per-column dot partials <X_j, Y_j> per row set feed the
 // level-1 step length (the same layout as the single-vector sweep). When the row sets
@@ -136,7 +137,9 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t 
                                              int nrs, int ncs, int nseg, int seg_cols, double* __restrict__ part) {
   using L = Ld<TA, TC>;
   constexpr int VEC = L::VEC;
-  constexpr int STEP = 4 * VEC;
+  constexpr int NCH = 2;          // 16-byte chunks per lane and step
+  constexpr int E = NCH * VEC;    // reduction elements per lane and step
+  constexpr int STEP = 4 * E;
   const int wg = blockIdx.x * 4 + threadIdx.x / WAVE;  // global wavefront index
   if (wg >= nrs * ncs * nseg) return;                    // whole wavefronts only
   // neighbouring wavefronts: column groups of the same rows and segment (A from cache)
@@ -148,12 +151,12 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t 
   // X is read in aligned pairs only when the vectors' rows are 16-byte aligned
   const TA* ap[RT];
 #pragma unroll
-  for (int t = 0; t < RT; ++t) ap[t] = A + (int64_t)min(r0 + 16 * t + i, rows - 1) * lda + VEC * g;
+  for (int t = 0; t < RT; ++t) ap[t] = A + (int64_t)min(r0 + 16 * t + i, rows - 1) * lda + E * g;
   const double* bp[KT];
 #pragma unroll
   for (int q = 0; q < KT; ++q) {
     const int j = min(16 * (gbase + q) + i, k - 1);
-    bp[q] = X + (int64_t)j * ldx + VEC * g;
+    bp[q] = X + (int64_t)j * ldx + E * g;
   }
   typename V4<TC>::t acc[RT][KT];
 #pragma unroll
@@ -164,13 +167,15 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t 
   if constexpr (ALN) {
 #pragma unroll 2
     for (; c0 + STEP <= cend; c0 += STEP) {
-      TC a[RT][VEC], b[KT][VEC];
+      TC a[RT][E], b[KT][E];
 #pragma unroll
-      for (int t = 0; t < RT; ++t) L::vec(ap[t] + c0, a[t]);
+      for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int q = 0; q < KT; ++q) ld_x<TC, VEC, true>(bp[q] + c0, b[q]);
+        for (int h = 0; h < NCH; ++h) L::vec(ap[t] + c0 + h * VEC, a[t] + h * VEC);
 #pragma unroll
-      for (int m = 0; m < VEC; ++m)
+      for (int q = 0; q < KT; ++q) ld_x<TC, E, true>(bp[q] + c0, b[q]);
+#pragma unroll
+      for (int m = 0; m < E; ++m)
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -178,17 +183,17 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, int64_t 
     }
   }
   for (; c0 < cend; c0 += STEP) {
-    TC a[RT][VEC], b[KT][VEC];
+    TC a[RT][E], b[KT][E];
 #pragma unroll
-    for (int m = 0; m < VEC; ++m) {
-      const bool ok = c0 + VEC * g + m < cend;
+    for (int m = 0; m < E; ++m) {
+      const bool ok = c0 + E * g + m < cend;
 #pragma unroll
       for (int t = 0; t < RT; ++t) a[t][m] = ok ? L::one(ap[t] + c0 + m) : (TC)0;
 #pragma unroll
       for (int q = 0; q < KT; ++q) b[q][m] = ok ? (TC)bp[q][c0 + m] : (TC)0;
     }
 #pragma unroll
-    for (int m = 0; m < VEC; ++m)
+    for (int m = 0; m < E; ++m)
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -279,7 +284,7 @@ hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64
   const int ngroups = (k + 15) / 16;
   const int ncs = (ngroups + KT - 1) / KT;
   const int nseg = scratch ? gemm_segments(rows, cols, k, (int64_t)nrs * ncs, scratch_doubles) : 1;
-  constexpr int STEP = 4 * Ld<TA, TC>::VEC;
+  constexpr int STEP = 4 * 2 * Ld<TA, TC>::VEC;  // four lane groups x two 16-byte chunks
   const int seg_cols = (int)(((cols + nseg - 1) / nseg + STEP - 1) / STEP * STEP);
   const int64_t waves = (int64_t)nrs * ncs * nseg;
   const unsigned blocks = (unsigned)((waves + 3) / 4);

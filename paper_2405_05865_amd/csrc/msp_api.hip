@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "msp_internal.h"
@@ -356,6 +358,7 @@ extern "C" void msp_solve_opts_default(msp_solve_opts* o) {
   o->profile = 0;
   o->level2_form = 1;
   o->sym_sweep = 1;
+  o->use_graph = 0;
 }
 
 
@@ -380,6 +383,19 @@ Level carve_level(WsCarver& w, int64_t len, int64_t k, int64_t state_len = 0) {
   L.S = carve_fcg_state(w, std::max(len, state_len), k);
   return L;
 }
+
+// instantiated graphs of inner-step chunks, per (chunk length, operator, output): captured
+// once on a private stream and replayed on the solve's stream for every SolveM1 call
+struct StepGraphs {
+  hipStream_t st = nullptr;   // the solve's stream (synchronised before destruction)
+  hipStream_t cap = nullptr;  // capture stream
+  std::map<std::tuple<int, const void*, const void*, const void*>, hipGraphExec_t> exec;
+  ~StepGraphs() {
+    if (!exec.empty() && st) (void)hipStreamSynchronize(st);
+    for (auto& e : exec) (void)hipGraphExecDestroy(e.second);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
 
 struct SolveCtx {
   hipStream_t st;
@@ -417,6 +433,7 @@ struct SolveCtx {
   int last_inner = 4, last_l3a = 4, last_l3b = 4;
   int nb_last = 0;
   msp_solve_info acc{};
+  StepGraphs graphs;
   std::vector<hipEvent_t>* evpool = nullptr;
   size_t evused = 0;
 };
@@ -673,11 +690,53 @@ msp_status run_l2(SolveCtx& c, const L2Step& a, const double* W, int slotid, int
 // inner FCG with one kernel per step (explicit operator): the right-hand side is in
 // X.r[0] and X.y is zero. Issues the predicted count plus one step (a finished column
 // costs a launch that only carries its state), then pairs until every column is done.
+// the first P steps as one graph (use_graph): steps 0..P-1 with their parities
+msp_status step_graph(SolveCtx& c, const L2xArgs& x, int P, hipGraphExec_t* out) {
+  const auto key = std::make_tuple(P, (const void*)x.G, (const void*)x.y, (const void*)x.mirror);
+  auto it = c.graphs.exec.find(key);
+  if (it != c.graphs.exec.end()) {
+    *out = it->second;
+    return MSP_OK;
+  }
+  c.graphs.st = c.st;
+  if (!c.graphs.cap) MSP_CHECK_HIP(hipStreamCreateWithFlags(&c.graphs.cap, hipStreamNonBlocking));
+  MSP_CHECK_HIP(hipStreamBeginCapture(c.graphs.cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < P && e == hipSuccess; ++i) e = l2x_step(c.graphs.cap, x, i & 1, i == 0 ? 1 : 0);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c.graphs.cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    MSP_CHECK_HIP(e != hipSuccess ? e : e2);
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  MSP_CHECK_HIP(e);
+  c.graphs.exec[key] = ex;
+  *out = ex;
+  return MSP_OK;
+}
+
 msp_status run_l2x(SolveCtx& c, const L2xArgs& x, int slotid, int* last, int64_t* counter) {
   MSP_CHECK_HIP(l2x_start(c.st, x));
   int issued = 0;
   int chunk = std::max(1, *last + 1);
   const int cap = x.max_iter;
+  if (c.o->use_graph && chunk <= cap) {  // the predicted chunk as one graph launch
+    hipGraphExec_t ex = nullptr;
+    TRY(step_graph(c, x, chunk, &ex));
+    MSP_CHECK_HIP(hipGraphLaunch(ex, c.st));
+    issued = chunk;
+    TRY(sync(c));
+    if (*slot(c, slotid) == 0 || issued >= cap) {
+      const int taken = *slot(c, slotid + 1);
+      *counter += taken;
+      if (taken > 0) *last = taken;
+      return MSP_OK;
+    }
+    chunk = 2;
+  }
   while (true) {
     for (int i = 0; i < chunk && issued < cap; ++i, ++issued)
       MSP_CHECK_HIP(l2x_step(c.st, x, issued & 1, issued == 0 ? 1 : 0));

@@ -164,3 +164,22 @@ def test_general_block_rhs_matrix_core_sweeps():
     x = X.cpu().numpy()
     for j in range(k):
         assert np.linalg.norm(a @ x[j] - bm[j]) <= 1e-10 * np.linalg.norm(bm[j])
+
+
+def test_general_graph_replayed_level3_steps_match_eager():
+    # the level-3 step chunks of both product-form solves as replayed graphs (two graphs
+    # per chunk length, one per operator) give the eager solution bit for bit
+    say("case general graph-replayed level-3 steps n=400")
+    n, k, s = 400, 12, 32
+    a, sv, _, _ = W.general_outlier(n, k, config_id=103, big=(1e2, 1e4))
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    b = torch.from_numpy(W.gaussian(n, 103)).to(DEV)
+    A, P = _gen(a, 0.0, lam0, s)
+    out = []
+    for g in (0, 1, 0, 1):
+        X, info = msp.solve(P, A, b, tol=1e-10, inner_tol=1e-12, level3_tol=1e-12, use_graph=g)
+        assert info["status"] == "MSP_OK", info
+        out.append((X.cpu().numpy(), info))
+    for x, info in out[1:]:
+        assert np.array_equal(x, out[0][0])
+        assert info["level3_iters"] == out[0][1]["level3_iters"]

@@ -300,3 +300,23 @@ def test_lower_triangle_sweep_refined_f32():
     xs = dense.solve_psd(a, b, lam)
     assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
     P.close()
+
+
+def test_graph_replayed_inner_steps_match_eager():
+    # the predicted inner steps of every SolveM1 call as one replayed HIP graph: the same
+    # kernels in the same order, so the solution is bitwise the eager one; the graph is
+    # replayed hundreds of times per solve with eager kernels and host syncs in between,
+    # and a second solve in a row replays fresh graphs
+    say("case graph-replayed inner steps n=1024")
+    w = W.config("psd_outlier_n1024")
+    runs = []
+    for g in (0, 1, 1, 0):
+        a, eigs, lam0, b, x, info, P, _ = _solve_case(w.n, 32, w.s, w.config_id, w.lam, w.tol, 1e-12,
+                                                      seeds=(w.seed_s, w.seed_phi), use_graph=g)
+        assert info["status"] == "MSP_OK", info
+        runs.append((x, info))
+        P.close()
+    for x, info in runs[1:]:
+        assert np.array_equal(x, runs[0][0])
+        assert info["outer_iters"] == runs[0][1]["outer_iters"]
+        assert info["inner_iters"] == runs[0][1]["inner_iters"]
