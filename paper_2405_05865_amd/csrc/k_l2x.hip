@@ -9,9 +9,11 @@
 // A step then needs one pass over the rows of [Minv; G] with r_{t+1}; everything else is
 // s-length vector work. Every block evaluates the s-length dots of the step redundantly,
 // with the same code on the same data (identical bits in every block), and computes the
-// matrix rows it owns. Vectors that every block reads in full (r, z, g, p, u) alternate
-// between two buffers by step parity, so no block overwrites what another block of the
-// same launch still reads; y is updated in place by the owner of each element.
+// matrix rows it owns. Columns (right-hand sides) are the grid's second dimension; with
+// one column the first block publishes the host mirror itself, with several a one-block
+// kernel does it after a chunk of steps. Vectors that every block reads in full (r, z, g,
+// p, u) alternate between two buffers by step parity, so no block overwrites what another
+// block of the same launch still reads; y is updated in place by the owner of each element.
 //
 // beta is the flexible (Polak-Ribiere) choice <z_t, r_t - r_{t-1}> / <z_{t-1}, r_{t-1}>,
 // with r_t - r_{t-1} = -alpha_{t-1} u_{t-1}. The stop rule is the one of the other inner
@@ -98,7 +100,8 @@ __global__ void __launch_bounds__(NT) k_l2x_start(L2xArgs a) {
   const int tid = threadIdx.x, s = a.s;
   const int row0 = blockIdx.x * NW * RPW;
   int cnt = 0;
-  for (int j = 0; j < a.k; ++j) {
+  {
+    const int j = blockIdx.y;
     const int64_t o = (int64_t)j * s;
     double rv[EPT];
     double sq = 0.0;
@@ -118,18 +121,18 @@ __global__ void __launch_bounds__(NT) k_l2x_start(L2xArgs a) {
       a.done[0][j] = dj;
       a.it[0][j] = 0;
     }
-    if (dj != 0) continue;  // uniform in the block
-    ++cnt;
+    if (dj == 0) {  // uniform in the block
+      ++cnt;
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = tid + q * NT;
-      if (e < CPL * WAVE) rs[e] = rv[q];
+      for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * NT;
+        if (e < CPL * WAVE) rs[e] = rv[q];
+      }
+      __syncthreads();
+      rows_pass<CPL, RPW>(a, row0, rs, a.z[0] + o, a.g[0] + o);
     }
-    __syncthreads();
-    rows_pass<CPL, RPW>(a, row0, rs, a.z[0] + o, a.g[0] + o);
-    __syncthreads();
   }
-  if (blockIdx.x == 0 && tid == 0 && a.mirror) {
+  if (gridDim.y == 1 && blockIdx.x == 0 && tid == 0 && a.mirror) {
     __hip_atomic_store(a.mirror, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(a.mirror + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
@@ -147,21 +150,25 @@ __global__ void __launch_bounds__(NT) k_l2x_step(L2xArgs a, int par, int first) 
   const int row0 = blockIdx.x * NW * RPW;
   const int row1 = min(s, row0 + NW * RPW);
   const bool lead = blockIdx.x == 0 && tid == 0;
-  int cnt = 0, mx = 0;
-  for (int j = 0; j < a.k; ++j) {
-    const int64_t o = (int64_t)j * s;
-    const int dcur = a.done[cur][j];
-    if (dcur != 0) {  // carry the finished column's state to the next parity
-      const int itc = a.it[cur][j];
-      if (lead) {
-        a.done[nxt][j] = dcur;
-        a.it[nxt][j] = itc;
-        a.rz[nxt][j] = a.rz[cur][j];
-        a.al[nxt][j] = a.al[cur][j];
-      }
-      mx = max(mx, itc);
-      continue;
+  const bool publish = gridDim.y == 1 && lead && a.mirror;
+  const int j = blockIdx.y;
+  const int64_t o = (int64_t)j * s;
+  const int dcur = a.done[cur][j];
+  if (dcur != 0) {  // carry the finished column's state to the next parity
+    const int itc = a.it[cur][j];
+    if (lead) {
+      a.done[nxt][j] = dcur;
+      a.it[nxt][j] = itc;
+      a.rz[nxt][j] = a.rz[cur][j];
+      a.al[nxt][j] = a.al[cur][j];
     }
+    if (publish) {
+      __hip_atomic_store(a.mirror, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(a.mirror + 1, itc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    return;  // uniform in the block
+  }
+  {
     double zv[EPT], rv[EPT], pv[EPT], uv[EPT];
     double zr = 0.0, zu = 0.0;
 #pragma unroll
@@ -218,19 +225,40 @@ __global__ void __launch_bounds__(NT) k_l2x_step(L2xArgs a, int par, int first) 
       a.rz[nxt][j] = zr;
       a.al[nxt][j] = alpha;
     }
-    mx = max(mx, it);
-    if (dj != 0) continue;  // uniform in the block
-    ++cnt;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = tid + q * NT;
-      if (e < CPL * WAVE) rs[e] = rv[q];
+    if (publish) {
+      __hip_atomic_store(a.mirror, dj == 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(a.mirror + 1, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    __syncthreads();
-    rows_pass<CPL, RPW>(a, row0, rs, a.z[nxt] + o, a.g[nxt] + o);
-    __syncthreads();
+    if (dj == 0) {  // uniform in the block
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * NT;
+        if (e < CPL * WAVE) rs[e] = rv[q];
+      }
+      __syncthreads();
+      rows_pass<CPL, RPW>(a, row0, rs, a.z[nxt] + o, a.g[nxt] + o);
+    }
   }
-  if (lead && a.mirror) {
+}
+
+// the host mirror for several columns: active count and largest iteration count of the
+// state at parity par
+__global__ void __launch_bounds__(NT) k_l2x_publish(L2xArgs a, int par) {
+  __shared__ int cnt, mx;
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    mx = 0;
+  }
+  __syncthreads();
+  int c = 0, m = 0;
+  for (int j = threadIdx.x; j < a.k; j += NT) {
+    c += a.done[par][j] == 0 ? 1 : 0;
+    m = max(m, a.it[par][j]);
+  }
+  atomicAdd(&cnt, c);
+  atomicMax(&mx, m);
+  __syncthreads();
+  if (threadIdx.x == 0 && a.mirror) {
     __hip_atomic_store(a.mirror, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(a.mirror + 1, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
@@ -243,9 +271,9 @@ template <int CPL, int RPW>
 hipError_t launch_t(hipStream_t st, const L2xArgs& a, int mode, int par, int first) {
   const unsigned blocks = (unsigned)((a.s + NW * RPW - 1) / (NW * RPW));
   if (mode == 0)
-    hipLaunchKernelGGL((k_l2x_start<CPL, RPW>), dim3(blocks), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((k_l2x_start<CPL, RPW>), dim3(blocks, (unsigned)a.k), dim3(NT), 0, st, a);
   else
-    hipLaunchKernelGGL((k_l2x_step<CPL, RPW>), dim3(blocks), dim3(NT), 0, st, a, par, first);
+    hipLaunchKernelGGL((k_l2x_step<CPL, RPW>), dim3(blocks, (unsigned)a.k), dim3(NT), 0, st, a, par, first);
   return hipGetLastError();
 }
 
@@ -292,4 +320,10 @@ hipError_t l2x_start(hipStream_t st, const L2xArgs& a) {
 hipError_t l2x_step(hipStream_t st, const L2xArgs& a, int par, int first) {
   if (a.s < 1 || a.s > kL2xMaxS || a.k < 1 || a.k > kL2xMaxK) return hipErrorInvalidValue;
   return dispatch(st, a, 1, par & 1, first ? 1 : 0);
+}
+
+hipError_t l2x_publish(hipStream_t st, const L2xArgs& a, int par) {
+  if (a.k <= 1) return hipSuccess;  // published by the step and start kernels
+  hipLaunchKernelGGL(k_l2x_publish, dim3(1), dim3(NT), 0, st, a, par & 1);
+  return hipGetLastError();
 }

@@ -703,6 +703,7 @@ msp_status step_graph(SolveCtx& c, const L2xArgs& x, int P, hipGraphExec_t* out)
   MSP_CHECK_HIP(hipStreamBeginCapture(c.graphs.cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
   for (int i = 0; i < P && e == hipSuccess; ++i) e = l2x_step(c.graphs.cap, x, i & 1, i == 0 ? 1 : 0);
+  if (e == hipSuccess) e = l2x_publish(c.graphs.cap, x, P & 1);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c.graphs.cap, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -740,6 +741,7 @@ msp_status run_l2x(SolveCtx& c, const L2xArgs& x, int slotid, int* last, int64_t
   while (true) {
     for (int i = 0; i < chunk && issued < cap; ++i, ++issued)
       MSP_CHECK_HIP(l2x_step(c.st, x, issued & 1, issued == 0 ? 1 : 0));
+    MSP_CHECK_HIP(l2x_publish(c.st, x, issued & 1));
     TRY(sync(c));
     if (*slot(c, slotid) == 0 || issued >= cap) break;
     chunk = 2;

@@ -292,6 +292,9 @@ L2xArgs l2x_carve(WsCarver& w, int64_t s, int64_t k);
 hipError_t l2x_start(hipStream_t st, const L2xArgs& a);
 // one step reading parity par; first = 1 for the step after l2x_start (par 0)
 hipError_t l2x_step(hipStream_t st, const L2xArgs& a, int par, int first);
+// host mirror (active columns, largest iteration count) of the state at parity par, for
+// k > 1 (with one column the step and start kernels publish it themselves)
+hipError_t l2x_publish(hipStream_t st, const L2xArgs& a, int par);
 
 // ---------------------------------------------------------------------------------
 // The preconditioner handle
