@@ -282,17 +282,21 @@ __global__ void __launch_bounds__(NT) k_beta(FcgState S, int64_t len, const doub
     S.part[((int64_t)blockIdx.x * S.k + j) * 2 + 0] = t1;
     S.part[((int64_t)blockIdx.x * S.k + j) * 2 + 1] = t2;
   }
-  if (!last_block(S.counter)) return;
+}
+
+// beta = <z, r - r_old> / rz and rz = <z, r> from the partials of k_beta, in one block (a
+// separate launch instead of a fenced last-block hand-off)
+__global__ void __launch_bounds__(NT) k_beta_fin(FcgState S, int nblocks) {
+  __shared__ double sh[NT / WAVE];
   for (int64_t jj = 0; jj < S.k; ++jj) {
     if (S.done[jj] != 0) continue;
-    const double zr = strided_sum(S.part + jj * 2 + 0, gridDim.x, S.k * 2, sh);
-    const double zro = strided_sum(S.part + jj * 2 + 1, gridDim.x, S.k * 2, sh);
+    const double zr = strided_sum(S.part + jj * 2 + 0, nblocks, S.k * 2, sh);
+    const double zro = strided_sum(S.part + jj * 2 + 1, nblocks, S.k * 2, sh);
     if (threadIdx.x == 0) {
       S.beta[jj] = (zr - zro) / S.rz[jj];
       S.rz[jj] = zr;
     }
   }
-  if (threadIdx.x == 0) *S.counter = 0;
 }
 
 __global__ void __launch_bounds__(NT) k_pupdate(FcgState S, int64_t len, const double* __restrict__ z,
@@ -514,6 +518,7 @@ hipError_t fcg_copy_done(hipStream_t st, FcgState S, const int32_t* src) {
 hipError_t fcg_direction(hipStream_t st, FcgState S, int64_t len, const double* r, const double* r_old,
                          const double* z, double* p) {
   hipLaunchKernelGGL(k_beta, dim3(grid_x(len), (unsigned)S.k), dim3(NT), 0, st, S, len, r, r_old, z);
+  hipLaunchKernelGGL(k_beta_fin, dim3(1), dim3(NT), 0, st, S, (int)grid_x(len));
   hipLaunchKernelGGL(k_pupdate, dim3(grid_x(len), (unsigned)S.k), dim3(NT), 0, st, S, len, z, p);
   return hipGetLastError();
 }
