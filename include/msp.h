@@ -178,6 +178,9 @@ typedef struct {
                               SolveM1 call as one HIP graph (captured once per solve and chunk
                               length, replayed on the solve's stream). Same kernels and results
                               as the eager launches. Default 0. */
+  int32_t batch_teams;     /* msp_solve_batched: a workgroup whose system is finished helps the
+                              A-sweeps of a larger unfinished system (same results bit for bit;
+                              chunked partials in a fixed order). Default 1. */
 } msp_solve_opts;
 
 typedef struct {

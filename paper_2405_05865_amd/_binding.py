@@ -59,6 +59,7 @@ class SolveOpts(ctypes.Structure):
         ("level2_form", ctypes.c_int32),
         ("sym_sweep", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
+        ("batch_teams", ctypes.c_int32),
     ]
 
 

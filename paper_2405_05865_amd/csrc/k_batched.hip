@@ -18,6 +18,15 @@
 //  The level-2 operator (C^T C + lam~ W) y is applied through H, formed once per
 //  system by the host; this is the same operator as C^T (C y) + lam~ W y, evaluated
 //  with s^2 instead of n s work per inner step.
+//
+// Teams. One compute unit streams only about 1/256 of the chip's bandwidth, so a batch
+// is bound by its largest systems. A workgroup whose system is finished joins a larger
+// unfinished one as a helper: the system's workgroup (the leader) publishes every A-sweep
+// as an epoch in the system's team record, and the row range is cut into 1024-row chunks
+// handed out as slices. Every chunk writes its own <x, A x> partials and the leader adds
+// them in chunk order, so the result is the same bits whoever computed which chunk. All
+// waits are bounded by wall-clock time: a slice that no helper claims in time is taken
+// by the leader, and an idle helper leaves.
 #include "msp_batched.h"
 
 #include <hip/hip_bf16.h>
@@ -29,6 +38,13 @@ constexpr int NW = 16;           // wavefronts per workgroup
 constexpr int NTB = NW * WAVE;   // 1024 threads
 constexpr int KB = MSP_BATCH_KMAX;
 constexpr int MAX_RESTARTS = 8;
+constexpr int CHR = MSP_BATCH_CHR;  // rows per chunk: NW wavefronts x one 64-row tile
+constexpr int MAXH = MSP_BATCH_MAXH;
+static_assert(CHR == NW * 64, "a chunk is one 64-row tile per wavefront");
+// wall-clock (100 MHz) bounds of the team waits
+constexpr uint64_t CLAIM_TICKS = 10000;       // 100 us: a live helper claims its slice sooner
+constexpr uint64_t SLICE_TICKS = 500000000;   // 5 s: a claimed slice must be done by then
+constexpr uint64_t IDLE_TICKS = 200000000;    // 2 s without a new epoch: the helper leaves
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -300,6 +316,10 @@ struct Ctx {
   double lam_lo;  // shift of the low-precision sweeps: lam, plus delta under refinement
   double* red;   // [NW][256]
   double* part;  // [NW][KB]
+  int* shi;      // [8] LDS ints for broadcasts
+  int epoch;     // thread 0: last published sweep epoch
+  int team_err;  // thread 0: a claimed slice timed out
+  int helped, selfdone;  // thread 0: slices done by helpers / taken back by the leader
   int outer, inner, refine, restarts;
   uint64_t ticks[BT_NPHASE];  // thread 0, when P.profile
 };
@@ -327,17 +347,151 @@ __device__ __forceinline__ bool any_active(const Cols* C, int k) {
   return a;
 }
 
-// sum over wavefronts of the per-lane accumulators v (lane l holds column l % 16):
-// C->pq[j] for j < k, fixed order
-__device__ __forceinline__ void reduce_cols(Ctx& c, double v, Cols* C) {
-  v += __shfl_xor(v, 16, WAVE);
-  v += __shfl_xor(v, 32, WAVE);
-  const int w = wave_id(), lane = lane_id();
-  if (lane < KB) c.part[w * KB + lane] = v;
+// ---- one A-sweep as chunked work ---------------------------------------------------
+// mode 0/1: out = (A + lam I) x with per-chunk partials <x, out>; mode 2: out = rhs -
+// (A + lam I) x. Bv is x in the arithmetic type (the F32 copy for low-precision A).
+struct Job {
+  const void* A;
+  int64_t lda;
+  const void* Bv;
+  const double* x;
+  const double* rhs;
+  int64_t ldr;
+  double* out;
+  double* cpart;
+  double lam;
+  int n, ldn, k, mode, aln;
+};
+
+template <class TA, class TC>
+__device__ void sweep_chunks(const Job& J, int ch0, int ch1, double* part /*LDS NW*KB*/) {
+  const int w = wave_id(), lane = lane_id(), i = lane & 15, g = lane >> 4;
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int r0 = ch * CHR + w * 64;
+    double pq = 0.0;
+    if (r0 < J.n) {
+      typename V4<TC>::t acc[4];
+      if (J.aln)
+        mm_rows<TA, TC, 4, true, true>((const TA*)J.A, J.lda, J.n, J.n, r0, (const TC*)J.Bv, J.ldn, J.k, acc);
+      else
+        mm_rows<TA, TC, 4, false, true>((const TA*)J.A, J.lda, J.n, J.n, r0, (const TC*)J.Bv, J.ldn, J.k, acc);
+      if (i < J.k) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int row = r0 + 16 * t + out_row<TC>(g, e);
+            if (row < J.n) {
+              const int64_t o = (int64_t)i * J.ldn + row;
+              const double xv = J.x[o];
+              const double q = (double)acc[t][e] + J.lam * xv;
+              if (J.mode == 2) {
+                J.out[o] = J.rhs[(int64_t)i * J.ldr + row] - q;
+              } else {
+                J.out[o] = q;
+                pq = fma(xv, q, pq);
+              }
+            }
+          }
+      }
+    }
+    // the chunk's partial per column: lanes l, l+16, l+32, l+48 hold column l
+    pq += __shfl_xor(pq, 16, WAVE);
+    pq += __shfl_xor(pq, 32, WAVE);
+    if (lane < KB) part[w * KB + lane] = pq;
+    __syncthreads();
+    if (threadIdx.x < (unsigned)J.k) {
+      double t = 0.0;
+      for (int q = 0; q < NW; ++q) t += part[q * KB + threadIdx.x];
+      J.cpart[(int64_t)ch * KB + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int ld_acq(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+// polling without cache maintenance; acquire once the awaited value is seen
+__device__ __forceinline__ int ld_rlx(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void st_rel(int32_t* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_claim(int32_t* p, int e) {
+  int cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (cur == e) return false;
+  return __hip_atomic_compare_exchange_strong(p, &cur, e, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int slice_begin(int s, int nslice, int nch) { return (int)((int64_t)s * nch / nslice); }
+
+// the leader's sweep: slices for the helpers that joined (published as a new epoch),
+// slice 0 itself, then every other slice done by a helper or, unclaimed, by itself
+template <class TA, class TC>
+__device__ void run_sweep(Ctx& c, const Job& J) {
+  const int nch = (J.n + CHR - 1) / CHR;
+  BatchTeam* T = c.S.team;
+  if (threadIdx.x == 0) {
+    int H = 0;
+    if (c.P.teams && T && nch > 1) {
+      H = min(__hip_atomic_load(&T->joined, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), MAXH);
+      H = min(H, nch - 1);
+    }
+    if (H > 0) {
+      T->x = J.x;
+      T->rhs = J.rhs;
+      T->out = J.out;
+      T->ldr = J.ldr;
+      T->lam = J.lam;
+      T->mode = J.mode;
+      T->nslice = H + 1;
+      c.epoch += 1;
+      st_rel(&T->epoch, c.epoch);  // after the barrier that ended the writes of x
+    }
+    c.shi[0] = H;
+  }
   __syncthreads();
+  const int H = c.shi[0];
+  sweep_chunks<TA, TC>(J, 0, slice_begin(1, H + 1, nch), c.part);
+  for (int s = 1; s <= H; ++s) {
+    if (threadIdx.x == 0) {
+      int self = 0;
+      const uint64_t t0 = wall_clock64();
+      while (true) {
+        if (ld_rlx(&T->done[s]) == c.epoch) {
+          fence_acq();
+          c.helped += 1;
+          break;
+        }
+        const uint64_t dt = wall_clock64() - t0;
+        if (dt > CLAIM_TICKS && cas_claim(&T->claim[s], c.epoch)) {
+          self = 1;
+          c.selfdone += 1;
+          break;
+        }
+        if (dt > SLICE_TICKS) {
+          c.team_err = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      c.shi[1] = self;
+    }
+    __syncthreads();
+    if (c.shi[1]) sweep_chunks<TA, TC>(J, slice_begin(s, H + 1, nch), slice_begin(s + 1, H + 1, nch), c.part);
+  }
+  __syncthreads();
+}
+
+// sum of the chunk partials in chunk order -> C->pq (columns < k)
+__device__ __forceinline__ void chunk_sum(const Ctx& c, const double* cpart, Cols* C) {
+  const int nch = (c.n + CHR - 1) / CHR;
   if (threadIdx.x < (unsigned)c.k) {
     double t = 0.0;
-    for (int q = 0; q < NW; ++q) t += c.part[q * KB + threadIdx.x];
+    for (int ch = 0; ch < nch; ++ch) t += cpart[(int64_t)ch * KB + threadIdx.x];
     C->pq[threadIdx.x] = t;
   }
   __syncthreads();
@@ -350,44 +504,29 @@ struct Batch {
   static __device__ void op_lo(Ctx& c) {
     PhaseTimer tm(c, BT_SWEEP_LO);
     const int w = wave_id(), lane = lane_id();
-    const double lam = c.lam_lo;
-    double pq = 0.0;
-    auto epi = [&](int j, int row, double v) {
-      const double pv = c.p1[(int64_t)j * c.ldn + row];
-      const double q = v + lam * pv;
-      c.q1[(int64_t)j * c.ldn + row] = q;
-      pq = fma(pv, q, pq);
-    };
+    Job J{c.S.A_lo, c.S.lda, c.p1, c.p1, nullptr, 0, c.q1, c.S.cpart, c.lam_lo, c.n, c.ldn, c.k, 0, c.S.aln_lo};
     if constexpr (sizeof(TLO) == 8) {
-      rows_pass<TLO, double, 4, true>((const TLO*)c.S.A_lo, c.S.lda, c.n, c.n, c.S.aln_lo, c.p1, c.ldn, c.k, epi);
+      __syncthreads();
+      run_sweep<TLO, double>(c, J);
     } else {
       if (w < c.k)
         _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) c.pf[(int64_t)w * c.ldn + i] = (float)c.p1[(int64_t)w * c.ldn + i];
       __syncthreads();
-      rows_pass<TLO, float, 4, true>((const TLO*)c.S.A_lo, c.S.lda, c.n, c.n, c.S.aln_lo, c.pf, c.ldn, c.k, epi);
+      J.Bv = c.pf;
+      run_sweep<TLO, float>(c, J);
     }
-    reduce_cols(c, pq, c.C1);
+    chunk_sum(c, c.S.cpart, c.C1);
   }
 
   // FP64 products with A_hi: mode 0: qh = (A_hi + lam I) ph, CH->pq = <ph, qh>;
   // mode 1: out = rhs - (A_hi + lam I) x
   static __device__ void op_hi(Ctx& c, int mode, const double* x, const double* rhs, int64_t ldr, double* out) {
     PhaseTimer tm(c, BT_SWEEP_HI);
-    const double lam = c.S.lam;
-    double pq = 0.0;
-    auto epi = [&](int j, int row, double v) {
-      const double xv = x[(int64_t)j * c.ldn + row];
-      const double q = v + lam * xv;
-      if (mode == 0) {
-        out[(int64_t)j * c.ldn + row] = q;
-        pq = fma(xv, q, pq);
-      } else {
-        out[(int64_t)j * c.ldn + row] = rhs[(int64_t)j * ldr + row] - q;
-      }
-    };
-    rows_pass<THI, double, 4, true>((const THI*)c.S.A_hi, c.S.lda, c.n, c.n, c.S.aln_hi, x, c.ldn, c.k, epi);
-    if (mode == 0) reduce_cols(c, pq, c.CH);
-    else __syncthreads();
+    const Job J{c.S.A_hi, c.S.lda, x, x, rhs, ldr, out, c.S.cpart, c.S.lam, c.n, c.ldn, c.k, mode == 0 ? 1 : 2,
+                c.S.aln_hi};
+    __syncthreads();
+    run_sweep<THI, double>(c, J);
+    if (mode == 0) chunk_sum(c, c.S.cpart, c.CH);
   }
 
   // out = M v for an s x s FP64 matrix (row-major, ld s); v, out: s-vectors
@@ -871,14 +1010,141 @@ struct Batch {
   }
 };
 
+
+// ---- helpers: a workgroup whose system is finished serves other systems' sweeps ----
+struct JobSh {  // the claimed job, broadcast through LDS
+  const double* x;
+  const double* rhs;
+  double* out;
+  int64_t ldr;
+  double lam;
+  int mode, nslice, epoch, state;
+};
+
+// serve slices of system S as helper h until it finishes or stays idle too long
+template <class TLO, class THI>
+__device__ void serve(const BatchSys& S, int h, int k, double* part, JobSh* js) {
+  BatchTeam* T = S.team;
+  const int nch = (S.n + CHR - 1) / CHR;
+  int last = 0;
+  if (threadIdx.x == 0) last = ld_acq(&T->epoch);  // epochs published before joining are not ours
+  while (true) {
+    if (threadIdx.x == 0) {
+      int state = 0;  // 0 leave, 1 work, 2 nothing for this helper in this epoch
+      const uint64_t t0 = wall_clock64();
+      while (true) {
+        if (ld_rlx(&T->finish)) break;
+        const int e = ld_rlx(&T->epoch);
+        if (e != last) {
+          fence_acq();
+          js->x = T->x;
+          js->rhs = T->rhs;
+          js->out = T->out;
+          js->ldr = T->ldr;
+          js->lam = T->lam;
+          js->mode = T->mode;
+          js->nslice = T->nslice;
+          if (ld_acq(&T->epoch) != e) continue;  // republished while reading: read again
+          last = e;
+          js->epoch = e;
+          state = (h < js->nslice && cas_claim(&T->claim[h], e)) ? 1 : 2;
+          break;
+        }
+        if (wall_clock64() - t0 > IDLE_TICKS) break;
+        __builtin_amdgcn_s_sleep(2);
+      }
+      js->state = state;
+    }
+    __syncthreads();
+    const int state = js->state;
+    if (state == 0) {
+      __syncthreads();
+      return;
+    }
+    if (state == 1) {
+      const int ns = js->nslice;
+      Job J{nullptr, S.lda, js->x, js->x, js->rhs, js->ldr, js->out, S.cpart, js->lam, S.n, S.ldn, k, js->mode, 0};
+      const int c0 = slice_begin(h, ns, nch), c1 = slice_begin(h + 1, ns, nch);
+      if (js->mode == 0) {
+        J.A = S.A_lo;
+        J.aln = S.aln_lo;
+        if constexpr (sizeof(TLO) == 8) {
+          sweep_chunks<TLO, double>(J, c0, c1, part);
+        } else {
+          J.Bv = S.pf;
+          sweep_chunks<TLO, float>(J, c0, c1, part);
+        }
+      } else {
+        J.A = S.A_hi;
+        J.aln = S.aln_hi;
+        sweep_chunks<THI, double>(J, c0, c1, part);
+      }
+      if (threadIdx.x == 0) st_rel(&T->done[h], js->epoch);  // after the barrier that ended the slice
+    }
+    __syncthreads();
+  }
+}
+
+// pick the unfinished system with the most work per helper and serve it; leave when no
+// system needs help or when some system has not started (its workgroup is waiting for a
+// compute unit: this one is better given back)
+template <class TLO, class THI>
+__device__ void help(const BatchSys* __restrict__ sys, const BatchPrm& prm, int k, double* part, int* shi,
+                     JobSh* js) {
+  for (int round = 0; round < 4 * MAXH; ++round) {
+    if (threadIdx.x == 0) {
+      int target = -1, h = 0;
+      double best = 0.0;
+      for (int j = 0; j < prm.nsys; ++j) {
+        BatchTeam* T = sys[j].team;
+        if (!__hip_atomic_load(&T->started, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          target = -1;
+          best = -1.0;
+          break;
+        }
+        if (__hip_atomic_load(&T->finish, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
+        const int nch = (sys[j].n + CHR - 1) / CHR;
+        const int jn = __hip_atomic_load(&T->joined, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (jn >= MAXH || jn >= nch - 1) continue;
+        const double score = (double)sys[j].n * (double)sys[j].n / (double)(jn + 2);
+        if (score > best) {
+          best = score;
+          target = j;
+        }
+      }
+      if (target >= 0) {
+        h = __hip_atomic_fetch_add(&sys[target].team->joined, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (h > MAXH) target = -2;
+      }
+      shi[2] = target;
+      shi[3] = h;
+    }
+    __syncthreads();
+    const int target = shi[2], h = shi[3];
+    __syncthreads();
+    if (target == -1) return;
+    if (target == -2) continue;
+    serve<TLO, THI>(sys[target], h, k, part, js);
+  }
+}
+
 template <class TLO, class THI, class TY>
 __global__ void __launch_bounds__(NTB) k_batch_psd(const BatchSys* __restrict__ sys, BatchPrm prm, int k,
                                                    BatchOut* __restrict__ out) {
   __shared__ Cols cH, c1, c2;
   __shared__ double red[NW * 256];
   __shared__ double part[NW * KB];
+  __shared__ int shi[8];
+  __shared__ JobSh js;
   Ctx c;
   c.S = sys[blockIdx.x];
+  c.shi = shi;
+  c.epoch = 0;
+  c.team_err = 0;
+  c.helped = 0;
+  c.selfdone = 0;
+  if (threadIdx.x == 0 && prm.teams)
+    __hip_atomic_store(&c.S.team->started, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   c.P = prm;
   c.k = k;
   c.n = c.S.n;
@@ -945,16 +1211,23 @@ __global__ void __launch_bounds__(NTB) k_batch_psd(const BatchSys* __restrict__ 
       if (d == 2) worst = max(worst, 2);
       else if (d != 4) worst = max(worst, 1);
     }
+    if (c.team_err) worst = max(worst, 4);
     o.code = worst;
     o.outer = c.outer;
     o.inner = c.inner;
     o.refine = c.refine;
     o.restarts = c.restarts;
+    o.helped = c.helped;
+    o.selfdone = c.selfdone;
     o.relres = rel;
     if (prm.profile) c.ticks[BT_TOTAL] = wall_clock64() - tstart;
     for (int q = 0; q < BT_NPHASE; ++q) o.ticks[q] = c.ticks[q];
     out[c.S.id] = o;
   }
+  if (!prm.teams) return;
+  __syncthreads();
+  if (threadIdx.x == 0) st_rel(&c.S.team->finish, 1);
+  help<TLO, THI>(sys, prm, k, part, shi, &js);
 }
 
 template <class TLO, class THI, class TY>

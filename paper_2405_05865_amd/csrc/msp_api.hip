@@ -359,6 +359,7 @@ extern "C" void msp_solve_opts_default(msp_solve_opts* o) {
   o->level2_form = 1;
   o->sym_sweep = 1;
   o->use_graph = 0;
+  o->batch_teams = 1;
 }
 
 

@@ -32,6 +32,8 @@ bool aligned16(const void* p, int64_t ld, size_t es) {
 struct BatchLayout {
   BatchSys* dsys = nullptr;
   BatchOut* dout = nullptr;
+  BatchTeam* team = nullptr;  // nsys records, zeroed before every launch
+  std::vector<double*> cpart;
   std::vector<double*> H;
   std::vector<double*> vec;
   std::vector<float*> pf;
@@ -43,9 +45,12 @@ struct BatchLayout {
 size_t batch_layout(WsCarver& w, int32_t nsys, const msp_system* sys, int kcap, BatchLayout* L) {
   BatchSys* dsys = w.take<BatchSys>(nsys);
   BatchOut* dout = w.take<BatchOut>(nsys);
+  BatchTeam* team = w.take<BatchTeam>(nsys);
   if (L) {
     L->dsys = dsys;
     L->dout = dout;
+    L->team = team;
+    L->cpart.resize(nsys);
     L->H.resize(nsys);
     L->vec.resize(nsys);
     L->pf.resize(nsys);
@@ -55,9 +60,11 @@ size_t batch_layout(WsCarver& w, int32_t nsys, const msp_system* sys, int kcap, 
     const msp_precond* P = sys[i].P;
     const int64_t n = P->n, s = P->s;
     double* H = w.take<double>(s * s);
+    double* cp = w.take<double>((size_t)((n + MSP_BATCH_CHR - 1) / MSP_BATCH_CHR) * MSP_BATCH_KMAX);
     double* v = w.take<double>((size_t)kcap * (11 * round8(n) + 7 * round8(s)));
     float* f = w.take<float>((size_t)kcap * round8(n));
     if (L) {
+      L->cpart[i] = cp;
       L->H[i] = H;
       L->vec[i] = v;
       L->pf[i] = f;
@@ -156,6 +163,8 @@ extern "C" msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_sy
   prm.refine = (o->refine && lo_t != MSP_F64) ? 1 : 0;
   prm.kcap = kcap;
   prm.profile = o->profile ? 1 : 0;
+  prm.teams = o->batch_teams ? 1 : 0;
+  prm.nsys = nsys;
   int clock_khz = 0;
   if (prm.profile) {
     int dev = 0;
@@ -197,10 +206,13 @@ extern "C" msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_sy
       d.aln_hi = aligned16(u.A_hi, u.lda, esize(hi_t));
       d.aln_y = aligned16(P->Y, P->ldy, esize(yt));
       d.aln_m = aligned16(P->Minv, P->s, 8) && aligned16(L.H[i], P->s, 8);
+      d.team = L.team + q;  // records in launch order: helpers scan the largest systems first
+      d.cpart = L.cpart[i];
       d.id = i;
       hs[q] = d;
     }
     MSP_CHECK_HIP(hipMemcpyAsync(L.dsys, hs.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
+    MSP_CHECK_HIP(hipMemsetAsync(L.team, 0, sizeof(BatchTeam) * nsys, st));
     MSP_CHECK_HIP(launch_batch_psd(st, lo_t, hi_t, yt, L.dsys, nsys, prm, kk, L.dout));
     MSP_CHECK_HIP(hipMemcpyAsync(ho.data(), L.dout, sizeof(BatchOut) * nsys, hipMemcpyDeviceToHost, st));
     MSP_CHECK_HIP(hipStreamSynchronize(st));
@@ -210,7 +222,8 @@ extern "C" msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_sy
       const msp_status s = r.code == 0 ? MSP_OK
                            : r.code == 1 ? MSP_ERR_NO_CONVERGENCE
                            : r.code == 2 ? MSP_ERR_BREAKDOWN
-                                         : MSP_ERR_NONFINITE;
+                           : r.code == 3 ? MSP_ERR_NONFINITE
+                                         : MSP_ERR_HIP;
       if (a.status == MSP_OK) a.status = s;
       a.outer_iters += r.outer;
       a.inner_iters += r.inner;
@@ -226,9 +239,10 @@ extern "C" msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_sy
         a.timed_sweeps += r.outer;
         if (batch_log_on())
           fprintf(stderr, "[msp] batch system %d n=%d: total %.2f ms | sweep_lo %.2f  sweep_hi %.2f  Y^T r %.2f  "
-                          "level-2 %.2f  Y y %.2f | outer %d inner %d refine %d\n",
+                          "level-2 %.2f  Y y %.2f | outer %d inner %d refine %d | slices helped %d self %d\n",
                   i, (int)sys[i].P->n, r.ticks[BT_TOTAL] * ms, r.ticks[BT_SWEEP_LO] * ms, r.ticks[BT_SWEEP_HI] * ms,
-                  r.ticks[BT_YT] * ms, r.ticks[BT_LEVEL2] * ms, r.ticks[BT_YZ] * ms, r.outer, r.inner, r.refine);
+                  r.ticks[BT_YT] * ms, r.ticks[BT_LEVEL2] * ms, r.ticks[BT_YZ] * ms, r.outer, r.inner, r.refine,
+                  r.helped, r.selfdone);
       }
     }
   }
@@ -240,6 +254,7 @@ extern "C" msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_sy
       msp_fail(ret, "system %d: %s (relative residual %.3e)", i,
                ret == MSP_ERR_NO_CONVERGENCE ? "tolerance not reached"
                : ret == MSP_ERR_BREAKDOWN    ? "breakdown"
+               : ret == MSP_ERR_HIP          ? "a helper workgroup's sweep slice did not complete in time"
                                              : "non-finite residual",
                acc[i].rel_residual_max);
     }

@@ -3,6 +3,23 @@
 #include "msp_internal.h"
 
 #define MSP_BATCH_KMAX 16  // right-hand sides per launch (the N dimension of the 16x16 tiles)
+#define MSP_BATCH_MAXH 31  // helper workgroups per system
+#define MSP_BATCH_CHR 1024 // rows per sweep chunk (16 wavefronts x 64-row tiles)
+
+// Cooperation record of one system (device memory, zeroed before the launch). The
+// system's own workgroup (the leader) publishes each A-sweep as an epoch; workgroups
+// whose systems are finished join as helpers and claim slices of its row chunks.
+struct BatchTeam {
+  int32_t epoch, nslice, mode, finish;
+  int32_t joined, started, pad[2];
+  int32_t claim[MSP_BATCH_MAXH + 1];  // slice s claimed for epoch claim[s]
+  int32_t done[MSP_BATCH_MAXH + 1];   // slice s completed for epoch done[s]
+  const double* x;    // the vector of the sweep (FP64)
+  const double* rhs;  // mode 2: right-hand side
+  double* out;        // output rows
+  int64_t ldr;
+  double lam;
+};
 
 // One system as the kernel sees it (host-filled, copied to the device)
 struct BatchSys {
@@ -22,6 +39,8 @@ struct BatchSys {
   int32_t n, s, ldn, lds;
   double lam, lt;     // lambda and lambda~ = lambda + lambda0
   int32_t aln_lo, aln_hi, aln_y, aln_m;  // rows of A_lo / A_hi / Y / the s x s matrices are 16-byte aligned
+  BatchTeam* team;    // cooperation record
+  double* cpart;      // per-chunk partials of <x, A x>: [ceil(n / MSP_BATCH_CHR)][MSP_BATCH_KMAX]
   int32_t id;         // position in the caller's array
   int32_t pad;
 };
@@ -31,13 +50,18 @@ struct BatchPrm {
   int32_t max_outer, max_inner, max_refine, refine;
   int32_t kcap;       // columns allocated per vector
   int32_t profile;    // record wall-clock time per phase (BatchOut.ticks)
+  int32_t teams;      // finished workgroups help the remaining systems' sweeps
+  int32_t nsys;       // systems in the launch (helpers scan their records)
 };
 
 enum { BT_SWEEP_LO = 0, BT_SWEEP_HI, BT_YT, BT_LEVEL2, BT_YZ, BT_TOTAL, BT_NPHASE };
 
 struct BatchOut {
-  int32_t code;       // 0 ok, 1 tolerance not reached, 2 breakdown, 3 non-finite
-  int32_t outer, inner, refine, restarts, pad;
+  int32_t code;       // 0 ok, 1 tolerance not reached, 2 breakdown, 3 non-finite,
+                      // 4 a helper's slice did not complete in time
+  int32_t outer, inner, refine, restarts;
+  int32_t helped, selfdone;  // sweep slices done by helpers / taken back by the leader
+  int32_t pad;
   double relres;      // largest confirmed relative residual on A_hi
   uint64_t ticks[BT_NPHASE];  // profile: wall-clock ticks per phase (thread 0's view)
 };

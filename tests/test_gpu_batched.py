@@ -184,3 +184,32 @@ def test_batched_adjoint_matches_dense_gradients(lo):
         lp = sum(np.sum(dense.solve_psd(a, Bm[j], lam + h) ** 2) for j in range(k))
         lm = sum(np.sum(dense.solve_psd(a, Bm[j], lam - h) ** 2) for j in range(k))
         assert abs(dl - (lp - lm) / (2 * h)) <= 1e-5 * abs(dld)
+
+
+def test_batched_teams_same_bits_as_single_workgroups():
+    # finished workgroups help the A-sweeps of the larger systems (row chunks with their
+    # own partials, summed in chunk order): the solutions are the same bits as without
+    # helpers, for several launches in a row
+    sizes = [3000, 2600, 2100, 300, 200, 180, 160, 150, 140, 130, 120, 110]
+    k = 4
+    say(f"case batched teams sizes={sizes} k={k}")
+    args, syss = [], []
+    for i, n in enumerate(sizes):
+        sy = _system(n, 900 + i, lengthscale=0.7 + 0.1 * i, dtype=np.float32)
+        A = _padded(sy["a"], torch.float32, pad=(i % 2) * 4)
+        P = _build(sy, A, y_dtype=torch.float32)
+        Bm = W.gaussian((k, n), 900 + i)
+        syss.append(sy)
+        args.append((P, A, A, torch.from_numpy(Bm).to(DEV)))
+    runs = []
+    for teams in (0, 1, 1, 0):
+        Xs, infos = msp.solve_batched(args, tol=1e-10, refine=1, batch_teams=teams)
+        assert all(d["status"] == "MSP_OK" for d in infos), infos
+        runs.append([X.cpu().numpy() for X in Xs])
+    for r in runs[1:]:
+        for x0, x1 in zip(runs[0], r):
+            assert np.array_equal(x0, x1)
+    for sy, x, (_, _, _, Bt) in zip(syss, runs[1], args):
+        Bm = Bt.cpu().numpy()
+        for j in range(k):
+            assert dense.rel_residual_psd(sy["a64"], x[j], Bm[j], sy["lam"]) <= 1e-10
