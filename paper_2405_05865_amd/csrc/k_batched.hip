@@ -353,14 +353,15 @@ __device__ __forceinline__ bool any_active(const Cols* C, int k) {
 struct Job {
   const void* A;
   int64_t lda;
-  const void* Bv;
+  const void* Bv;  // x in the arithmetic type, ld ldb
+  int64_t ldb;
   const double* x;
   const double* rhs;
   int64_t ldr;
   double* out;
   double* cpart;
   double lam;
-  int n, ldn, k, mode, aln;
+  int n, ncols, ldn, k, mode, aln;
 };
 
 template <class TA, class TC>
@@ -372,9 +373,9 @@ __device__ void sweep_chunks(const Job& J, int ch0, int ch1, double* part /*LDS 
     if (r0 < J.n) {
       typename V4<TC>::t acc[4];
       if (J.aln)
-        mm_rows<TA, TC, 4, true, true>((const TA*)J.A, J.lda, J.n, J.n, r0, (const TC*)J.Bv, J.ldn, J.k, acc);
+        mm_rows<TA, TC, 4, true, true>((const TA*)J.A, J.lda, J.n, J.ncols, r0, (const TC*)J.Bv, J.ldb, J.k, acc);
       else
-        mm_rows<TA, TC, 4, false, true>((const TA*)J.A, J.lda, J.n, J.n, r0, (const TC*)J.Bv, J.ldn, J.k, acc);
+        mm_rows<TA, TC, 4, false, true>((const TA*)J.A, J.lda, J.n, J.ncols, r0, (const TC*)J.Bv, J.ldb, J.k, acc);
       if (i < J.k) {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -409,6 +410,101 @@ __device__ void sweep_chunks(const Job& J, int ch0, int ch1, double* part /*LDS 
   }
 }
 
+
+// mode 3: out = (rhs - Y x) * lam on the rows of the chunks (x: s-vectors, ld ldb)
+template <class TY>
+__device__ void yz_chunks(const Job& J, int ch0, int ch1) {
+  const int w = wave_id(), lane = lane_id(), i = lane & 15, g = lane >> 4;
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int r0 = ch * CHR + w * 64;
+    if (r0 >= J.n) continue;
+    v4d acc[4];
+    if (J.aln)
+      mm_rows<TY, double, 4, true, false>((const TY*)J.A, J.lda, J.n, J.ncols, r0, (const double*)J.Bv, J.ldb, J.k, acc);
+    else
+      mm_rows<TY, double, 4, false, false>((const TY*)J.A, J.lda, J.n, J.ncols, r0, (const double*)J.Bv, J.ldb, J.k,
+                                           acc);
+    if (i < J.k) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = r0 + 16 * t + out_row<double>(g, e);
+          if (row < J.n) {
+            const int64_t o = (int64_t)i * J.ldn + row;
+            J.out[o] = (J.rhs[(int64_t)i * J.ldr + row] - acc[t][e]) * J.lam;
+          }
+        }
+    }
+  }
+}
+
+// mode 4: out[ch][j][c] = sum over the rows of chunk ch of Y[row, c] rhs_j[row]; the
+// 16-column tiles of Y are the MFMA rows and the chunk's rows the reduction
+template <class TY>
+__device__ void ytr_chunks(const Job& J, int ch0, int ch1) {
+  const int w = wave_id(), lane = lane_id(), i = lane & 15, g = lane >> 4;
+  const int s = J.ncols;
+  const int T = (s + 15) / 16;
+  const int jb = i < J.k ? i : J.k - 1;
+  const TY* Y = (const TY*)J.A;
+  const double* V = J.rhs + (int64_t)jb * J.ldr;
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int rb = ch * CHR, re = min(J.n, rb + CHR);
+    for (int tile = w; tile < T; tile += NW) {
+      const int c0 = tile * 16;
+      const int col = min(c0 + i, s - 1);
+      v4d acc = {0, 0, 0, 0};
+      int r = rb;
+      for (; r + 64 <= re; r += 64) {
+        double a[16], b[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int row = r + 4 * u + g;
+          a[u] = (double)Y[(int64_t)row * J.lda + col];
+          b[u] = V[row];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = mfma(a[u], b[u], acc);
+      }
+      for (; r < re; r += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int row = r + 4 * u + g;
+          const bool ok = row < re;
+          a[u] = ok ? (double)Y[(int64_t)row * J.lda + col] : 0.0;
+          b[u] = ok ? V[row] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = mfma(a[u], b[u], acc);
+      }
+      if (i < J.k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int cc = c0 + out_row<double>(g, e);
+          if (cc < s) J.out[((int64_t)ch * KB + i) * s + cc] = acc[e];
+        }
+    }
+  }
+}
+
+template <class TLO, class THI, class TY>
+__device__ void do_chunks(const Job& J, int ch0, int ch1, double* part) {
+  if (J.mode == 0) {
+    if constexpr (sizeof(TLO) == 8) sweep_chunks<TLO, double>(J, ch0, ch1, part);
+    else sweep_chunks<TLO, float>(J, ch0, ch1, part);
+  } else if (J.mode <= 2) {
+    sweep_chunks<THI, double>(J, ch0, ch1, part);
+  } else if (J.mode == 3) {
+    yz_chunks<TY>(J, ch0, ch1);
+    __syncthreads();
+  } else {
+    ytr_chunks<TY>(J, ch0, ch1);
+    __syncthreads();
+  }
+}
+
 __device__ __forceinline__ int ld_acq(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -430,8 +526,8 @@ __device__ __forceinline__ int slice_begin(int s, int nslice, int nch) { return 
 
 // the leader's sweep: slices for the helpers that joined (published as a new epoch),
 // slice 0 itself, then every other slice done by a helper or, unclaimed, by itself
-template <class TA, class TC>
-__device__ void run_sweep(Ctx& c, const Job& J) {
+template <class TLO, class THI, class TY>
+__device__ void run_job(Ctx& c, const Job& J) {
   const int nch = (J.n + CHR - 1) / CHR;
   BatchTeam* T = c.S.team;
   if (threadIdx.x == 0) {
@@ -441,6 +537,9 @@ __device__ void run_sweep(Ctx& c, const Job& J) {
       H = min(H, nch - 1);
     }
     if (H > 0) {
+      T->bv = J.Bv;
+      T->ldb = J.ldb;
+      T->ncols = J.ncols;
       T->x = J.x;
       T->rhs = J.rhs;
       T->out = J.out;
@@ -455,7 +554,7 @@ __device__ void run_sweep(Ctx& c, const Job& J) {
   }
   __syncthreads();
   const int H = c.shi[0];
-  sweep_chunks<TA, TC>(J, 0, slice_begin(1, H + 1, nch), c.part);
+  do_chunks<TLO, THI, TY>(J, 0, slice_begin(1, H + 1, nch), c.part);
   for (int s = 1; s <= H; ++s) {
     if (threadIdx.x == 0) {
       int self = 0;
@@ -481,7 +580,7 @@ __device__ void run_sweep(Ctx& c, const Job& J) {
       c.shi[1] = self;
     }
     __syncthreads();
-    if (c.shi[1]) sweep_chunks<TA, TC>(J, slice_begin(s, H + 1, nch), slice_begin(s + 1, H + 1, nch), c.part);
+    if (c.shi[1]) do_chunks<TLO, THI, TY>(J, slice_begin(s, H + 1, nch), slice_begin(s + 1, H + 1, nch), c.part);
   }
   __syncthreads();
 }
@@ -504,17 +603,15 @@ struct Batch {
   static __device__ void op_lo(Ctx& c) {
     PhaseTimer tm(c, BT_SWEEP_LO);
     const int w = wave_id(), lane = lane_id();
-    Job J{c.S.A_lo, c.S.lda, c.p1, c.p1, nullptr, 0, c.q1, c.S.cpart, c.lam_lo, c.n, c.ldn, c.k, 0, c.S.aln_lo};
-    if constexpr (sizeof(TLO) == 8) {
-      __syncthreads();
-      run_sweep<TLO, double>(c, J);
-    } else {
+    Job J{c.S.A_lo, c.S.lda, c.p1, c.ldn, c.p1, nullptr, 0, c.q1, c.S.cpart, c.lam_lo, c.n, c.n, c.ldn, c.k, 0,
+          c.S.aln_lo};
+    if constexpr (sizeof(TLO) != 8) {
       if (w < c.k)
         _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) c.pf[(int64_t)w * c.ldn + i] = (float)c.p1[(int64_t)w * c.ldn + i];
-      __syncthreads();
       J.Bv = c.pf;
-      run_sweep<TLO, float>(c, J);
     }
+    __syncthreads();
+    run_job<TLO, THI, TY>(c, J);
     chunk_sum(c, c.S.cpart, c.C1);
   }
 
@@ -522,10 +619,10 @@ struct Batch {
   // mode 1: out = rhs - (A_hi + lam I) x
   static __device__ void op_hi(Ctx& c, int mode, const double* x, const double* rhs, int64_t ldr, double* out) {
     PhaseTimer tm(c, BT_SWEEP_HI);
-    const Job J{c.S.A_hi, c.S.lda, x, x, rhs, ldr, out, c.S.cpart, c.S.lam, c.n, c.ldn, c.k, mode == 0 ? 1 : 2,
-                c.S.aln_hi};
+    const Job J{c.S.A_hi, c.S.lda, x, c.ldn, x, rhs, ldr, out, c.S.cpart, c.S.lam, c.n, c.n, c.ldn, c.k,
+                mode == 0 ? 1 : 2, c.S.aln_hi};
     __syncthreads();
-    run_sweep<THI, double>(c, J);
+    run_job<TLO, THI, TY>(c, J);
     if (mode == 0) chunk_sum(c, c.S.cpart, c.CH);
   }
 
@@ -536,91 +633,29 @@ struct Batch {
     __syncthreads();
   }
 
-  // z1 = (r1 - Y y2) / lam~ for the columns active at level 1
+  // z1 = (r1 - Y y2) / lam~ (written for every column; only active ones are read)
   static __device__ void y_z(Ctx& c) {
     PhaseTimer tm(c, BT_YZ);
-    const double inv = 1.0 / c.S.lt;
-    const Cols* C1 = c.C1;
-    auto epi = [&](int j, int row, double v) {
-      if (C1->done[j] != 0) return;
-      const int64_t o = (int64_t)j * c.ldn + row;
-      c.z1[o] = (c.r1[o] - v) * inv;
-    };
-    rows_pass<TY, double, 4, false>((const TY*)c.S.Y, c.S.ldy, c.n, c.s, c.S.aln_y, c.y2, c.lds, c.k, epi);
+    const Job J{c.S.Y, c.S.ldy, c.y2, c.lds, nullptr, c.r1, c.ldn, c.z1, nullptr, 1.0 / c.S.lt, c.n, c.s, c.ldn, c.k, 3,
+                c.S.aln_y};
     __syncthreads();
+    run_job<TLO, THI, TY>(c, J);
   }
 
-  // b2 = Y^T r1: column tiles of Y (16 columns) as MFMA rows, rows of Y as the reduction;
-  // with fewer tiles than wavefronts the rows are split and the splits summed in order
+  // b2 = Y^T r1 from chunk partials (each 1024 rows: 16-column tiles of Y as MFMA rows, the
+  // chunk's rows as the reduction), added in chunk order
   static __device__ void yt_r(Ctx& c) {
     PhaseTimer tm(c, BT_YT);
-    const int w = wave_id(), lane = lane_id(), i = lane & 15, g = lane >> 4;
-    const int T = (c.s + 15) / 16;
-    const int RS = T >= NW ? 1 : NW / T;
-    const int jb = i < c.k ? i : c.k - 1;
-    const TY* Y = (const TY*)c.S.Y;
-    const int64_t ldy = c.S.ldy;
-    const double* V = c.r1 + (int64_t)jb * c.ldn;
-    const int per = ((c.n + RS - 1) / RS + 15) / 16 * 16;
-    for (int item = w; item < T * RS; item += NW) {
-      const int tile = item % T, split = item / T;
-      const int c0 = tile * 16;
-      const int col = min(c0 + i, c.s - 1);
-      const int rb = split * per, re = min(c.n, rb + per);
-      v4d acc = {0, 0, 0, 0};
-      int r = rb;
-      for (; r + 64 <= re; r += 64) {
-        double a[16], b[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int row = r + 4 * u + g;
-          a[u] = (double)Y[(int64_t)row * ldy + col];
-          b[u] = V[row];
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc = mfma(a[u], b[u], acc);
-      }
-      for (; r < re; r += 16) {
-        double a[4], b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int row = r + 4 * u + g;
-          const bool ok = row < re;
-          a[u] = ok ? (double)Y[(int64_t)row * ldy + col] : 0.0;
-          b[u] = ok ? V[row] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc = mfma(a[u], b[u], acc);
-      }
-      if (RS == 1) {
-        if (i < c.k)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int cc = c0 + out_row<double>(g, e);
-            if (cc < c.s) c.b2[(int64_t)i * c.lds + cc] = acc[e];
-          }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) c.red[item * 256 + lane * 4 + e] = acc[e];
-      }
-    }
-    if (RS > 1) {
-      __syncthreads();
-      if (w < T) {
-        const int c0 = w * 16;
-        double v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = c.red[w * 256 + lane * 4 + e];
-        for (int sp = 1; sp < RS; ++sp)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] += c.red[(w + sp * T) * 256 + lane * 4 + e];
-        if (i < c.k)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int cc = c0 + out_row<double>(g, e);
-            if (cc < c.s) c.b2[(int64_t)i * c.lds + cc] = v[e];
-          }
-      }
+    const Job J{c.S.Y, c.S.ldy, nullptr, 0, nullptr, c.r1, c.ldn, c.S.ypart, nullptr, 0.0, c.n, c.s, c.ldn, c.k, 4,
+                c.S.aln_y};
+    __syncthreads();
+    run_job<TLO, THI, TY>(c, J);
+    const int nch = (c.n + CHR - 1) / CHR;
+    for (int t = threadIdx.x; t < c.k * c.s; t += NTB) {
+      const int j = t / c.s, cc = t % c.s;
+      double v = 0.0;
+      for (int ch = 0; ch < nch; ++ch) v += c.S.ypart[((int64_t)ch * KB + j) * c.s + cc];
+      c.b2[(int64_t)j * c.lds + cc] = v;
     }
     __syncthreads();
   }
@@ -1013,16 +1048,17 @@ struct Batch {
 
 // ---- helpers: a workgroup whose system is finished serves other systems' sweeps ----
 struct JobSh {  // the claimed job, broadcast through LDS
+  const void* bv;
   const double* x;
   const double* rhs;
   double* out;
-  int64_t ldr;
+  int64_t ldb, ldr;
   double lam;
-  int mode, nslice, epoch, state;
+  int mode, ncols, nslice, epoch, state;
 };
 
 // serve slices of system S as helper h until it finishes or stays idle too long
-template <class TLO, class THI>
+template <class TLO, class THI, class TY>
 __device__ void serve(const BatchSys& S, int h, int k, double* part, JobSh* js) {
   BatchTeam* T = S.team;
   const int nch = (S.n + CHR - 1) / CHR;
@@ -1037,12 +1073,15 @@ __device__ void serve(const BatchSys& S, int h, int k, double* part, JobSh* js) 
         const int e = ld_rlx(&T->epoch);
         if (e != last) {
           fence_acq();
+          js->bv = T->bv;
           js->x = T->x;
           js->rhs = T->rhs;
           js->out = T->out;
+          js->ldb = T->ldb;
           js->ldr = T->ldr;
           js->lam = T->lam;
           js->mode = T->mode;
+          js->ncols = T->ncols;
           js->nslice = T->nslice;
           if (ld_acq(&T->epoch) != e) continue;  // republished while reading: read again
           last = e;
@@ -1062,23 +1101,13 @@ __device__ void serve(const BatchSys& S, int h, int k, double* part, JobSh* js) 
       return;
     }
     if (state == 1) {
-      const int ns = js->nslice;
-      Job J{nullptr, S.lda, js->x, js->x, js->rhs, js->ldr, js->out, S.cpart, js->lam, S.n, S.ldn, k, js->mode, 0};
-      const int c0 = slice_begin(h, ns, nch), c1 = slice_begin(h + 1, ns, nch);
-      if (js->mode == 0) {
-        J.A = S.A_lo;
-        J.aln = S.aln_lo;
-        if constexpr (sizeof(TLO) == 8) {
-          sweep_chunks<TLO, double>(J, c0, c1, part);
-        } else {
-          J.Bv = S.pf;
-          sweep_chunks<TLO, float>(J, c0, c1, part);
-        }
-      } else {
-        J.A = S.A_hi;
-        J.aln = S.aln_hi;
-        sweep_chunks<THI, double>(J, c0, c1, part);
-      }
+      const int ns = js->nslice, mode = js->mode;
+      const bool yjob = mode >= 3;
+      const Job J{mode == 0 ? S.A_lo : (yjob ? S.Y : S.A_hi),
+                  yjob ? S.ldy : S.lda,
+                  js->bv, js->ldb, js->x, js->rhs, js->ldr, js->out, S.cpart, js->lam, S.n, js->ncols, S.ldn, k, mode,
+                  mode == 0 ? S.aln_lo : (yjob ? S.aln_y : S.aln_hi)};
+      do_chunks<TLO, THI, TY>(J, slice_begin(h, ns, nch), slice_begin(h + 1, ns, nch), part);
       if (threadIdx.x == 0) st_rel(&T->done[h], js->epoch);  // after the barrier that ended the slice
     }
     __syncthreads();
@@ -1088,7 +1117,7 @@ __device__ void serve(const BatchSys& S, int h, int k, double* part, JobSh* js) 
 // pick the unfinished system with the most work per helper and serve it; leave when no
 // system needs help or when some system has not started (its workgroup is waiting for a
 // compute unit: this one is better given back)
-template <class TLO, class THI>
+template <class TLO, class THI, class TY>
 __device__ void help(const BatchSys* __restrict__ sys, const BatchPrm& prm, int k, double* part, int* shi,
                      JobSh* js) {
   for (int round = 0; round < 4 * MAXH; ++round) {
@@ -1124,7 +1153,7 @@ __device__ void help(const BatchSys* __restrict__ sys, const BatchPrm& prm, int 
     __syncthreads();
     if (target == -1) return;
     if (target == -2) continue;
-    serve<TLO, THI>(sys[target], h, k, part, js);
+    serve<TLO, THI, TY>(sys[target], h, k, part, js);
   }
 }
 
@@ -1227,7 +1256,7 @@ __global__ void __launch_bounds__(NTB) k_batch_psd(const BatchSys* __restrict__ 
   if (!prm.teams) return;
   __syncthreads();
   if (threadIdx.x == 0) st_rel(&c.S.team->finish, 1);
-  help<TLO, THI>(sys, prm, k, part, shi, &js);
+  help<TLO, THI, TY>(sys, prm, k, part, shi, &js);
 }
 
 template <class TLO, class THI, class TY>

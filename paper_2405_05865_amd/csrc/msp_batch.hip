@@ -33,7 +33,7 @@ struct BatchLayout {
   BatchSys* dsys = nullptr;
   BatchOut* dout = nullptr;
   BatchTeam* team = nullptr;  // nsys records, zeroed before every launch
-  std::vector<double*> cpart;
+  std::vector<double*> cpart, ypart;
   std::vector<double*> H;
   std::vector<double*> vec;
   std::vector<float*> pf;
@@ -51,6 +51,7 @@ size_t batch_layout(WsCarver& w, int32_t nsys, const msp_system* sys, int kcap, 
     L->dout = dout;
     L->team = team;
     L->cpart.resize(nsys);
+    L->ypart.resize(nsys);
     L->H.resize(nsys);
     L->vec.resize(nsys);
     L->pf.resize(nsys);
@@ -60,11 +61,14 @@ size_t batch_layout(WsCarver& w, int32_t nsys, const msp_system* sys, int kcap, 
     const msp_precond* P = sys[i].P;
     const int64_t n = P->n, s = P->s;
     double* H = w.take<double>(s * s);
-    double* cp = w.take<double>((size_t)((n + MSP_BATCH_CHR - 1) / MSP_BATCH_CHR) * MSP_BATCH_KMAX);
+    const size_t nch = (size_t)((n + MSP_BATCH_CHR - 1) / MSP_BATCH_CHR);
+    double* cp = w.take<double>(nch * MSP_BATCH_KMAX);
+    double* yp = w.take<double>(nch * MSP_BATCH_KMAX * s);
     double* v = w.take<double>((size_t)kcap * (11 * round8(n) + 7 * round8(s)));
     float* f = w.take<float>((size_t)kcap * round8(n));
     if (L) {
       L->cpart[i] = cp;
+      L->ypart[i] = yp;
       L->H[i] = H;
       L->vec[i] = v;
       L->pf[i] = f;
@@ -208,6 +212,7 @@ extern "C" msp_status msp_solve_batched(void* stream, int32_t nsys, const msp_sy
       d.aln_m = aligned16(P->Minv, P->s, 8) && aligned16(L.H[i], P->s, 8);
       d.team = L.team + q;  // records in launch order: helpers scan the largest systems first
       d.cpart = L.cpart[i];
+      d.ypart = L.ypart[i];
       d.id = i;
       hs[q] = d;
     }

@@ -11,13 +11,16 @@
 // whose systems are finished join as helpers and claim slices of its row chunks.
 struct BatchTeam {
   int32_t epoch, nslice, mode, finish;
-  int32_t joined, started, pad[2];
+  int32_t joined, started, ncols, pad;
   int32_t claim[MSP_BATCH_MAXH + 1];  // slice s claimed for epoch claim[s]
   int32_t done[MSP_BATCH_MAXH + 1];   // slice s completed for epoch done[s]
-  const double* x;    // the vector of the sweep (FP64)
-  const double* rhs;  // mode 2: right-hand side
-  double* out;        // output rows
-  int64_t ldr;
+  // the published job: 0 q = (A_lo + lam I) x, 1 q = (A_hi + lam I) x, 2 out = rhs - (A_hi +
+  // lam I) x, 3 out = (rhs - Y x) lam (x s-vectors), 4 chunk partials of Y^T rhs
+  const void* bv;     // x in the arithmetic type of the product
+  const double* x;
+  const double* rhs;
+  double* out;
+  int64_t ldb, ldr;
   double lam;
 };
 
@@ -41,6 +44,7 @@ struct BatchSys {
   int32_t aln_lo, aln_hi, aln_y, aln_m;  // rows of A_lo / A_hi / Y / the s x s matrices are 16-byte aligned
   BatchTeam* team;    // cooperation record
   double* cpart;      // per-chunk partials of <x, A x>: [ceil(n / MSP_BATCH_CHR)][MSP_BATCH_KMAX]
+  double* ypart;      // per-chunk partials of Y^T r: [ceil(n / MSP_BATCH_CHR)][MSP_BATCH_KMAX][s]
   int32_t id;         // position in the caller's array
   int32_t pad;
 };
