@@ -22,8 +22,8 @@
 // Teams. One compute unit streams only about 1/256 of the chip's bandwidth, so a batch
 // is bound by its largest systems. A workgroup whose system is finished joins a larger
 // unfinished one as a helper: the system's workgroup (the leader) publishes every A-sweep
-// as an epoch in the system's team record, and the row range is cut into 1024-row chunks
-// handed out as slices. Every chunk writes its own <x, A x> partials and the leader adds
+// as an epoch in the system's team record, and the row range is cut into 512-row chunks
+// handed out as slices (the Y^T r and Y y passes of SolveM1 are team jobs too). Every chunk writes its own <x, A x> partials and the leader adds
 // them in chunk order, so the result is the same bits whoever computed which chunk. All
 // waits are bounded by wall-clock time: a slice that no helper claims in time is taken
 // by the leader, and an idle helper leaves.
@@ -38,9 +38,10 @@ constexpr int NW = 16;           // wavefronts per workgroup
 constexpr int NTB = NW * WAVE;   // 1024 threads
 constexpr int KB = MSP_BATCH_KMAX;
 constexpr int MAX_RESTARTS = 8;
-constexpr int CHR = MSP_BATCH_CHR;  // rows per chunk: NW wavefronts x one 64-row tile
+constexpr int CRT = 2;              // 16-row MFMA tiles per wavefront and chunk
+constexpr int CHR = MSP_BATCH_CHR;  // rows per chunk: NW wavefronts x one 32-row tile
 constexpr int MAXH = MSP_BATCH_MAXH;
-static_assert(CHR == NW * 64, "a chunk is one 64-row tile per wavefront");
+static_assert(CHR == NW * 16 * CRT, "a chunk is one tile row set per wavefront");
 // wall-clock (100 MHz) bounds of the team waits
 constexpr uint64_t CLAIM_TICKS = 10000;       // 100 us: a live helper claims its slice sooner
 constexpr uint64_t SLICE_TICKS = 500000000;   // 5 s: a claimed slice must be done by then
@@ -368,17 +369,17 @@ template <class TA, class TC>
 __device__ void sweep_chunks(const Job& J, int ch0, int ch1, double* part /*LDS NW*KB*/) {
   const int w = wave_id(), lane = lane_id(), i = lane & 15, g = lane >> 4;
   for (int ch = ch0; ch < ch1; ++ch) {
-    const int r0 = ch * CHR + w * 64;
+    const int r0 = ch * CHR + w * 16 * CRT;
     double pq = 0.0;
     if (r0 < J.n) {
-      typename V4<TC>::t acc[4];
+      typename V4<TC>::t acc[CRT];
       if (J.aln)
-        mm_rows<TA, TC, 4, true, true>((const TA*)J.A, J.lda, J.n, J.ncols, r0, (const TC*)J.Bv, J.ldb, J.k, acc);
+        mm_rows<TA, TC, CRT, true, true>((const TA*)J.A, J.lda, J.n, J.ncols, r0, (const TC*)J.Bv, J.ldb, J.k, acc);
       else
-        mm_rows<TA, TC, 4, false, true>((const TA*)J.A, J.lda, J.n, J.ncols, r0, (const TC*)J.Bv, J.ldb, J.k, acc);
+        mm_rows<TA, TC, CRT, false, true>((const TA*)J.A, J.lda, J.n, J.ncols, r0, (const TC*)J.Bv, J.ldb, J.k, acc);
       if (i < J.k) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < CRT; ++t)
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int row = r0 + 16 * t + out_row<TC>(g, e);
@@ -416,17 +417,18 @@ template <class TY>
 __device__ void yz_chunks(const Job& J, int ch0, int ch1) {
   const int w = wave_id(), lane = lane_id(), i = lane & 15, g = lane >> 4;
   for (int ch = ch0; ch < ch1; ++ch) {
-    const int r0 = ch * CHR + w * 64;
+    const int r0 = ch * CHR + w * 16 * CRT;
     if (r0 >= J.n) continue;
-    v4d acc[4];
+    v4d acc[CRT];
     if (J.aln)
-      mm_rows<TY, double, 4, true, false>((const TY*)J.A, J.lda, J.n, J.ncols, r0, (const double*)J.Bv, J.ldb, J.k, acc);
+      mm_rows<TY, double, CRT, true, false>((const TY*)J.A, J.lda, J.n, J.ncols, r0, (const double*)J.Bv, J.ldb, J.k,
+                                            acc);
     else
-      mm_rows<TY, double, 4, false, false>((const TY*)J.A, J.lda, J.n, J.ncols, r0, (const double*)J.Bv, J.ldb, J.k,
-                                           acc);
+      mm_rows<TY, double, CRT, false, false>((const TY*)J.A, J.lda, J.n, J.ncols, r0, (const double*)J.Bv, J.ldb, J.k,
+                                             acc);
     if (i < J.k) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < CRT; ++t)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int row = r0 + 16 * t + out_row<double>(g, e);
@@ -642,7 +644,7 @@ struct Batch {
     run_job<TLO, THI, TY>(c, J);
   }
 
-  // b2 = Y^T r1 from chunk partials (each 1024 rows: 16-column tiles of Y as MFMA rows, the
+  // b2 = Y^T r1 from chunk partials (each 512 rows: 16-column tiles of Y as MFMA rows, the
   // chunk's rows as the reduction), added in chunk order
   static __device__ void yt_r(Ctx& c) {
     PhaseTimer tm(c, BT_YT);

@@ -4,7 +4,7 @@
 
 #define MSP_BATCH_KMAX 16  // right-hand sides per launch (the N dimension of the 16x16 tiles)
 #define MSP_BATCH_MAXH 31  // helper workgroups per system
-#define MSP_BATCH_CHR 1024 // rows per sweep chunk (16 wavefronts x 64-row tiles)
+#define MSP_BATCH_CHR 512  // rows per sweep chunk (16 wavefronts x 32-row tiles)
 
 // Cooperation record of one system (device memory, zeroed before the launch). The
 // system's own workgroup (the leader) publishes each A-sweep as an epoch; workgroups
