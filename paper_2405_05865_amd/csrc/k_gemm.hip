@@ -265,11 +265,13 @@ __global__ void __launch_bounds__(WAVE) k_gemm_sum(const double* __restrict__ pa
   }
 }
 
-// segments of the reduction range: double until the launch has about 32 wavefronts per
-// CU, each segment keeps >= 1024 columns and the partials fit the scratch
+// segments of the reduction range: double until the launch has about 8 wavefronts per CU
+// (measured at n = 32768, 16 RHS: 2048 wavefronts stream faster than 8192 once every step
+// reads whole cache lines), each segment keeps >= 1024 columns and the partials fit the
+// scratch
 int gemm_segments(int64_t rows, int64_t cols, int k, int64_t waves, size_t scratch_doubles) {
   int nseg = 1;
-  while (waves * nseg < 8192 && nseg < 64 && cols / (2 * nseg) >= 1024 &&
+  while (waves * nseg < 2048 && nseg < 64 && cols / (2 * nseg) >= 1024 &&
          (size_t)(2 * nseg) * (size_t)k * (size_t)rows <= scratch_doubles)
     nseg *= 2;
   return nseg;
