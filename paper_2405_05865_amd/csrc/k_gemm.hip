@@ -468,6 +468,12 @@ hipError_t launch_gemm_t(hipStream_t st, const void* A, msp_dtype a_t, int64_t r
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_gemm_t_f32_as_f64(hipStream_t st, const float* A, int64_t rows, int64_t cols, int64_t lda,
+                                    const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
+                                    const int32_t* skip, double* part) {
+  return gemmT_t<float, double, 2>(st, A, rows, cols, lda, X, ldx, Y, ldy, (int)k, skip, part);
+}
+
 hipError_t launch_gemm_split(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows,
                              int64_t cols, int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
                              double lam, bool diag, const int32_t* skip, double* dot_part, int* nblocks,

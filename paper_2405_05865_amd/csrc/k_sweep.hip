@@ -331,6 +331,12 @@ hipError_t launch_gemv_f32_as_f64(hipStream_t st, const float* A, int64_t rows, 
                                   nblocks);
 }
 
+hipError_t launch_gemv_t_f32_as_f64(hipStream_t st, const float* A, int64_t rows, int64_t cols, int64_t lda,
+                                    const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
+                                    const int32_t* skip, double* part) {
+  return gemvT_k<float, double, 4>(st, A, rows, cols, lda, X, ldx, Y, ldy, (int)k, skip, part);
+}
+
 size_t gemv_t_part_doubles(int64_t rows, int64_t cols, int64_t k) { return (size_t)64 * cols * k + 1024; }
 
 hipError_t launch_gemv_t(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,

@@ -405,6 +405,10 @@ struct SolveCtx {
   int64_t n, m, s, k;
   const void* A_sw;  // matrix swept inside MSP
   msp_dtype sw_t;
+  // general path on an FP32-stored A_sw: its sweeps accumulate in FP64, since the
+  // normal-equation operator A^T A squares A's condition number and FP32 sums would
+  // bury its smallest directions
+  bool sw64 = false;
   const void* A_cf;  // matrix of the confirmation / refinement residuals (FP64 arithmetic)
   msp_dtype cf_t;
   int64_t lda;
@@ -599,6 +603,7 @@ msp_status sweep(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t 
   if (timed) TRY(ev_begin(c, &stop));
   hipError_t e;
   const double lam = (A == c.A_sw) ? c.lam_sw : c.lam;
+  fp64 = fp64 || (c.sw64 && A == c.A_sw);
   // the level-1 operator of a symmetric A from its lower triangle
   const bool sym = c.sympart && A == c.A_sw && !fp64 && rows == cols && symv_supported(A, t, c.lda, c.k);
   if (sym)
@@ -623,13 +628,26 @@ msp_status sweep(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t 
 // Y = A^T X for A rows x cols (X length rows, Y length cols)
 msp_status sweep_t(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t cols, const double* X, int64_t ldx,
                    double* Y, int64_t ldy, const int32_t* skip) {
-  if (c.k >= kGemmMinK)
+  if (c.sw64 && A == c.A_sw && t == MSP_F32)
+    MSP_CHECK_HIP((c.k >= kGemmMinK ? launch_gemm_t_f32_as_f64 : launch_gemv_t_f32_as_f64)(
+        c.st, (const float*)A, rows, cols, c.lda, X, ldx, Y, ldy, c.k, skip, c.gpart));
+  else if (c.k >= kGemmMinK)
     MSP_CHECK_HIP(launch_gemm_t(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k, skip, c.gpart));
   else
     MSP_CHECK_HIP(launch_gemv_t(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k, skip, c.gpart));
   c.acc.sweeps += 1;
   c.acc.sweep_bytes += (double)rows * (double)cols * (double)dsize(t);
   return MSP_OK;
+}
+
+// Y = A^T X in FP64 arithmetic whatever A's storage (the residuals of the normal equations)
+hipError_t sweep_t64(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t cols, const double* X,
+                     int64_t ldx, double* Y, int64_t ldy) {
+  if (t == MSP_F32)
+    return (c.k >= kGemmMinK ? launch_gemm_t_f32_as_f64 : launch_gemv_t_f32_as_f64)(
+        c.st, (const float*)A, rows, cols, c.lda, X, ldx, Y, ldy, c.k, nullptr, c.gpart);
+  return (c.k >= kGemmMinK ? launch_gemm_t : launch_gemv_t)(c.st, A, t, rows, cols, c.lda, X, ldx, Y, ldy, c.k,
+                                                            nullptr, c.gpart);
 }
 
 L2Step l2step_for(SolveCtx& c, Level& L, const double* Minv, const double* W, double wscale, double sigma,
@@ -817,7 +835,10 @@ msp_status build_explicit(SolveCtx& c) {
   int nb = 0;
   MSP_CHECK_HIP(launch_transpose_f64(c.st, P->Y, P->y_t, m, s, P->ldy, c.Act, m));
   // B^T rows: (A^T A~)[:, j] = A^T (A~ e_j), the block transposed product with s columns
-  if (s >= kGemmMinK)
+  if (s >= kGemmMinK && c.sw64)
+    MSP_CHECK_HIP(launch_gemm_t_f32_as_f64(c.st, (const float*)c.A_sw, m, n, c.lda, c.Act, m, c.B2t, n, s, nullptr,
+                                           c.gtmp));
+  else if (s >= kGemmMinK)
     MSP_CHECK_HIP(launch_gemm_t(c.st, c.A_sw, c.sw_t, m, n, c.lda, c.Act, m, c.B2t, n, s, nullptr, c.gtmp));
   else
     MSP_CHECK_HIP(launch_gemv_t(c.st, c.A_sw, c.sw_t, m, n, c.lda, c.Act, m, c.B2t, n, s, nullptr, c.gpart));
@@ -1061,8 +1082,7 @@ msp_status gen_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int m
       if (normal) {
         // rtrue = B - (A^T A + lam I) x
         TRY(sweep(c, c.A_cf, c.cf_t, m, n, L.x, n, c.tvec, m, false, nullptr, false, true, false));
-        MSP_CHECK_HIP((k >= kGemmMinK ? launch_gemm_t : launch_gemv_t)(c.st, c.A_cf, c.cf_t, m, n, c.lda, c.tvec, m,
-                                                                        L.q, n, k, nullptr, c.gpart));
+        MSP_CHECK_HIP(sweep_t64(c, c.A_cf, c.cf_t, m, n, c.tvec, m, L.q, n));
         if (c.lam != 0.0) MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, L.q, n, c.lam, L.x, n, L.q, n, nullptr));
         MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, B, ldb, -1.0, L.q, n, L.q, n, nullptr));
         MSP_CHECK_HIP(fcg_confirm(c.st, L.S, n, L.q, L.r, tol, c.relres, c.df + SLOT_L1));
@@ -1117,8 +1137,7 @@ msp_status hi_residual(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const doub
     MSP_CHECK_HIP(launch_axpby(c.st, m, k, 1.0, B, ldb, -1.0, out, m, out, m, nullptr));
   } else {
     TRY(sweep(c, A_hi, hi_t, m, n, c.xh, n, c.tvec, m, false, nullptr, false, true, false));
-    MSP_CHECK_HIP((k >= kGemmMinK ? launch_gemm_t : launch_gemv_t)(c.st, A_hi, hi_t, m, n, c.lda, c.tvec, m, out, n,
-                                                                    k, nullptr, c.gpart));
+    MSP_CHECK_HIP(sweep_t64(c, A_hi, hi_t, m, n, c.tvec, m, out, n));
     if (c.lam != 0.0) MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, out, n, c.lam, c.xh, n, out, n, nullptr));
     MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, B, ldb, -1.0, out, n, out, n, nullptr));
   }
@@ -1301,6 +1320,7 @@ msp_status make_ctx(SolveCtx& c, void* stream, const msp_precond* P, const void*
   c.k = k;
   c.A_sw = A_lo;
   c.sw_t = lo_t;
+  c.sw64 = P->structure == MSP_GENERAL && lo_t == MSP_F32;
   c.A_cf = A_hi;
   c.cf_t = hi_t;
   c.lda = lda;

@@ -123,6 +123,13 @@ size_t gemv_t_part_doubles(int64_t rows, int64_t cols, int64_t k);
 hipError_t launch_gemv_t(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,
                          const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip,
                          double* part);
+// both transposed products with FP64 arithmetic on an FP32-stored A (same contracts)
+hipError_t launch_gemm_t_f32_as_f64(hipStream_t st, const float* A, int64_t rows, int64_t cols, int64_t lda,
+                                    const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
+                                    const int32_t* skip, double* part);
+hipError_t launch_gemv_t_f32_as_f64(hipStream_t st, const float* A, int64_t rows, int64_t cols, int64_t lda,
+                                    const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
+                                    const int32_t* skip, double* part);
 
 // ---------------------------------------------------------------------------------
 // Tall-skinny kernels on Y (n x s) and reductions (k_tall.hip)
