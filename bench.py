@@ -116,7 +116,8 @@ def main():
                          "F32 RBF systems x 16 right-hand sides in one batched launch; general_outlier_n65536: "
                          "the three-level solve of A x = b, n=65536, 8 right-hand sides")
     ap.add_argument("--count", type=int, default=None, help="batched: number of systems (default 256)")
-    ap.add_argument("--lo", default="f32", choices=["f32", "bf16"], help="batched: sweep precision inside MSP")
+    ap.add_argument("--lo", default="f32", choices=["f32", "bf16", "f64"],
+                    help="batched (f32, bf16) and general (f32, f64): sweep precision inside MSP")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="batched: skip the timed adjoint pass (forward plus adjoint under L = sum |X|^2)")
     ap.add_argument("--fp64-sample", type=int, default=4,
@@ -277,7 +278,9 @@ def bench_general(args):
     t = time.time()
     sv, u_vs, v_vs = W.general_outlier_factors(n, w.extra["k"] if args.n is None else max(8, n // 64), w.config_id)
     A = assemble_householder(u_vs, sv, v_vs, dev)
-    A32 = A.float()
+    if args.lo == "bf16":
+        raise SystemExit("general workload: --lo must be f32 or f64")
+    A32 = A.float() if args.lo == "f32" else A
     B = torch.from_numpy(W.gaussian((w.nrhs, n), w.config_id)).to(dev)
     torch.cuda.synchronize()
     ev = np.sort(sv)[::-1] ** 2  # eigenvalues of A^T A
@@ -315,11 +318,13 @@ def bench_general(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"general_outlier_n{n}", "n": n, "s": s, "phi": phi, "gamma": w.gamma,
                    "nrhs": w.nrhs, "lambda": 0.0, "lambda0": lam0, "tol": w.tol, "matrix": "f64",
-                   "sweeps": "f32", "refinement": "fp64", "level2_form": args.level2_form, "levels": 3},
+                   "matrix_in_msp": args.lo, "sweep_arithmetic": "f64",
+                   "refinement": "fp64" if args.lo == "f32" else "none",
+                   "level2_form": args.level2_form, "levels": 3},
         "outer_iters": info["outer_iters"],
         "inner_iters": info["inner_iters"],
         "level3_iters": info["level3_iters"],

@@ -1,10 +1,9 @@
 // Inner flexible-PCG iterations with an explicit s x s operator, one kernel per step.
 //
 // Under level2_form 1 the level-2 solve of Algorithm 2 applies the formed operator
-// H = C^T C + lam~ W with the preconditioner M2^{-1}, and each level-3 solve of
-// Algorithm 5 applies H = A~^T A~ + sigma I with M3a^{-1} or M3b^{-1}. Both H and Minv are
-// fixed, so with G = H Minv (formed once per solve) the operator image of the direction
-// follows from the residual:
+// H = C^T C + lam~ W with the preconditioner M2^{-1}. Both H and Minv are fixed, so with
+// G = H Minv (formed once per solve) the operator image of the direction follows from the
+// residual:
 //   z_t = Minv r_t,   p_t = z_t + beta_t p_{t-1},   u_t = H p_t = G r_t + beta_t u_{t-1}.
 // A step then needs one pass over the rows of [Minv; G] with r_{t+1}; everything else is
 // s-length vector work. Every block evaluates the s-length dots of the step redundantly,
@@ -18,6 +17,9 @@
 // beta is the flexible (Polak-Ribiere) choice <z_t, r_t - r_{t-1}> / <z_{t-1}, r_{t-1}>,
 // with r_t - r_{t-1} = -alpha_{t-1} u_{t-1}. The stop rule is the one of the other inner
 // kernels: |r| <= tol |b| on the recurrence residual, breakdown, or the iteration cap.
+// The recurrence for u is exact only in exact arithmetic: with H and Minv as ill-conditioned
+// as the general level-3 matrices (A~^T A~, whose spread is kappa(A)^2) u drifts from H p
+// and the iterate stalls far above the tolerance, so those solves keep direct products.
 #include "msp_internal.h"
 
 namespace {

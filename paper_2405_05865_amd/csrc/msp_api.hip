@@ -431,8 +431,6 @@ struct SolveCtx {
   bool use_x = false;
   L2xArgs X{};
   double* G2 = nullptr;                      // PSD: H2 M2^{-1}
-  double *G3a = nullptr, *G3b = nullptr;     // general: A~^T A~ M3a^{-1}, (A~^T A~ + lam~ I) M3b^{-1}
-  double* Hs = nullptr;                      // general: A~^T A~ + lam~ I
   int32_t* hf;
   int32_t* df;
   int last_inner = 4, last_l3a = 4, last_l3b = 4;
@@ -491,19 +489,18 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
       gtmp = w.take<double>(gemm_t_part_doubles(m, n, s));
     }
   }
-  // the one-kernel inner step (level2_form 1, block of at most kL2xMaxK columns)
-  const bool use_x = form == 1 && s >= kGemmMinK && s <= kL2xMaxS && k <= kL2xMaxK;
+  // the one-kernel inner step (level2_form 1, block of at most kL2xMaxK columns). PSD only:
+  // the step carries u = H p by the recurrence u_t = G r_t + beta u_{t-1} with G = H M^{-1},
+  // which is exact in exact arithmetic but drifts from H p when H and M are as
+  // ill-conditioned as the general level-3 matrices (A~^T A~ with kappa(A)^2 spread): there
+  // the recurrence iterate stalls near 1e-4 relative error where direct products reach
+  // 1e-7, and the outer levels take about three times the oracle's steps
+  const bool use_x = form == 1 && P->structure == MSP_SYM_PSD && s >= kGemmMinK && s <= kL2xMaxS && k <= kL2xMaxK;
   L2xArgs X{};
-  double *G2 = nullptr, *G3a = nullptr, *G3b = nullptr, *Hs = nullptr;
+  double* G2 = nullptr;
   if (use_x) {
     X = l2x_carve(w, s, k);
-    if (P->structure == MSP_SYM_PSD) {
-      G2 = w.take<double>(s * s);
-    } else {
-      G3a = w.take<double>(s * s);
-      G3b = w.take<double>(s * s);
-      Hs = w.take<double>(s * s);
-    }
+    G2 = w.take<double>(s * s);
   }
   // the lower-triangle level-1 sweep (PSD, one right-hand side)
   double* sympart = nullptr;
@@ -518,9 +515,6 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
     c->use_x = use_x;
     c->X = X;
     c->G2 = G2;
-    c->G3a = G3a;
-    c->G3b = G3b;
-    c->Hs = Hs;
     c->Htmp = Htmp;
     c->Hscal = Hscal;
     c->Hstat = Hstat;
@@ -845,11 +839,6 @@ msp_status build_explicit(SolveCtx& c) {
   MSP_CHECK_HIP(launch_gemm(c.st, c.Act, MSP_F64, false, s, m, m, c.Act, m, c.H3, s, s, 0.0, false, nullptr, nullptr,
                             &nb));
   MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H3, 0.0, nullptr, 0.0, c.H3));
-  if (c.use_x) {
-    MSP_CHECK_HIP(launch_combine_sym(c.st, s, 1.0, c.H3, 0.0, nullptr, P->lt, c.Hs));
-    TRY(form_g(c, c.H3, P->Minv, c.G3a));
-    TRY(form_g(c, c.Hs, P->Minv2, c.G3b));
-  }
   if (c.form == 2) {  // the one-level variant needs the level-2 matrix itself
     MSP_CHECK_HIP(launch_gemm(c.st, c.B2t, MSP_F64, false, s, n, n, c.B2t, n, c.H2, s, s, 0.0, false, nullptr,
                               nullptr, &nb));
@@ -945,21 +934,6 @@ msp_status gen_level3(SolveCtx& c, const double* rhs, double* out, double sigma,
                       const int32_t* parent_done, int* last) {
   L2Step a = l2step_for(c, c.L3, Minv, nullptr, 0.0, sigma, c.o->level3_tol, c.o->max_level3, SLOT_L3, parent_done);
   a.rhs = rhs;
-  if (c.use_x) {  // one kernel per step through G = (A~^T A~ + sigma I) Minv; y is out
-    L2xArgs x = c.X;
-    x.Minv = Minv;
-    x.G = (Minv == c.P->Minv2) ? c.G3b : c.G3a;
-    x.y = out;
-    x.tol = c.o->level3_tol;
-    x.max_iter = c.o->max_level3;
-    x.mirror = c.df + SLOT_L3;
-    x.parent_done = parent_done;
-    a.r = x.r[0];
-    a.y = out;
-    MSP_CHECK_HIP(l2_rhs(c.st, a));
-    TRY(run_l2x(c, x, SLOT_L3, last, &c.acc.level3_iters));
-    return MSP_OK;
-  }
   if (c.form == 1) {  // (A~^T A~ + sigma I) through the explicit A~^T A~
     a.nbC = 0;
     a.wscale = 1.0;
