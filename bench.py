@@ -243,22 +243,6 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def assemble_householder(u_vs, diag, v_vs, dev):
-    """U diag(d) V^T (U, V products of Householder reflections) on the GPU, by the same
-    rank-one updates as the host recipe of workloads.general_outlier (input preparation)."""
-    import torch
-    n = diag.shape[0]
-    A = torch.zeros((n, n), dtype=torch.float64, device=dev)
-    A.diagonal().copy_(torch.from_numpy(diag).to(dev))
-    for r in range(len(v_vs) - 1, -1, -1):
-        v = torch.from_numpy(v_vs[r]).to(dev)
-        A.addr_(torch.mv(A, v), v, alpha=-2.0)
-    for r in range(len(u_vs) - 1, -1, -1):
-        u = torch.from_numpy(u_vs[r]).to(dev)
-        A.addr_(u, torch.mv(A.t(), u), alpha=-2.0)
-    return A
-
-
 def bench_general(args):
     """A x = b through the three-level method (Algorithms 3-5): A = U diag(sv) V^T,
     n = 65536, 1024 singular values 10^U(3,6), the rest U(1,10); 8 right-hand sides;
@@ -277,7 +261,7 @@ def bench_general(args):
     msp.library()
     t = time.time()
     sv, u_vs, v_vs = W.general_outlier_factors(n, w.extra["k"] if args.n is None else max(8, n // 64), w.config_id)
-    A = assemble_householder(u_vs, sv, v_vs, dev)
+    A = W.outer_product_on_device(u_vs, sv, v_vs, dev)
     if args.lo == "bf16":
         raise SystemExit("general workload: --lo must be f32 or f64")
     A32 = A.float() if args.lo == "f32" else A

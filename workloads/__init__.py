@@ -16,6 +16,9 @@ from .generators import (  # noqa: F401
     general_outlier,
     general_outlier_factors,
     householder_apply,
+    outer_product_on_device,
+    outer_product_row,
+    outer_product_apply,
     schatten_psd,
     schatten_psd_factors,
     batched_rbf_sizes,

@@ -177,6 +177,36 @@ def general_outlier_factors(n: int, k: int, config_id: int, reflections: int = 8
     return sv, u_vs, v_vs
 
 
+def outer_product_on_device(u_vs, diag, v_vs, device):
+    """U diag(d) V^T on a torch device (FP64) by the rank-one updates of
+    _outer_product_matrix, for sizes the host cannot assemble quickly."""
+    import torch
+    n = diag.shape[0]
+    a = torch.zeros((n, n), dtype=torch.float64, device=device)
+    a.diagonal().copy_(torch.from_numpy(np.ascontiguousarray(diag)).to(device))
+    for r in range(len(v_vs) - 1, -1, -1):
+        v = torch.from_numpy(np.ascontiguousarray(v_vs[r])).to(device)
+        a.addr_(torch.mv(a, v), v, alpha=-2.0)
+    for r in range(len(u_vs) - 1, -1, -1):
+        u = torch.from_numpy(np.ascontiguousarray(u_vs[r])).to(device)
+        a.addr_(u, torch.mv(a.t(), u), alpha=-2.0)
+    return a
+
+
+def outer_product_row(u_vs, diag, v_vs, i: int) -> np.ndarray:
+    """Row i of U diag(d) V^T from the factors: ((U^T e_i) * d)^T V^T."""
+    e = np.zeros(diag.shape[0])
+    e[i] = 1.0
+    return householder_apply(v_vs, diag * householder_apply(u_vs, e, transpose=True))
+
+
+def outer_product_apply(u_vs, diag, v_vs, x: np.ndarray) -> np.ndarray:
+    """U diag(d) V^T x from the factors (x of shape (n,) or (n, k))."""
+    y = householder_apply(v_vs, x, transpose=True)
+    y = diag * y if y.ndim == 1 else diag[:, None] * y
+    return householder_apply(u_vs, y)
+
+
 def general_outlier(n: int, k: int, config_id: int, reflections: int = 8,
                     big=(1e3, 1e6), small=(1.0, 10.0)):
     """Nonsymmetric A = U diag(sv) V^T with U, V products of Householder reflections,
