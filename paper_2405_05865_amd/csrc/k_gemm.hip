@@ -267,11 +267,11 @@ __global__ void __launch_bounds__(WAVE) k_gemm_sum(const double* __restrict__ pa
 
 // segments of the reduction range: double until the launch has about 8 wavefronts per CU
 // (measured at n = 32768, 16 RHS: 2048 wavefronts stream faster than 8192 once every step
-// reads whole cache lines), each segment keeps >= 1024 columns and the partials fit the
+// reads whole cache lines), each segment keeps >= min_seg columns and the partials fit the
 // scratch
-int gemm_segments(int64_t rows, int64_t cols, int k, int64_t waves, size_t scratch_doubles) {
+int gemm_segments(int64_t rows, int64_t cols, int k, int64_t waves, size_t scratch_doubles, int min_seg) {
   int nseg = 1;
-  while (waves * nseg < 2048 && nseg < 64 && cols / (2 * nseg) >= 1024 &&
+  while (waves * nseg < 2048 && nseg < 64 && cols / (2 * nseg) >= min_seg &&
          (size_t)(2 * nseg) * (size_t)k * (size_t)rows <= scratch_doubles)
     nseg *= 2;
   return nseg;
@@ -280,12 +280,12 @@ int gemm_segments(int64_t rows, int64_t cols, int k, int64_t waves, size_t scrat
 template <class TA, class TC, int RT, int KT>
 hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X,
                   int64_t ldx, double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip,
-                  double* dot_part, int* nblocks, double* scratch, size_t scratch_doubles) {
+                  double* dot_part, int* nblocks, double* scratch, size_t scratch_doubles, int min_seg) {
   static_assert(16 * RT == WAVE, "the segment sum takes 64-row sets");
   const int nrs = (int)((rows + 16 * RT - 1) / (16 * RT));
   const int ngroups = (k + 15) / 16;
   const int ncs = (ngroups + KT - 1) / KT;
-  const int nseg = scratch ? gemm_segments(rows, cols, k, (int64_t)nrs * ncs, scratch_doubles) : 1;
+  const int nseg = scratch ? gemm_segments(rows, cols, k, (int64_t)nrs * ncs, scratch_doubles, min_seg) : 1;
   constexpr int STEP = 4 * 2 * Ld<TA, TC>::VEC;  // four lane groups x two 16-byte chunks
   const int seg_cols = (int)(((cols + nseg - 1) / nseg + STEP - 1) / STEP * STEP);
   const int64_t waves = (int64_t)nrs * ncs * nseg;
@@ -310,15 +310,15 @@ hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64
 template <class TA, class TC>
 hipError_t gemm_k(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X, int64_t ldx,
                   double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip, double* dot_part,
-                  int* nblocks, double* scratch, size_t scratch_doubles) {
+                  int* nblocks, double* scratch, size_t scratch_doubles, int min_seg = 1024) {
   if (k <= 16)
     return gemm_t<TA, TC, 4, 1>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
-                                scratch_doubles);
+                                scratch_doubles, min_seg);
   if (sizeof(TC) == 8 || k <= 32)
     return gemm_t<TA, TC, 4, 2>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
-                                scratch_doubles);
+                                scratch_doubles, min_seg);
   return gemm_t<TA, TC, 4, 4>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
-                              scratch_doubles);
+                              scratch_doubles, min_seg);
 }
 
 // Transposed block product Y[:, j] = A^T X[:, j] (A rows x cols row-major; the
@@ -504,3 +504,10 @@ hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_a
 }
 
 size_t gemm_split_doubles(int64_t rows, int64_t k) { return (size_t)16 * rows * k + 64; }
+
+hipError_t launch_gemm_seg(hipStream_t st, const double* M, int64_t rows, int64_t cols, const double* X,
+                           int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip, double* scratch,
+                           size_t scratch_doubles, int min_seg) {
+  return gemm_k<double, double>(st, M, rows, cols, cols, X, ldx, Y, ldy, (int)k, 0.0, false, skip, nullptr, nullptr,
+                                scratch, scratch_doubles, min_seg);
+}

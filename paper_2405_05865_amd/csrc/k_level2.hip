@@ -248,6 +248,7 @@ struct L2Args {
   int32_t* mirror;
   const int32_t* parent_done;
   const double* rhs;     // k_l2_init: given right-hand side (s x k) or null
+  int ndp;               // blocks of dot partials in dpart (read by k_l2_dir)
 };
 
 constexpr int NTU = 1024;  // 16 wavefronts
@@ -255,6 +256,10 @@ constexpr int NTU = 1024;  // 16 wavefronts
 __host__ __device__ inline int ngroups(int nbC) { return (nbC + GROUP - 1) / GROUP; }
 __host__ __device__ inline int ublocks(int s) { return (s + WAVE - 1) / WAVE; }
 __host__ __device__ inline int pblocks(int s) { return (s + 3) / 4; }
+__host__ __device__ inline int dblocks(int s) { return (s + 255) / 256; }
+
+// z = Minv r on the matrix cores (then k_l2_dots) instead of k_l2_prec
+inline bool mfma_prec(const L2Step& a) { return a.gscratch && a.k >= kGemmMinK && a.Minv; }
 
 // fixed-order parallel sum over count strided values, valid in every thread
 template <int NT>
@@ -315,6 +320,7 @@ __global__ void __launch_bounds__(NTU) k_l2_update(L2Args a) {
   for (int i = threadIdx.x; i < a.s; i += NTU) {
     const double pi = a.p[(int64_t)j * a.s + i];
     if (a.pqw) t = fma(a.wscale, a.pqw[(int64_t)j * a.s + i], t);
+    else if (a.wp) t = fma(a.wscale * pi, a.wp[(int64_t)j * a.s + i], t);
     t = fma(a.sigma * pi, pi, t);
   }
   const double pq = block_sum<NTU>(t, shs);
@@ -421,13 +427,66 @@ __global__ void __launch_bounds__(256) k_l2_prec(L2Args a, int decide) {
   }
 }
 
+// ---- after z = Minv r on the matrix cores: the decision of k_l2_prec for column
+// blockIdx.y and the partials of <z, r> and <z, r_old> over 256 rows per block
+__global__ void __launch_bounds__(256) k_l2_dots(L2Args a, int decide) {
+  __shared__ double sh[4];
+  __shared__ int live_sh;
+  const int j = blockIdx.y;
+  const int nu = ublocks(a.s);
+  if (threadIdx.x == 0) {
+    int dj = a.S.done[j];
+    int it = a.S.iters[j];
+    double sum = 0.0;
+    for (int b = 0; b < nu; ++b) sum += a.upart[(int64_t)b * a.k + j];
+    const double rn = sqrt(sum);
+    if (decide == 2) {
+      const bool pd = a.parent_done && a.parent_done[j];
+      dj = (pd || rn == 0.0) ? 1 : 0;
+      it = 0;
+      if (blockIdx.x == 0) {
+        a.S.bnorm[j] = rn;
+        a.S.rnorm[j] = rn;
+        a.S.rz[j] = 0.0;
+        a.S.beta[j] = 0.0;
+      }
+    } else if (dj == 0) {
+      ++it;
+      if (a.S.brk[j] || !(rn == rn)) dj = 2;
+      else if (rn <= a.tol * a.S.bnorm[j]) dj = 1;
+      else if (it >= a.max_iter) dj = 3;
+      if (blockIdx.x == 0) a.S.rnorm[j] = rn;
+    }
+    if (blockIdx.x == 0) {
+      a.S.done_next[j] = dj;
+      a.S.iters_next[j] = it;
+    }
+    live_sh = (dj == 0);
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double zr = 0.0, zro = 0.0;
+  if (live_sh && i < a.s) {
+    const int64_t o = (int64_t)j * a.s + i;
+    const double t = a.z[o];
+    zr = t * a.r[o];
+    zro = (decide == 2) ? 0.0 : t * a.ro[o];
+  }
+  const double s1 = block_sum<256>(zr, sh);
+  const double s2 = block_sum<256>(zro, sh);
+  if (threadIdx.x == 0) {
+    a.dpart[((int64_t)blockIdx.x * a.k + j) * 2 + 0] = s1;
+    a.dpart[((int64_t)blockIdx.x * a.k + j) * 2 + 1] = s2;
+  }
+}
+
 // ---- commit the decision; beta = <z, r - r_old> / rz ; rz = <r, z> ; p = z + beta p.
 // One block per column; the last block to finish publishes the active count and the
 // largest iteration count.
 __global__ void __launch_bounds__(256) k_l2_dir(L2Args a, int first) {
   __shared__ double shs[4];
   const int j = blockIdx.x;
-  const int np = pblocks(a.s);
+  const int np = a.ndp;
   const int dj = a.S.done_next[j];
   if (dj == 0) {
     const double zr = strided_sum<256>(a.dpart + (int64_t)j * 2 + 0, np, (int64_t)a.k * 2, shs);
@@ -573,6 +632,7 @@ L2Args make_args(const L2Step& a) {
   x.mirror = a.mirror;
   x.parent_done = a.parent_done;
   x.rhs = a.rhs;
+  x.ndp = mfma_prec(a) ? dblocks((int)a.s) : pblocks((int)a.s);
   return x;
 }
 
@@ -589,6 +649,14 @@ hipError_t prec_launch(hipStream_t st, const L2Step& a, int decide) {
   const int cpl = (int)((a.s + WAVE - 1) / WAVE);
   const unsigned blocks = (unsigned)pblocks((int)a.s);
   L2Args x = make_args(a);
+  if (mfma_prec(a)) {
+    // columns already done keep their z; at the first application every column is new
+    hipError_t e = launch_gemm_seg(st, a.Minv, a.s, a.s, a.r, a.s, a.z, a.s, a.k, decide == 2 ? nullptr : a.S.done,
+                                   a.gscratch, a.gscratch_n, kSegSmall);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_l2_dots, dim3((unsigned)dblocks((int)a.s), (unsigned)a.k), dim3(256), 0, st, x, decide);
+    return hipGetLastError();
+  }
   if (cpl <= 1) hipLaunchKernelGGL(k_l2_prec<1>, dim3(blocks), dim3(256), 0, st, x, decide);
   else if (cpl <= 2) hipLaunchKernelGGL(k_l2_prec<2>, dim3(blocks), dim3(256), 0, st, x, decide);
   else if (cpl <= 4) hipLaunchKernelGGL(k_l2_prec<4>, dim3(blocks), dim3(256), 0, st, x, decide);
@@ -636,7 +704,9 @@ hipError_t l2_op(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_
 // the inner operator through an explicit s x s matrix M: wp = M v and pqw = v .* (M v)
 // (the W-row part of the Y pass alone; steps built on it use nbC = 0)
 hipError_t l2_op_matrix(hipStream_t st, const double* M, int64_t s, const double* v, int64_t k, const int32_t* done,
-                        double* wp, double* pqw) {
+                        double* wp, double* pqw, double* scratch, size_t scratch_n) {
+  if (scratch && k >= kGemmMinK)
+    return launch_gemm_seg(st, M, s, s, v, s, wp, s, k, done, scratch, scratch_n, kSegSmall);
   const int cpl = (int)((s + WAVE - 1) / WAVE);
   const unsigned blocks = (unsigned)((s + 3) / 4);
   const int si = (int)s, ki = (int)k;

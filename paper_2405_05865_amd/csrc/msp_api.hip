@@ -669,22 +669,27 @@ L2Step l2step_for(SolveCtx& c, Level& L, const double* Minv, const double* W, do
   a.max_iter = max_iter;
   a.mirror = c.df + slotid;
   a.parent_done = parent_done;
+  a.gscratch = c.gemmpart;
+  a.gscratch_n = c.gemmpart_n;
   return a;
 }
 
 // iterations of an inner FCG on the sketch: chunk = predicted count, then pairs
 // M != null: the operator is the explicit s x s matrix M (a.nbC = 0, wscale = 1)
-msp_status run_l2(SolveCtx& c, const L2Step& a, const double* W, int slotid, int* last, int64_t* counter,
+msp_status run_l2(SolveCtx& c, const L2Step& a_in, const double* W, int slotid, int* last, int64_t* counter,
                   const double* M = nullptr) {
   const msp_precond* P = c.P;
   const int64_t rows = P->structure == MSP_SYM_PSD ? c.n : c.m;
+  L2Step a = a_in;
+  // an explicit operator on the matrix cores leaves <p, M p> to the step (no pqw)
+  if (M && a.gscratch && c.k >= kGemmMinK) a.pqw = nullptr;
   int issued = 0;
   int chunk = std::max(1, *last);
   const int cap = a.max_iter;
   while (true) {
     for (int i = 0; i < chunk && issued < cap; ++i, ++issued) {
       if (M)
-        MSP_CHECK_HIP(l2_op_matrix(c.st, M, c.s, a.p, c.k, a.S.done, a.wp, a.pqw));
+        MSP_CHECK_HIP(l2_op_matrix(c.st, M, c.s, a.p, c.k, a.S.done, a.wp, a.pqw, a.gscratch, a.gscratch_n));
       else
         MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, rows, c.s, P->ldy, a.p, c.s, c.k, a.S.done, a.part, a.pqpart, W,
                             a.wp, a.pqw, false));
@@ -769,7 +774,12 @@ msp_status run_l2x(SolveCtx& c, const L2xArgs& x, int slotid, int* last, int64_t
 msp_status dense_mv(SolveCtx& c, const double* M, int64_t rows, int64_t cols, const double* v, int64_t ldv,
                     double* out, int64_t ldo, const int32_t* skip) {
   int nb = 0;
-  if (c.k >= kGemmMinK)
+  if (c.k >= kGemmMinK && c.gemmpart) {
+    // short reduction segments pay for these few-row matrices; shortest while cache-resident
+    const int min_seg = (double)rows * (double)cols * 8.0 <= 64.0 * (1 << 20) ? kSegSmall : kSegWide;
+    MSP_CHECK_HIP(launch_gemm_seg(c.st, M, rows, cols, v, ldv, out, ldo, c.k, skip, c.gemmpart, c.gemmpart_n,
+                                  min_seg));
+  } else if (c.k >= kGemmMinK)
     MSP_CHECK_HIP(launch_gemm(c.st, M, MSP_F64, false, rows, cols, cols, v, ldv, out, ldo, c.k, 0.0, false, skip,
                               nullptr, &nb));
   else

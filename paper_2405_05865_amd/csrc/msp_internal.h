@@ -111,6 +111,16 @@ hipError_t launch_gemm_split(hipStream_t st, const void* A, msp_dtype a_t, bool 
                              int64_t cols, int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
                              double lam, bool diag, const int32_t* skip, double* dot_part, int* nblocks,
                              double* scratch, size_t scratch_doubles);
+// Y[:, j] = M X[:, j] for an FP64 row-major M (ld = cols) with few rows: the same
+// matrix-core product, its reduction range cut into segments of at least min_seg columns
+// until about 2048 wavefronts run (scratch of at least gemm_split_doubles(rows, k)
+// doubles). The level-1 sweep keeps min_seg = 1024 (long streams from HBM); the s x s
+// inner operators, which stay in cache, take 64; the s x n level-2 factor takes 256.
+hipError_t launch_gemm_seg(hipStream_t st, const double* M, int64_t rows, int64_t cols, const double* X,
+                           int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip, double* scratch,
+                           size_t scratch_doubles, int min_seg);
+constexpr int kSegSmall = 64;
+constexpr int kSegWide = 256;
 // Y[:, j] = A^T X[:, j] on the matrix cores for k >= kGemmMinK (same contract as
 // launch_gemv_t; part: gemv_t_part_doubles(rows, cols, k) doubles)
 size_t gemm_t_part_doubles(int64_t rows, int64_t cols, int64_t k);  // its split partials
@@ -246,6 +256,10 @@ struct L2Step {
   int32_t* mirror = nullptr;
   const int32_t* parent_done = nullptr;
   const double* rhs = nullptr; // l2_init: right-hand side given directly (s x k), else Y^T v partials
+  // with k >= kGemmMinK: z = Minv r (and an explicit operator's M p) as matrix-core block
+  // products through this scratch (gemm_split_doubles(s, k) doubles or more)
+  double* gscratch = nullptr;
+  size_t gscratch_n = 0;
 };
 int l2_blocks(int64_t n);
 size_t l2_bpart_doubles(int64_t s, int64_t k);
@@ -259,9 +273,11 @@ hipError_t l2_op(hipStream_t st, const void* Y, msp_dtype y_t, int64_t n, int64_
                  int64_t ldv, int64_t k, const int32_t* done, double* part, double* pqpart, const double* W,
                  double* wp, double* pqw, bool rhs_mode);
 // the same step input from an explicit s x s operator M (steps then run with nbC = 0 and
-// wscale = 1): wp = M p, pqw = p .* (M p)
+// wscale = 1): wp = M p, pqw = p .* (M p). With a scratch and k >= kGemmMinK, wp comes
+// from launch_gemm_seg and pqw is not written (the step then takes <p, M p> from wp
+// and must run with pqw = null)
 hipError_t l2_op_matrix(hipStream_t st, const double* M, int64_t s, const double* v, int64_t k, const int32_t* done,
-                        double* wp, double* pqw);
+                        double* wp, double* pqw, double* scratch, size_t scratch_n);
 // right-hand side (after l2_op in rhs mode): y = 0, r = rhs, |rhs|, z = Minv r, p = z
 hipError_t l2_init(hipStream_t st, const L2Step& a);
 // the first kernel of l2_init alone: y = 0, r = rhs (0 where parent_done)
