@@ -106,6 +106,9 @@ def main():
                     help="inner operator through the sketch each step (0) or through C^T C + lam~ W formed "
                          "once (1, default; the same iteration), or the one-level variant with SolveM1 solved "
                          "exactly through its inverse (2, a comparison, not the multi-level method)")
+    ap.add_argument("--autotune", type=int, default=0, choices=[0, 1],
+                    help="1: time the segment counts of the block sweep (--nrhs >= 8) before the first step "
+                         "and keep the fastest (cached per shape; MSP_TUNE_CACHE names a file to keep it in)")
     ap.add_argument("--max-outer", type=int, default=None,
                     help="cap the level-1 iterations (counter runs over a few sweeps only)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -174,7 +177,7 @@ def main():
         P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi)
         X, info = msp.solve(P, A, bt, tol=w.tol, inner_tol=args.inner_tol, profile=profile,
                             max_outer=args.max_outer, level2_form=args.level2_form, sym_sweep=args.sym_sweep,
-                            use_graph=args.use_graph)
+                            use_graph=args.use_graph, autotune=args.autotune)
         P.close()
         return X, info
 
@@ -217,7 +220,7 @@ def main():
         "config": {"workload": f"rbf_gp_n{w.n}_fp64_{K}rhs", "n": w.n, "s": w.s, "gamma": w.gamma, "phi": w.phi,
                    "lambda": w.lam, "lambda0": lam0, "tol": w.tol, "inner_tol": args.inner_tol, "nrhs": K,
                    "levels": 2, "level2_form": args.level2_form, "sym_sweep": args.sym_sweep,
-                   "use_graph": args.use_graph},
+                   "use_graph": args.use_graph, "autotune": args.autotune},
         "hbm_gbs_per_sweep": round(achieved, 1),
         "outer_iters": infos[-1]["outer_iters"],
         "inner_iters": infos[-1]["inner_iters"],
@@ -236,7 +239,8 @@ def main():
         flops = 2.0 * w.n * w.n * K
         line["block_sweep"] = {"flops_per_sweep": flops, "achieved_tflops": round(flops / (sweep_ms * 1e-3) / 1e12, 2),
                                "fp64_peak_tflops": 78.6,
-                               "arithmetic_intensity_flop_per_byte": round(flops / bytes_per_sweep, 3)}
+                               "arithmetic_intensity_flop_per_byte": round(flops / bytes_per_sweep, 3),
+                               "segments": infos[-1]["sweep_segments"]}
     if not args.no_cpu_baseline and K == 1:
         log("[bench] timing the CPU oracle (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(a, b, w, lam0, infos[-1]["outer_iters"], args.cpu_seconds)

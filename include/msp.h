@@ -182,6 +182,15 @@ typedef struct {
   int32_t batch_teams;     /* msp_solve_batched: a workgroup whose system is finished helps the
                               A-sweeps of a larger unfinished system (same results bit for bit;
                               chunked partials in a fixed order). Default 1. */
+  int32_t autotune;        /* k >= 8 (level-1 sweeps on the matrix cores): before the first step,
+                              time every admissible count of reduction segments (1..64) of the
+                              block sweep on A_lo and keep the fastest. Cached per (dtype,
+                              arithmetic, rows, cols, lda, k) for the process, and in the file
+                              named by the environment variable MSP_TUNE_CACHE (one JSON object
+                              per line) when set. The sweep's output scratch is overwritten
+                              while timing; results differ from the built-in choice only by
+                              summation order. Default 0 (built-in rule: about 2048
+                              wavefronts). */
 } msp_solve_opts;
 
 typedef struct {
@@ -197,6 +206,8 @@ typedef struct {
   int64_t sweeps;           /* number of passes over A (per block of k RHS) */
   double sweep_ms;          /* profile != 0: summed duration of the timed level-1 sweeps */
   int64_t timed_sweeps;     /* profile != 0: number of sweeps in sweep_ms */
+  int32_t sweep_segments;   /* k >= 8: reduction segments of the level-1 block sweep (tuned with
+                               autotune, else the built-in rule); 0 for the other sweeps */
 } msp_solve_info;
 
 void msp_solve_opts_default(msp_solve_opts* o /*host*/);

@@ -60,6 +60,7 @@ class SolveOpts(ctypes.Structure):
         ("sym_sweep", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("batch_teams", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
     ]
 
 
@@ -109,6 +110,7 @@ class SolveInfo(ctypes.Structure):
         ("sweeps", ctypes.c_int64),
         ("sweep_ms", ctypes.c_double),
         ("timed_sweeps", ctypes.c_int64),
+        ("sweep_segments", ctypes.c_int32),
     ]
 
     def as_dict(self):

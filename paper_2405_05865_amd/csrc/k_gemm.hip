@@ -280,12 +280,17 @@ int gemm_segments(int64_t rows, int64_t cols, int k, int64_t waves, size_t scrat
 template <class TA, class TC, int RT, int KT>
 hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X,
                   int64_t ldx, double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip,
-                  double* dot_part, int* nblocks, double* scratch, size_t scratch_doubles, int min_seg) {
+                  double* dot_part, int* nblocks, double* scratch, size_t scratch_doubles, int min_seg,
+                  int force_nseg) {
   static_assert(16 * RT == WAVE, "the segment sum takes 64-row sets");
   const int nrs = (int)((rows + 16 * RT - 1) / (16 * RT));
   const int ngroups = (k + 15) / 16;
   const int ncs = (ngroups + KT - 1) / KT;
-  const int nseg = scratch ? gemm_segments(rows, cols, k, (int64_t)nrs * ncs, scratch_doubles, min_seg) : 1;
+  // a forced count (the autotuner's) must fit the scratch; otherwise the built-in rule
+  const bool forced = force_nseg == 1 || (force_nseg > 1 && scratch &&
+                                          (size_t)force_nseg * (size_t)k * (size_t)rows <= scratch_doubles);
+  const int nseg = forced ? force_nseg
+                          : (scratch ? gemm_segments(rows, cols, k, (int64_t)nrs * ncs, scratch_doubles, min_seg) : 1);
   constexpr int STEP = 4 * 2 * Ld<TA, TC>::VEC;  // four lane groups x two 16-byte chunks
   const int seg_cols = (int)(((cols + nseg - 1) / nseg + STEP - 1) / STEP * STEP);
   const int64_t waves = (int64_t)nrs * ncs * nseg;
@@ -310,16 +315,19 @@ hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64
 template <class TA, class TC>
 hipError_t gemm_k(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X, int64_t ldx,
                   double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip, double* dot_part,
-                  int* nblocks, double* scratch, size_t scratch_doubles, int min_seg = 1024) {
+                  int* nblocks, double* scratch, size_t scratch_doubles, int min_seg = 1024, int force_nseg = 0) {
   if (k <= 16)
     return gemm_t<TA, TC, 4, 1>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
-                                scratch_doubles, min_seg);
+                                scratch_doubles, min_seg, force_nseg);
   if (sizeof(TC) == 8 || k <= 32)
     return gemm_t<TA, TC, 4, 2>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
-                                scratch_doubles, min_seg);
+                                scratch_doubles, min_seg, force_nseg);
   return gemm_t<TA, TC, 4, 4>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
-                              scratch_doubles, min_seg);
+                              scratch_doubles, min_seg, force_nseg);
 }
+
+// column groups per wavefront as gemm_k picks them (KT)
+int gemm_kt(int k, bool tc64) { return k <= 16 ? 1 : ((tc64 || k <= 32) ? 2 : 4); }
 
 // Transposed block product Y[:, j] = A^T X[:, j] (A rows x cols row-major; the
 // normal-equation operator of Algorithm 3). Lane l loads VEC consecutive columns
@@ -477,30 +485,39 @@ hipError_t launch_gemm_t_f32_as_f64(hipStream_t st, const float* A, int64_t rows
 hipError_t launch_gemm_split(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows,
                              int64_t cols, int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
                              double lam, bool diag, const int32_t* skip, double* dot_part, int* nblocks,
-                             double* scratch, size_t scratch_doubles) {
+                             double* scratch, size_t scratch_doubles, int nseg) {
   const int kk = (int)k;
   switch (a_t) {
     case MSP_F64:
       return gemm_k<double, double>(st, (const double*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam, diag, skip,
-                                    dot_part, nblocks, scratch, scratch_doubles);
+                                    dot_part, nblocks, scratch, scratch_doubles, 1024, nseg);
     case MSP_F32:
       if (fp64_arith)
         return gemm_k<float, double>(st, (const float*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam, diag, skip,
-                                     dot_part, nblocks, scratch, scratch_doubles);
+                                     dot_part, nblocks, scratch, scratch_doubles, 1024, nseg);
       return gemm_k<float, float>(st, (const float*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam, diag, skip, dot_part,
-                                  nblocks, scratch, scratch_doubles);
+                                  nblocks, scratch, scratch_doubles, 1024, nseg);
     case MSP_BF16:
       return gemm_k<__hip_bfloat16, float>(st, (const __hip_bfloat16*)A, rows, cols, lda, X, ldx, Y, ldy, kk, lam,
-                                           diag, skip, dot_part, nblocks, scratch, scratch_doubles);
+                                           diag, skip, dot_part, nblocks, scratch, scratch_doubles, 1024, nseg);
   }
   return hipErrorInvalidValue;
+}
+
+int gemm_split_default(int64_t rows, int64_t cols, int64_t k, msp_dtype a_t, bool fp64_arith,
+                       size_t scratch_doubles) {
+  const bool tc64 = a_t == MSP_F64 || (a_t == MSP_F32 && fp64_arith);
+  const int kt = gemm_kt((int)k, tc64);
+  const int64_t nrs = (rows + 63) / 64;
+  const int64_t ncs = (((k + 15) / 16) + kt - 1) / kt;
+  return gemm_segments(rows, cols, (int)k, nrs * ncs, scratch_doubles, 1024);
 }
 
 hipError_t launch_gemm(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows, int64_t cols,
                        int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
                        bool diag, const int32_t* skip, double* dot_part, int* nblocks) {
   return launch_gemm_split(st, A, a_t, fp64_arith, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part,
-                           nblocks, nullptr, 0);
+                           nblocks, nullptr, 0, 0);
 }
 
 size_t gemm_split_doubles(int64_t rows, int64_t k) { return (size_t)16 * rows * k + 64; }

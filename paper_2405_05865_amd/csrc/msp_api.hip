@@ -360,6 +360,7 @@ extern "C" void msp_solve_opts_default(msp_solve_opts* o) {
   o->sym_sweep = 1;
   o->use_graph = 0;
   o->batch_teams = 1;
+  o->autotune = 0;
 }
 
 
@@ -409,6 +410,7 @@ struct SolveCtx {
   // normal-equation operator A^T A squares A's condition number and FP32 sums would
   // bury its smallest directions
   bool sw64 = false;
+  int sweep_nseg = 0;  // segments of the level-1 block sweep over A_sw (0: built-in rule)
   const void* A_cf;  // matrix of the confirmation / refinement residuals (FP64 arithmetic)
   msp_dtype cf_t;
   int64_t lda;
@@ -604,7 +606,7 @@ msp_status sweep(SolveCtx& c, const void* A, msp_dtype t, int64_t rows, int64_t 
     e = launch_symv(c.st, A, t, rows, c.lda, X, Y, lam, diag, skip, c.sympart, parts ? c.gpart : nullptr, &nb);
   else if (c.k >= kGemmMinK)
     e = launch_gemm_split(c.st, A, t, fp64 && t == MSP_F32, rows, cols, c.lda, X, ldx, Y, ldy, c.k, lam, diag, skip,
-                          parts ? c.gpart : nullptr, &nb, c.gemmpart, c.gemmpart_n);
+                          parts ? c.gpart : nullptr, &nb, c.gemmpart, c.gemmpart_n, A == c.A_sw ? c.sweep_nseg : 0);
   else if (fp64 && t == MSP_F32)
     e = launch_gemv_f32_as_f64(c.st, (const float*)A, rows, cols, c.lda, X, ldx, Y, ldy, c.k, lam, diag, skip,
                                parts ? c.gpart : nullptr, &nb);
@@ -1232,6 +1234,30 @@ msp_status validate_solve(const msp_precond* P, const void* A_hi, msp_dtype hi_t
   return MSP_OK;
 }
 
+// segments of the level-1 block sweep over A_sw (k >= 8): the autotuner's choice, timed on
+// this matrix into scratch vectors, or the built-in rule's
+msp_status choose_segments(SolveCtx& c) {
+  if (c.k < kGemmMinK || !c.gemmpart) return MSP_OK;
+  const bool psd = c.P->structure == MSP_SYM_PSD;
+  const int64_t rows = psd ? c.n : c.m, cols = c.n;
+  const bool f64 = c.sw64;
+  if (c.o->autotune) {
+    // X = zeros (n x k), Y = a level-1 scratch of rows x k; both are rewritten before use
+    double* Xs = c.L1.p;
+    double* Ys = psd ? c.L1.q : c.tvec;
+    MSP_CHECK_HIP(hipMemsetAsync(Xs, 0, sizeof(double) * (size_t)cols * (size_t)c.k, c.st));
+    int nseg = 0;
+    MSP_CHECK_HIP(tune_block_sweep(c.st, c.A_sw, c.sw_t, f64, rows, cols, c.lda, Xs, cols, Ys, rows, c.k, c.gemmpart,
+                                   c.gemmpart_n, &nseg));
+    c.sweep_nseg = nseg;
+  } else {
+    c.sweep_nseg = 0;
+  }
+  c.acc.sweep_segments =
+      c.sweep_nseg > 0 ? c.sweep_nseg : gemm_split_default(rows, cols, c.k, c.sw_t, f64, c.gemmpart_n);
+  return MSP_OK;
+}
+
 // the whole solve into X; status from the residuals
 msp_status solve_into(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const double* B, int64_t ldb, double* X,
                       int64_t ldx, msp_solve_info* info) {
@@ -1239,6 +1265,7 @@ msp_status solve_into(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const doubl
   msp_status st = MSP_OK;
   std::vector<double> rel;
   const bool do_refine = o->refine && (c.sw_t != MSP_F64);
+  TRY(choose_segments(c));
   TRY(build_explicit(c));
   if (do_refine) {
     c.A_cf = c.A_sw;  // the inner solves confirm on the matrix they sweep
@@ -1452,6 +1479,7 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
     acc.sweeps += i.sweeps;
     acc.sweep_bytes += i.sweep_bytes;
     acc.rel_residual_max = std::max(acc.rel_residual_max, i.rel_residual_max);
+    acc.sweep_segments = i.sweep_segments;
   };
   if (kind == MSP_TRACE_EFFDIM) {
     REQUIRE(P->structure == MSP_SYM_PSD, "effective dimension needs an MSP_SYM_PSD handle");

@@ -107,10 +107,22 @@ hipError_t launch_symv(hipStream_t st, const void* A, msp_dtype a_t, int64_t n, 
 // launch would have too few wavefronts; gemm_split_doubles(rows, k) allows up to 16
 // segments)
 size_t gemm_split_doubles(int64_t rows, int64_t k);
+// nseg > 0 forces that many segments (the autotuner's choice; it must fit the scratch,
+// nseg * k * rows doubles, or the built-in rule is used); 0 = built-in rule
 hipError_t launch_gemm_split(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows,
                              int64_t cols, int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
                              double lam, bool diag, const int32_t* skip, double* dot_part, int* nblocks,
-                             double* scratch, size_t scratch_doubles);
+                             double* scratch, size_t scratch_doubles, int nseg);
+// the segment count the built-in rule picks for that launch
+int gemm_split_default(int64_t rows, int64_t cols, int64_t k, msp_dtype a_t, bool fp64_arith,
+                       size_t scratch_doubles);
+// autotuner of the level-1 block sweep (msp_tune.hip): times every admissible segment
+// count of launch_gemm_split on this matrix (Y is overwritten) and returns the fastest,
+// cached per (dtype, arithmetic, rows, cols, lda, k) for the process and, when the
+// environment names a file in MSP_TUNE_CACHE, across processes (JSON lines)
+hipError_t tune_block_sweep(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows,
+                            int64_t cols, int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
+                            double* scratch, size_t scratch_doubles, int* nseg_out);
 // Y[:, j] = M X[:, j] for an FP64 row-major M (ld = cols) with few rows: the same
 // matrix-core product, its reduction range cut into segments of at least min_seg columns
 // until about 2048 wavefronts run (scratch of at least gemm_split_doubles(rows, k)

@@ -33,6 +33,7 @@ def test_version_and_defaults():
     L.msp_solve_opts_default(ctypes.byref(o))
     assert o.tol == 1e-8 and o.max_outer > 0 and o.inner_tol > 0
     assert o.level2_form == 1 and o.sym_sweep == 1
+    assert o.autotune == 0
 
 
 def test_batched_adjoint_rejects_empty_batch():
