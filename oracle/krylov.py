@@ -71,6 +71,10 @@ def fcg(op, b, prec, tol: float, max_iter: int, true_residual=None) -> KrylovRes
             rz = float(r @ z)
             continue
         z = prec(r)
+        if not (rz != 0.0 and np.isfinite(rz)):
+            # beta's denominator <r_old, z_old> vanished (an inexact preconditioner that
+            # is not positive definite): no conjugate direction can be formed
+            return KrylovResult(x, it, "breakdown", hist, restarts)
         beta = float(z @ (r - r_old)) / rz
         rz = float(r @ z)
         p = z + beta * p

@@ -63,3 +63,20 @@ def test_zero_rhs_and_breakdown():
     assert res.status == "zero_rhs" and res.iterations == 0
     res = krylov.fcg(lambda x: -x, np.ones(10), lambda r: r, 1e-8, 10)
     assert res.status == "breakdown"
+
+
+def test_breakdown_when_the_preconditioned_residual_is_orthogonal():
+    # a preconditioner whose output is orthogonal to r makes <r, z> = 0: beta cannot be
+    # formed, which is reported as a breakdown after the first step (no exception)
+    a, _ = _spd(6, 10.0, 11)
+    b = np.array([1.0, 2.0, 0.5, -1.0, 0.25, 3.0])
+
+    def prec(r):  # pairs (r0, r1) -> (r1, -r0): <r, z> = r0 r1 - r1 r0 = 0 exactly
+        z = np.empty_like(r)
+        z[0::2], z[1::2] = r[1::2], -r[0::2]
+        return z
+
+    res = krylov.fcg(lambda x: a @ x, b, prec, 1e-12, 10)
+    # the first step takes alpha = <r, z> / <p, A p> = 0, the second cannot form beta
+    assert res.status == "breakdown" and res.iterations == 1
+    assert not np.any(res.x)
