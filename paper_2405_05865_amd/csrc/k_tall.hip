@@ -215,6 +215,15 @@ template <class TY, int CPL>
 hipError_t y_z_t(hipStream_t st, const TY* Y, int64_t n, int s, int64_t ldy, const double* Z, int k, double a,
                  const double* V, int64_t ldv, double b, const int32_t* skip, double* out, int64_t ldo) {
   constexpr int KG = KGroup<CPL>::value;
+  if (k == 1) {
+    // one column: no idle column groups, and a wavefront per row keeps every row's loads
+    // in flight at once (the pass is one read of Y)
+    const int64_t waves1 = n < 65536 ? n : 65536;
+    const unsigned blocks1 = (unsigned)((waves1 * WAVE + NT - 1) / NT);
+    hipLaunchKernelGGL((k_y_z<TY, CPL, 1>), dim3(blocks1), dim3(NT), 0, st, Y, n, s, ldy, Z, k, 0, a, V, ldv, b, skip,
+                       out, ldo);
+    return hipGetLastError();
+  }
   const int64_t waves = n < 16384 ? n : 16384;
   const unsigned blocks = (unsigned)((waves * WAVE + NT - 1) / NT);
   for (int j0 = 0; j0 < k; j0 += KG)
