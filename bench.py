@@ -114,10 +114,12 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 2 GiB elementwise copy (calibrates the HBM byte counters) and exit")
     ap.add_argument("--workload", default="rbf_gp_n32768",
-                    choices=["rbf_gp_n32768", "batched_rbf_256", "general_outlier_n65536"],
+                    choices=["rbf_gp_n32768", "batched_rbf_256", "general_outlier_n65536", "schatten1_n16384"],
                     help="rbf_gp_n32768: the single n=32768 FP64 solve (default); batched_rbf_256: 256 uneven "
                          "F32 RBF systems x 16 right-hand sides in one batched launch; general_outlier_n65536: "
-                         "the three-level solve of A x = b, n=65536, 8 right-hand sides")
+                         "the three-level solve of A x = b, n=65536, 8 right-hand sides; schatten1_n16384: the "
+                         "Schatten-1 estimate of A = Q diag(1/i) Q^T, n=16384, 512 probes as one block")
+    ap.add_argument("--h", type=float, default=1.5, help="schatten: quadrature node spacing")
     ap.add_argument("--count", type=int, default=None, help="batched: number of systems (default 256)")
     ap.add_argument("--lo", default="f32", choices=["f32", "bf16", "f64"],
                     help="batched (f32, bf16) and general (f32, f64): sweep precision inside MSP")
@@ -152,6 +154,9 @@ def main():
         return
     if args.workload == "general_outlier_n65536":
         bench_general(args)
+        return
+    if args.workload == "schatten1_n16384":
+        bench_schatten(args)
         return
 
     name = "rbf_gp_n32768"
@@ -244,6 +249,80 @@ def main():
     if not args.no_cpu_baseline and K == 1:
         log("[bench] timing the CPU oracle (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(a, b, w, lam0, infos[-1]["outer_iters"], args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def bench_schatten(args):
+    """||A||_1 = sum sigma_i for A = Q diag(1/i) Q^T (Q a product of 8 Householder
+    reflections), n = 16384, by quadrature over ridge solves (A^T A + t I) X = G with 512
+    Gaussian probes as one block: FP32 copy of A inside MSP (FP64 sweep arithmetic), FP64
+    refinement; s = 1024, phi = 4096. One step = one whole estimate."""
+    import numpy as np
+    import torch
+
+    import paper_2405_05865_amd as msp
+    import workloads as W
+
+    w = W.config("schatten1_n16384")
+    n, s, N = w.n, w.s, w.nrhs
+    dev = torch.device("cuda:0")
+    msp.library()
+    t = time.time()
+    sig, q_vs = W.schatten_psd_factors(n, w.config_id)
+    A = W.outer_product_on_device(q_vs, sig, q_vs, dev)
+    A = 0.5 * (A + A.t())
+    A32 = A.float()
+    G = torch.from_numpy(W.gaussian((N, n), w.config_id)).to(dev)
+    torch.cuda.synchronize()
+    l = s // 2
+    lam0 = float(2.0 / l * np.sum(np.sort(sig)[::-1][l:] ** 2))
+    exact = float(np.sum(sig))
+    log(f"[bench] schatten n={n} s={s} probes={N}: inputs resident in HBM ({time.time() - t:.1f} s), "
+        f"lam0={lam0:.4g}, exact sum sigma={exact:.6f}")
+
+    def step():
+        rows, signs, Y = msp.sketch(A32, s, w.gamma, w.seed_s)
+        P = msp.Precond("general", rows, signs, Y, 1.0, lam0, w.phi, w.phi_gamma, w.seed_phi)
+        est, se, info = msp.schatten(P, A, G, p=1.0, A_lo=A32, h=args.h, refine=1, tol=w.tol)
+        P.close()
+        return est, se, info
+
+    for i in range(args.warmup):
+        est, se, info = step()
+        log(f"[bench] warmup {i}: estimate {est:.6f} +- {se:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        est, se, info = step()
+        log(f"[bench] step {i}: estimate {est:.6f} +- {se:.2e} (exact {exact:.6f}), outer={info['outer_iters']} "
+            f"inner={info['inner_iters']} level3={info['level3_iters']} sweeps={info['sweeps']}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    line = {
+        "metric": "Schatten-1 estimates/sec (512 probes, n=16384)",
+        "value": round(args.steps / el, 5),
+        "unit": "estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"schatten1_n{n}", "n": n, "s": s, "phi": w.phi, "gamma": w.gamma, "probes": N,
+                   "p": 1.0, "h": args.h, "lambda0": lam0, "tol": w.tol, "matrix": "f64", "matrix_in_msp": "f32",
+                   "sweep_arithmetic": "f64", "refinement": "fp64"},
+        "estimate": est,
+        "std_err": se,
+        "exact": exact,
+        "rel_error": abs(est - exact) / exact,
+        "outer_iters": info["outer_iters"],
+        "inner_iters": info["inner_iters"],
+        "level3_iters": info["level3_iters"],
+        "sweeps": info["sweeps"],
+    }
     print(json.dumps(line), flush=True)
 
 
