@@ -37,6 +37,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;  // valid in every thread
 }
 
+// the last block of the grid to arrive (device-scope fence in every block)
 __device__ __forceinline__ bool last_block(int32_t* counter) {
   __shared__ int is_last;
   __threadfence();
@@ -51,31 +52,11 @@ __device__ __forceinline__ bool last_block(int32_t* counter) {
   return is_last != 0;
 }
 
-__device__ __forceinline__ void publish(FcgState S, int32_t* mirror, int nt) {
-  __shared__ int cnt, mx;
-  if (threadIdx.x == 0) {
-    cnt = 0;
-    mx = 0;
-  }
-  __syncthreads();
-  int mine = 0, it = 0;
-  for (int64_t j = threadIdx.x; j < S.k; j += nt) {
-    mine += (S.done[j] == 0);
-    it = max(it, S.iters[j]);
-  }
-  atomicAdd(&cnt, mine);
-  atomicMax(&mx, it);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    *S.active = cnt;
-    if (mirror) {
-      __hip_atomic_store(mirror, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(mirror + 1, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __threadfence_system();
-    }
-    *S.counter = 0;
-  }
-}
+// columns up to which the last block of k_l2_dir publishes (its fences are cheap for a
+// few blocks); beyond, a one-block kernel does it after k_l2_dir
+constexpr int kDirFenceMaxK = 16;
+// columns from which the explicit-operator update runs one block per column
+constexpr int kUpdateColMinK = 32;
 
 template <class T>
 __device__ __forceinline__ double ldy(const T* p) { return (double)(*p); }
@@ -307,6 +288,48 @@ __global__ void __launch_bounds__(NTU) k_l2_init(L2Args a) {
   if (threadIdx.x == 0) a.upart[(int64_t)blockIdx.x * a.k + j] = t;
 }
 
+// ---- the same step for an explicit operator (no Y-pass partials, nbC = 0): one block of
+// 256 threads per column; wavefront w of round m owns the 64 elements of chunk 4m + w, so
+// the |r|^2 partial of every 64-element chunk is one wavefront sum, as in k_l2_update
+__global__ void __launch_bounds__(256) k_l2_update_m(L2Args a) {
+  __shared__ double shs[4];
+  const int j = blockIdx.x, lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  if (a.S.done[j] != 0) return;
+  double t = 0.0;
+  for (int i = threadIdx.x; i < a.s; i += 256) {
+    const double pi = a.p[(int64_t)j * a.s + i];
+    if (a.pqw) t = fma(a.wscale, a.pqw[(int64_t)j * a.s + i], t);
+    else if (a.wp) t = fma(a.wscale * pi, a.wp[(int64_t)j * a.s + i], t);
+    t = fma(a.sigma * pi, pi, t);
+  }
+  const double pq = block_sum<256>(t, shs);
+  const bool brk = !(pq > 0.0);
+  const double alpha = brk ? 0.0 : a.S.rz[j] / pq;
+  for (int base = 0; base < a.s; base += 256) {
+    const int c = base + threadIdx.x;
+    double sq = 0.0;
+    if (c < a.s) {
+      const int64_t o = (int64_t)j * a.s + c;
+      const double pv = a.p[o];
+      double qv = a.sigma * pv;
+      if (a.wp) qv = fma(a.wscale, a.wp[o], qv);
+      a.q[o] = qv;
+      a.y[o] = fma(alpha, pv, a.y[o]);
+      const double rv = a.r[o];
+      a.ro[o] = rv;
+      const double rn = fma(-alpha, qv, rv);
+      a.r[o] = rn;
+      sq = rn * rn;
+    }
+    const double cs = wave_sum(sq);
+    if (lane == 0 && base + w * WAVE < a.s) a.upart[(int64_t)(base / WAVE + w) * a.k + j] = cs;
+  }
+  if (threadIdx.x == 0) {
+    a.S.alpha[j] = alpha;
+    a.S.brk[j] = brk ? 1 : 0;
+  }
+}
+
 // ---- q, alpha, y += alpha p, r_old = r, r -= alpha q, |r|^2 partials ---------------
 __global__ void __launch_bounds__(NTU) k_l2_update(L2Args a) {
   __shared__ double sh[NTU];
@@ -480,6 +503,28 @@ __global__ void __launch_bounds__(256) k_l2_dots(L2Args a, int decide) {
   }
 }
 
+// active count and largest iteration count of done_next / iters_next (one block)
+__device__ __forceinline__ void publish_next(const L2Args& a) {
+  __shared__ int cnt, mx;
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    mx = 0;
+  }
+  __syncthreads();
+  for (int jj = threadIdx.x; jj < a.k; jj += 256) {
+    atomicAdd(&cnt, a.S.done_next[jj] == 0 ? 1 : 0);
+    atomicMax(&mx, a.S.iters_next[jj]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *a.S.active = cnt;
+    if (a.mirror) {
+      __hip_atomic_store(a.mirror, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(a.mirror + 1, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
 // ---- commit the decision; beta = <z, r - r_old> / rz ; rz = <r, z> ; p = z + beta p.
 // One block per column; the last block to finish publishes the active count and the
 // largest iteration count.
@@ -505,28 +550,18 @@ __global__ void __launch_bounds__(256) k_l2_dir(L2Args a, int first) {
     a.S.done[j] = dj;
     a.S.iters[j] = a.S.iters_next[j];
   }
-  // one column: no other block to wait for (and no device-scope fence)
-  if (gridDim.x > 1 && !last_block(a.S.counter)) return;
-  __shared__ int cnt, mx;
-  if (threadIdx.x == 0) {
-    cnt = 0;
-    mx = 0;
-  }
-  __syncthreads();
-  for (int jj = threadIdx.x; jj < a.k; jj += 256) {
-    atomicAdd(&cnt, a.S.done_next[jj] == 0 ? 1 : 0);
-    atomicMax(&mx, a.S.iters_next[jj]);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    *a.S.active = cnt;
-    *a.S.counter = 0;
-    if (a.mirror) {
-      __hip_atomic_store(a.mirror, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(a.mirror + 1, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+  // one column: publish here; a few: the last block publishes; more: k_l2_publish after
+  // this kernel (a device-scope fence in every one of many blocks costs more than a launch)
+  if (gridDim.x == 1) {
+    publish_next(a);
+  } else if (a.k <= kDirFenceMaxK && last_block(a.S.counter)) {
+    publish_next(a);
+    if (threadIdx.x == 0) *a.S.counter = 0;
   }
 }
+
+// ---- active count and largest iteration count of the committed decisions, for the host
+__global__ void __launch_bounds__(256) k_l2_publish(L2Args a) { publish_next(a); }
 
 // ---- the inner operator through an explicit s x s matrix W, every column in one pass:
 // wp = W v and pqw = v .* (W v) (a wavefront per row of W)
@@ -728,6 +763,7 @@ hipError_t l2_init(hipStream_t st, const L2Step& a) {
   hipError_t e = prec_launch(st, a, 2);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_l2_dir, dim3((unsigned)a.k), dim3(256), 0, st, make_args(a), 1);
+  if (a.k > kDirFenceMaxK) hipLaunchKernelGGL(k_l2_publish, dim3(1), dim3(256), 0, st, make_args(a));
   return hipGetLastError();
 }
 
@@ -745,9 +781,14 @@ hipError_t l2_reduce_to(hipStream_t st, const L2Step& a, double* out, const int3
 
 // one step after l2_op(p): update, decision + preconditioner, new direction
 hipError_t l2_step(hipStream_t st, const L2Step& a) {
-  hipLaunchKernelGGL(k_l2_update, dim3((unsigned)ublocks((int)a.s), (unsigned)a.k), dim3(NTU), 0, st, make_args(a));
+  if (a.nbC == 0 && a.k >= kUpdateColMinK)
+    hipLaunchKernelGGL(k_l2_update_m, dim3((unsigned)a.k), dim3(256), 0, st, make_args(a));
+  else
+    hipLaunchKernelGGL(k_l2_update, dim3((unsigned)ublocks((int)a.s), (unsigned)a.k), dim3(NTU), 0, st,
+                       make_args(a));
   hipError_t e = prec_launch(st, a, 1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_l2_dir, dim3((unsigned)a.k), dim3(256), 0, st, make_args(a), 0);
+  if (a.k > kDirFenceMaxK) hipLaunchKernelGGL(k_l2_publish, dim3(1), dim3(256), 0, st, make_args(a));
   return hipGetLastError();
 }
