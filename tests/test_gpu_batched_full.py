@@ -1,0 +1,89 @@
+"""Parity at the full size of the batched workload: 256 uneven RBF systems (n_j ~ U{512..8192},
+points in 4 dimensions, lengthscales U(0.5, 2)), lam = 1e-2, 16 right-hand sides each, the F32
+matrix is the problem, F32 sweeps inside MSP and FP64 refinement, all systems in one
+msp_solve_batched launch, then the batched adjoint of L = sum |X|^2 in one launch (the
+launch configuration the benchmark times).
+
+Every system must report a relative residual <= 1e-8. Three sampled systems (the smallest,
+the largest and one in between) are regenerated on the host and checked one by one: the
+residuals of X and of dB = (A + lam I)^{-1} (2 X) recomputed on the host (<= 1e-8), their
+distance to dense FP64 solves on the F32 matrix within what that residual allows
+(|x - x*| <= |r| / lam, since A is PSD), and dlam = -<dB, X>.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_05865_amd as msp
+import workloads as W
+from oracle import dense
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_batched_forward_and_adjoint():
+    w = W.config("batched_rbf_256")
+    count, nrhs, dim = w.extra["count"], w.nrhs, w.extra["dim"]
+    sizes, ls = W.batched_rbf_sizes(count, w.config_id)
+    say(f"case batched full size: {count} systems, n in [{sizes.min()}, {sizes.max()}], {nrhs} RHS")
+    systems = []
+    for j in range(count):
+        n = int(sizes[j])
+        a, b = W.batched_rbf_system(j, n, float(ls[j]), dim, nrhs, w.config_id)
+        ld = (n + 7) // 8 * 8
+        buf = torch.zeros((n, ld), dtype=torch.float32, device=DEV)
+        buf[:, :n] = torch.from_numpy(a).to(DEV)
+        A = buf[:, :n]
+        s = min(w.s, n // 2)
+        phi = min(4 * s, n)
+        # lam0 = (2/l) sum_{i>l} lambda_i, l = s/2, from the spectrum of the F32 matrix (as the
+        # benchmark takes it; a parameter of the input, not a step of the solve)
+        ev = torch.linalg.eigvalsh(A.double()).flip(0)
+        lam0 = float(2.0 / (s // 2) * ev[s // 2:].clamp_min(0).sum())
+        rows, signs, Y = msp.sketch(A, s, w.gamma, w.seed_s + 97 * j)
+        P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, phi, w.phi_gamma, w.seed_s + 97 * j + 8)
+        systems.append((P, A, None, torch.from_numpy(b).to(DEV)))
+        if j % 64 == 63:
+            say(f"generated {j + 1}/{count}")
+    Xs, infos = msp.solve_batched(systems, tol=w.tol, refine=1)
+    bad = [j for j, d in enumerate(infos) if d["status"] != "MSP_OK" or d["rel_residual_max"] > w.tol]
+    say("forward done; not converged:", bad)
+    assert not bad
+    Gs = [2.0 * X for X in Xs]
+    dBs, dlams, _, binfos = msp.solve_batched_backward(systems, Xs, Gs, tol=w.tol, refine=1)
+    badb = [j for j, d in enumerate(binfos) if d["status"] != "MSP_OK" or d["rel_residual_max"] > w.tol]
+    say("adjoint done; not converged:", badb)
+    assert not badb
+    order = np.argsort(sizes)
+    for j in (int(order[0]), int(order[count // 2]), int(order[-1])):
+        n = int(sizes[j])
+        a, b = W.batched_rbf_system(j, n, float(ls[j]), dim, nrhs, w.config_id)
+        a64 = a.astype(np.float64)
+        x = Xs[j].cpu().numpy()
+        say(f"system {j}: n={n}")
+        # A + lam I >= lam I (A is PSD), so |x - x*| <= |b - (A + lam I) x| / lam: the forward
+        # error the residual allows, checked against the dense solution
+        xs = dense.solve_psd(a64, b.T, w.lam).T
+        for q in range(nrhs):
+            rel = dense.rel_residual_psd(a64, x[q], b[q], w.lam)
+            assert rel <= 1e-8 * (1 + 1e-6), (j, q, rel)
+            bound = rel * np.linalg.norm(b[q]) / w.lam
+            assert np.linalg.norm(x[q] - xs[q]) <= 1.01 * bound + 1e-10 * np.linalg.norm(xs[q]), (j, q)
+        db = dBs[j].cpu().numpy()
+        want = dense.solve_psd(a64, 2.0 * x.T, w.lam).T
+        for q in range(nrhs):
+            g = 2.0 * x[q]
+            rel = dense.rel_residual_psd(a64, db[q], g, w.lam)
+            assert rel <= 1e-8 * (1 + 1e-6), (j, q, rel)
+            bound = rel * np.linalg.norm(g) / w.lam
+            assert np.linalg.norm(db[q] - want[q]) <= 1.01 * bound + 1e-10 * np.linalg.norm(want[q]), (j, q)
+        # dlam = -<dB, X> over the block
+        assert dlams[j] == pytest.approx(-float(np.sum(db * x)), rel=1e-9)
+    for P, *_ in systems:
+        P.close()
