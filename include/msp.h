@@ -326,6 +326,8 @@ msp_status msp_solve_backward(void* stream, const msp_precond* P,
  *   x = (A + lam I)^{-1} g by the two-level MSP of P (an MSP_SYM_PSD handle); `p` is lam.
  *   G        N probes of length n, ld ldg, FP64
  *   estimate, std_err  [host] out (std_err: standard error over probes)
+ * Returns MSP_ERR_NO_CONVERGENCE, with the estimate and info still written, when some
+ * ridge solve stopped at its iteration cap; other failures return before any output.
  * Synchronises the stream before returning.
  * ------------------------------------------------------------------------------ */
 typedef enum { MSP_TRACE_SCHATTEN_P = 0, MSP_TRACE_EFFDIM = 1 } msp_trace_kind;

@@ -335,11 +335,15 @@ def schatten(P: Precond, A_hi, probes, p: float = 1.0, A_lo=None, h: float = 1.5
     est, se = ctypes.c_double(), ctypes.c_double()
     info = SolveInfo()
     kc = B.MSP_TRACE_SCHATTEN_P if kind == "schatten" else B.MSP_TRACE_EFFDIM
-    B.check(L.msp_schatten(_stream(probes.device), kc, P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(),
-                           _code(A_lo), A_hi.stride(0), float(p), probes.data_ptr(), ldg, N, float(h), float(u_lo),
-                           float(u_hi), ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(est),
-                           ctypes.byref(se), ctypes.byref(info)))
-    return est.value, se.value, info.as_dict()
+    code = L.msp_schatten(_stream(probes.device), kc, P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(),
+                          _code(A_lo), A_hi.stride(0), float(p), probes.data_ptr(), ldg, N, float(h), float(u_lo),
+                          float(u_hi), ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(est),
+                          ctypes.byref(se), ctypes.byref(info))
+    if code not in (0, 4):  # 4: a ridge solve hit its cap; the estimate is still written
+        B.check(code)
+    d = info.as_dict()
+    d["code"] = B.STATUS.get(code, code)
+    return est.value, se.value, d
 
 
 def effective_dimension(P: Precond, A_hi, probes, lam: float, **opts):

@@ -1470,6 +1470,7 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
   double* gtp = AX + n * N;
   double* dv = gtp + gemv_t_part_doubles(n, n, 1);
   std::vector<double> per(N, 0.0), d(N);
+  bool unconverged = false;  // some solve stopped at its iteration cap (estimate still written)
   msp_solve_info acc{};
   auto add_info = [&](const msp_solve_info& i) {
     acc.outer_iters += i.outer_iters;
@@ -1488,6 +1489,7 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
     msp_solve_info i{};
     msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
     if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) return s_;
+    if (s_ != MSP_OK) unconverged = true;
     add_info(i);
     // per probe: g^T g - lam g^T x
     MSP_CHECK_HIP(launch_coldots(st, n, N, G, ldg, G, ldg, dv));
@@ -1544,7 +1546,11 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
       TRY(msp_precond_set_lambda(stream, P, t));
       msp_solve_info i{};
       msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
-      if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) return s_;
+      if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) {
+        (void)msp_precond_set_lambda(stream, P, lam_save);
+        return s_;
+      }
+      if (s_ != MSP_OK) unconverged = true;
       add_info(i);
       if (log_on())
         fprintf(stderr, "[msp] schatten node %d/%d t=%.3e outer=%d inner=%lld level3=%lld relres=%.2e\n", jn + 1,
@@ -1566,7 +1572,8 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
   for (double v : per) var += (v - mean) * (v - mean);
   *estimate = mean;
   if (std_err) *std_err = N > 1 ? std::sqrt(var / (double)(N - 1) / (double)N) : NAN;
-  acc.status = MSP_OK;
+  acc.status = unconverged ? MSP_ERR_NO_CONVERGENCE : MSP_OK;
   if (info) *info = acc;
+  if (unconverged) return msp_fail(MSP_ERR_NO_CONVERGENCE, "a ridge solve stopped at its iteration cap");
   return MSP_OK;
 }
