@@ -130,6 +130,34 @@ def test_schatten1_matches_oracle_estimator(monkeypatch):
     assert abs(est - exact) < 4 * math.sqrt(2.0 * np.sum(sig ** 2) / N) + 2e-2 * exact
 
 
+@pytest.mark.parametrize("pp", [0.5, 1.5])
+def test_schatten_p_matches_oracle_estimator(pp):
+    # p != 1 through the same driver: weights h sin(pi p/2)/pi e^{(p/2) u} and the range
+    # rule in p, against the oracle's estimator on the same probes and nodes
+    say(f"case schatten-p p={pp} n=160 N=24")
+    n, s, N = 160, 32, 24
+    a, sig, _ = W.schatten_psd(n, config_id=201)
+    g = W.gaussian((N, n), 201)
+    lam0 = omsp.paper_lambda0(sig ** 2, s // 2)
+    A = torch.from_numpy(a).to(DEV)
+    rows, signs, Y = msp.sketch(A, s, 8, 17)
+    P = msp.Precond("general", rows, signs, Y, 1.0, lam0, 4 * s, 8, 18)
+    u_lo, u_hi = trace.default_range(1.0, n, p=pp, eps_q=1e-2)
+    h = 2.0
+    est, se, info = msp.schatten(P, A, torch.from_numpy(g).to(DEV), p=pp, h=h, u_lo=u_lo, u_hi=u_hi,
+                                 tol=1e-8, inner_tol=1e-10, level3_tol=1e-10)
+    assert info["code"] == "MSP_OK", info
+    nodes, w = trace.quadrature(pp, h, u_lo, u_hi)
+    ridge = lambda t, G: np.linalg.solve(a.T @ a + t * np.eye(n), G)
+    est_o, se_o, _ = trace.schatten_estimate(a, g.T, pp, nodes, w, ridge)
+    say(est, se, est_o, se_o)
+    assert est == pytest.approx(est_o, rel=1e-6)
+    assert se == pytest.approx(se_o, rel=1e-4)
+    # the quadrature of the exact spectrum with these nodes bounds what the estimator targets
+    target = float(trace.quadrature_scalar(sig, pp, nodes, w).sum())
+    assert abs(est - target) < 5 * se + 1e-12
+
+
 def test_effective_dimension_matches_oracle():
     say("case effdim n=256 N=64")
     n, s, lam, N = 256, 32, 0.05, 64
