@@ -15,6 +15,7 @@ from .generators import (  # noqa: F401
     rbf_rows,
     general_outlier,
     general_outlier_factors,
+    tall_outlier,
     householder_apply,
     outer_product_on_device,
     outer_product_row,

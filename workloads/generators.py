@@ -66,6 +66,21 @@ def psd_outlier(n: int, k: int, config_id: int, big=(1e2, 1e4), small=(0.5, 1.0)
     return a, eigs, q
 
 
+def tall_outlier(n: int, d: int, k: int, config_id: int, big=(1e2, 1e4), small=(1.0, 10.0)):
+    """Tall A = U diag(sv) V^T (n x d, n >= d): U from the QR factorization of an N(0,1)
+    n x d matrix, V from that of a d x d one (columns sign-fixed by diag(R)), k singular
+    values log-uniform in ``big`` and d-k uniform in ``small`` (the setting of the paper's
+    least-squares corollary). Returns (A, sv sorted non-increasing)."""
+    u, r = np.linalg.qr(rng_for(config_id, _MATRIX).standard_normal((n, d)))
+    u *= np.sign(np.diag(r))[None, :]
+    v, r = np.linalg.qr(rng_for(config_id, _MATRIX + 10).standard_normal((d, d)))
+    v *= np.sign(np.diag(r))[None, :]
+    rs = rng_for(config_id, _SPECTRUM)
+    lo, hi = math.log10(big[0]), math.log10(big[1])
+    sv = np.sort(np.concatenate([10.0 ** rs.uniform(lo, hi, size=k), rs.uniform(small[0], small[1], size=d - k)]))[::-1]
+    return (u * sv[None, :]) @ v.T, sv.copy()
+
+
 # ----------------------------------------------------------------------------------
 # RBF kernel matrices (kernel ridge regression / GP regression)
 # ----------------------------------------------------------------------------------
