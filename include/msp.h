@@ -340,6 +340,45 @@ msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precond* P,
                         void* ws, size_t ws_bytes, double* estimate /*host*/, double* std_err /*host*/,
                         msp_solve_info* info /*host*/);
 
+/* ---------------------------------------------------------------------------------
+ * Least squares min |A x - b| for a tall A (n x d, n >= d): sketch-and-precondition with
+ * MSP as the inner solver (Section 3, the least-squares corollary).
+ *
+ * msp_left_sketch -- Psi, a Definition 2.1 sketch with q rows over the n rows of A
+ *   (gamma nonzeros +-1/sqrt(gamma) per column, from seed), and A~ = Psi A (q x d, FP64,
+ *   ld ldat), a subspace embedding of A for q of a few times d.
+ *   A          n x d row-major (lda >= d), F64 or F32
+ *   Psi_rows   [n][gamma] int32 out; Psi_signs [n][gamma] int8 out (+1 / -1)
+ *   ws         msp_left_sketch_workspace(n, q, gamma) bytes, 256-B aligned; caller-owned
+ *
+ * msp_lstsq -- flexible PCG on A^T A x = A^T b (k right-hand sides) whose preconditioner
+ *   applies (A~^T A~)^{-1} by msp_solve on P, an MSP_GENERAL handle of A~ with lambda = 0
+ *   (msp_sketch and msp_nystrom on A~), in normal mode to the relative accuracy
+ *   opts->refine_inner_tol (a constant suffices; default 1e-4). The products with A use
+ *   FP64 arithmetic on F64 or F32 storage. Stops when |A^T (b - A x)| <= opts->tol |A^T b|
+ *   per right-hand side (confirmed on the recomputed residual) or after opts->max_outer
+ *   steps.
+ *   At         A~ (P->m x d, FP64, ld ldat), the matrix P was built from
+ *   B          k columns of length n (ld ldb); X: k columns of length d (ld ldx), out
+ *   ws         msp_lstsq_workspace(P, n, k, opts) bytes, 256-B aligned (holds the inner
+ *              solve's workspace)
+ *   info       outer_iters: steps of the outer iteration; inner_iters: level-1 steps of the
+ *              inner solves; level3_iters: their level-2 and level-3 steps; rel_residual_max:
+ *              max_j |A^T (b_j - A x_j)| / |A^T b_j| in FP64; sweeps, sweep_bytes: passes
+ *              over A.
+ *   Returns MSP_ERR_NO_CONVERGENCE (X still written) when the tolerance was not reached.
+ * ------------------------------------------------------------------------------ */
+msp_status msp_left_sketch_workspace(int64_t n, int64_t q, int32_t gamma, size_t* bytes /*host*/);
+msp_status msp_left_sketch(void* stream, const void* A, msp_dtype a_t, int64_t n, int64_t d, int64_t lda, int64_t q,
+                           int32_t gamma, uint64_t seed, int32_t* Psi_rows, int8_t* Psi_signs, double* At,
+                           int64_t ldat, void* ws, size_t ws_bytes);
+msp_status msp_lstsq_workspace(const msp_precond* P, int64_t n, int64_t k, const msp_solve_opts* opts,
+                               size_t* bytes /*host*/);
+msp_status msp_lstsq(void* stream, const msp_precond* P, const double* At, int64_t ldat, const void* A,
+                     msp_dtype a_t, int64_t n, int64_t lda, const double* B, int64_t ldb, int64_t k, double* X,
+                     int64_t ldx, const msp_solve_opts* opts, void* ws, size_t ws_bytes,
+                     msp_solve_info* info /*host*/);
+
 /* Thread-local description of the last failure (empty string if none). */
 const char* msp_last_error(void);
 /* Library version string. */

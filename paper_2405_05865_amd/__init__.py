@@ -351,6 +351,53 @@ def effective_dimension(P: Precond, A_hi, probes, lam: float, **opts):
 
 
 # -----------------------------------------------------------------------------------
+# least squares: msp_left_sketch / msp_lstsq
+# -----------------------------------------------------------------------------------
+def left_sketch(A: torch.Tensor, q: int, gamma: int, seed: int):
+    """Psi (q rows over the n rows of A) and A~ = Psi A. Returns (Psi_rows int32 [n, gamma],
+    Psi_signs int8 [n, gamma], A~ float64 [q, d])."""
+    L = library()
+    _rowmajor(A, "A")
+    n, d = A.shape
+    rows = torch.empty((n, gamma), dtype=torch.int32, device=A.device)
+    signs = torch.empty((n, gamma), dtype=torch.int8, device=A.device)
+    At = torch.empty((q, d), dtype=torch.float64, device=A.device)
+    need = B.size_out()
+    B.check(L.msp_left_sketch_workspace(n, q, gamma, ctypes.byref(need)))
+    ws = _workspace(need.value, A.device)
+    B.check(L.msp_left_sketch(_stream(A.device), A.data_ptr(), _code(A), n, d, A.stride(0), q, gamma,
+                              ctypes.c_uint64(seed & (2 ** 64 - 1)), rows.data_ptr(), signs.data_ptr(),
+                              At.data_ptr(), At.stride(0), ws.data_ptr(), ws.numel()))
+    return rows, signs, At
+
+
+def lstsq(P: Precond, At: torch.Tensor, A: torch.Tensor, Bv: torch.Tensor, **opts):
+    """argmin |A x - b| for each right-hand side ((n,) or (k, n)) with the MSP_GENERAL
+    handle P of A~ = Psi A (lambda = 0). Returns (X, info dict)."""
+    L = library()
+    _rowmajor(A, "A")
+    _rowmajor(At, "A~")
+    if At.dtype != torch.float64:
+        raise ValueError("A~ must be float64")
+    n = A.shape[0]
+    o = _opts(**opts)
+    k, ldb = _vectors(Bv, n, "B")
+    X = torch.empty((k, P.n) if Bv.dim() == 2 else (P.n,), dtype=torch.float64, device=Bv.device)
+    need = B.size_out()
+    B.check(L.msp_lstsq_workspace(P.handle, n, k, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, Bv.device)
+    info = SolveInfo()
+    code = L.msp_lstsq(_stream(Bv.device), P.handle, At.data_ptr(), At.stride(0), A.data_ptr(), _code(A), n,
+                       A.stride(0), Bv.data_ptr(), ldb, k, X.data_ptr(), P.n, ctypes.byref(o), ws.data_ptr(),
+                       ws.numel(), ctypes.byref(info))
+    if code not in (0, 4):
+        B.check(code)
+    d = info.as_dict()
+    d["code"] = B.STATUS.get(code, code)
+    return X, d
+
+
+# -----------------------------------------------------------------------------------
 # convenience: the whole path in one call, and the autograd wrapper
 # -----------------------------------------------------------------------------------
 @dataclass

@@ -32,7 +32,8 @@ EXPORTS = (
     "msp_precond_set_lambda", "msp_precond_factors", "msp_solve_opts_default", "msp_solve_workspace", "msp_solve",
     "msp_solve_batched_workspace", "msp_solve_batched", "msp_solve_batched_backward_workspace",
     "msp_solve_batched_backward", "msp_solve_backward",
-    "msp_schatten_workspace", "msp_schatten", "msp_last_error", "msp_version",
+    "msp_schatten_workspace", "msp_schatten", "msp_left_sketch_workspace", "msp_left_sketch",
+    "msp_lstsq_workspace", "msp_lstsq", "msp_last_error", "msp_version",
 )
 
 
@@ -171,6 +172,11 @@ def load(path: str | None = None):
     L.msp_schatten.argtypes = [P, ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_int, I64, D, P, I64, I64, D, D, D,
                                ctypes.POINTER(SolveOpts), P, ctypes.c_size_t, ctypes.POINTER(D), ctypes.POINTER(D),
                                ctypes.POINTER(SolveInfo)]
+    L.msp_left_sketch_workspace.argtypes = [I64, I64, I32, SZ]
+    L.msp_left_sketch.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, I32, U64, P, P, P, I64, P, ctypes.c_size_t]
+    L.msp_lstsq_workspace.argtypes = [P, I64, I64, ctypes.POINTER(SolveOpts), SZ]
+    L.msp_lstsq.argtypes = [P, P, P, I64, P, ctypes.c_int, I64, I64, P, I64, I64, P, I64, ctypes.POINTER(SolveOpts),
+                            P, ctypes.c_size_t, ctypes.POINTER(SolveInfo)]
     L.msp_last_error.restype = ctypes.c_char_p
     L.msp_last_error.argtypes = []
     L.msp_version.restype = ctypes.c_char_p

@@ -46,9 +46,6 @@ extern "C" const char* msp_version(void) { return "libmsp 0.1 (gfx950)"; }
     if (_s != MSP_OK) return _s;          \
   } while (0)
 
-hipError_t launch_gemv_f32_as_f64(hipStream_t st, const float* A, int64_t rows, int64_t cols, int64_t lda,
-                                  const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
-                                  bool diag_shift, const int32_t* skip, double* dot_part, int* nblocks);
 
 namespace {
 

@@ -88,6 +88,10 @@ hipError_t spd_inverse(hipStream_t st, int64_t s, double* M, double* tmp, double
 hipError_t launch_gemv(hipStream_t st, const void* A, msp_dtype a_t, int64_t rows, int64_t cols, int64_t lda,
                        const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
                        bool diag_shift, const int32_t* skip, double* dot_part, int* nblocks);
+// the same with FP64 arithmetic on an FP32-stored A
+hipError_t launch_gemv_f32_as_f64(hipStream_t st, const float* A, int64_t rows, int64_t cols, int64_t lda,
+                                  const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k, double lam,
+                                  bool diag_shift, const int32_t* skip, double* dot_part, int* nblocks);
 // Blocks of k >= kGemmMinK vectors take the matrix-core block sweep (k_gemm.hip) with the
 // same contract; its dot partials come per 64-row set (gemm_row_sets(rows) of them).
 constexpr int64_t kGemmMinK = 8;

@@ -88,3 +88,17 @@ def test_solve_rejects_null_handle():
     info = B.SolveInfo()
     assert L.msp_solve(None, None, None, 0, None, 0, 10, None, 10, 1, None, 10, None, None, 0,
                        ctypes.byref(info)) == 1
+
+
+def test_least_squares_validation_before_device_work():
+    L = msp.library()
+    need = ctypes.c_size_t(0)
+    assert L.msp_left_sketch_workspace(100, 0, 8, ctypes.byref(need)) == 1
+    assert L.msp_left_sketch_workspace(100, 40, 33, ctypes.byref(need)) == 1
+    assert L.msp_left_sketch_workspace(100, 40, 8, ctypes.byref(need)) == 0 and need.value > 0
+    assert L.msp_lstsq_workspace(None, 100, 1, None, ctypes.byref(need)) == 1
+    o = B.SolveOpts()
+    L.msp_solve_opts_default(ctypes.byref(o))
+    info = B.SolveInfo()
+    assert L.msp_lstsq(None, None, None, 0, None, 0, 10, 10, None, 10, 1, None, 10, ctypes.byref(o), None, 0,
+                       ctypes.byref(info)) == 1
