@@ -114,12 +114,16 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 2 GiB elementwise copy (calibrates the HBM byte counters) and exit")
     ap.add_argument("--workload", default="rbf_gp_n32768",
-                    choices=["rbf_gp_n32768", "batched_rbf_256", "general_outlier_n65536", "schatten1_n16384"],
+                    choices=["rbf_gp_n32768", "batched_rbf_256", "general_outlier_n65536", "schatten1_n16384",
+                             "lstsq_tall"],
                     help="rbf_gp_n32768: the single n=32768 FP64 solve (default); batched_rbf_256: 256 uneven "
                          "F32 RBF systems x 16 right-hand sides in one batched launch; general_outlier_n65536: "
                          "the three-level solve of A x = b, n=65536, 8 right-hand sides; schatten1_n16384: the "
-                         "Schatten-1 estimate of A = Q diag(1/i) Q^T, n=16384, 512 probes as one block")
+                         "Schatten-1 estimate of A = Q diag(1/i) Q^T, n=16384, 512 probes as one block; lstsq_tall: "
+                         "least squares with a tall A (n=262144 x d=2048, FP64, 64 large singular values), one RHS")
     ap.add_argument("--h", type=float, default=1.5, help="schatten: quadrature node spacing")
+    ap.add_argument("--inner-rel", type=float, default=0.1,
+                    help="lstsq_tall: relative accuracy of the inner MSP solves with A~ (a constant suffices)")
     ap.add_argument("--count", type=int, default=None, help="batched: number of systems (default 256)")
     ap.add_argument("--lo", default="f32", choices=["f32", "bf16", "f64"],
                     help="batched (f32, bf16) and general (f32, f64): sweep precision inside MSP")
@@ -157,6 +161,9 @@ def main():
         return
     if args.workload == "schatten1_n16384":
         bench_schatten(args)
+        return
+    if args.workload == "lstsq_tall":
+        bench_lstsq(args)
         return
 
     name = "rbf_gp_n32768"
@@ -249,6 +256,80 @@ def main():
     if not args.no_cpu_baseline and K == 1:
         log("[bench] timing the CPU oracle (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(a, b, w, lam0, infos[-1]["outer_iters"], args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def bench_lstsq(args):
+    """min |A x - b| for a tall A = U diag(sv) V^T (n = 262144, d = 2048, FP64; 64 singular
+    values 10^U(2,4), the rest U(1,10); U, V from QR factorizations of seeded Gaussian
+    matrices, built on the device), one right-hand side, to |A^T (b - A x)| <= 1e-9 |A^T b|.
+    One step = left sketch (q = 4d) + sketch and factors of A~ + the outer iteration."""
+    import numpy as np
+    import torch
+
+    import paper_2405_05865_amd as msp
+    import workloads as W
+
+    n, d, k = (args.n or 262144), 2048, 64
+    q, s = 4 * d, 256
+    dev = torch.device("cuda:0")
+    msp.library()
+    t = time.time()
+    g = torch.Generator(device="cpu").manual_seed(901)
+    # input preparation: orthonormal factors from QR of seeded Gaussian matrices (torch, on the device)
+    U, _ = torch.linalg.qr(torch.randn(n, d, generator=g, dtype=torch.float64).to(dev))
+    V, _ = torch.linalg.qr(torch.randn(d, d, generator=g, dtype=torch.float64).to(dev))
+    rs = np.random.default_rng(902)
+    sv = np.sort(np.concatenate([10.0 ** rs.uniform(2, 4, size=k), rs.uniform(1, 10, size=d - k)]))[::-1].copy()
+    A = (U * torch.from_numpy(sv).to(dev)[None, :]) @ V.t()
+    del U
+    b = torch.from_numpy(np.random.default_rng(903).standard_normal(n)).to(dev)
+    torch.cuda.synchronize()
+    lam0 = float(2.0 / (s // 2) * np.sum(sv[s // 2:] ** 2))
+    log(f"[bench] lstsq n={n} d={d} q={q} s={s}: inputs resident in HBM ({time.time() - t:.1f} s), lam0={lam0:.4g}")
+
+    def step():
+        rows, signs, At = msp.left_sketch(A, q, 8, 911)
+        r2, s2, Y = msp.sketch(At, s, 8, 912)
+        P = msp.Precond("general", r2, s2, Y, 0.0, lam0, 4 * s, 8, 913)
+        X, info = msp.lstsq(P, At, A, b, tol=1e-9, refine_inner_tol=args.inner_rel, level2_form=args.level2_form)
+        P.close()
+        return X, info
+
+    for i in range(args.warmup):
+        _, info = step()
+        log(f"[bench] warmup {i}: outer={info['outer_iters']} inner={info['inner_iters']} {info['code']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        X, info = step()
+        log(f"[bench] step {i}: outer={info['outer_iters']} inner={info['inner_iters']} "
+            f"level2+3={info['level3_iters']} relres={info['rel_residual_max']:.2e} {info['code']}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    line = {
+        "metric": "least-squares solves/sec at |A^T r| <= 1e-9 |A^T b| (n=262144 x d=2048)",
+        "value": round(args.steps / el, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"lstsq_tall_n{n}_d{d}", "n": n, "d": d, "q": q, "s": s, "phi": 4 * s,
+                   "large_sv": k, "tol": 1e-9, "inner_rel": args.inner_rel, "level2_form": args.level2_form},
+        "outer_iters": info["outer_iters"],
+        "inner_level1_steps": info["inner_iters"],
+        "inner_level2_3_steps": info["level3_iters"],
+        "passes_over_A": info["sweeps"],
+        "a_bytes_per_step": info["sweep_bytes"],
+        "rel_residual": info["rel_residual_max"],
+        "converged": info["code"] == "MSP_OK",
+    }
     print(json.dumps(line), flush=True)
 
 
