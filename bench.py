@@ -292,7 +292,8 @@ def bench_lstsq(args):
         rows, signs, At = msp.left_sketch(A, q, 8, 911)
         r2, s2, Y = msp.sketch(At, s, 8, 912)
         P = msp.Precond("general", r2, s2, Y, 0.0, lam0, 4 * s, 8, 913)
-        X, info = msp.lstsq(P, At, A, b, tol=1e-9, refine_inner_tol=args.inner_rel, level2_form=args.level2_form)
+        X, info = msp.lstsq(P, At, A, b, tol=1e-9, refine_inner_tol=args.inner_rel, level2_form=args.level2_form,
+                            use_graph=args.use_graph)
         P.close()
         return X, info
 
@@ -321,7 +322,8 @@ def bench_lstsq(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"lstsq_tall_n{n}_d{d}", "n": n, "d": d, "q": q, "s": s, "phi": 4 * s,
-                   "large_sv": k, "tol": 1e-9, "inner_rel": args.inner_rel, "level2_form": args.level2_form},
+                   "large_sv": k, "tol": 1e-9, "inner_rel": args.inner_rel, "level2_form": args.level2_form,
+                   "use_graph": args.use_graph},
         "outer_iters": info["outer_iters"],
         "inner_level1_steps": info["inner_iters"],
         "inner_level2_3_steps": info["level3_iters"],

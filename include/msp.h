@@ -174,11 +174,11 @@ typedef struct {
                               lower triangle of A_lo only (n(n+1)/2 elements per sweep instead of
                               n^2; A is symmetric by the problem statement). The FP64 confirmation
                               and refinement residuals still use all of A_hi. Default 1. */
-  int32_t use_graph;       /* MSP_SYM_PSD, level2_form 1 with k <= 16 (the one-kernel level-2
-                              step): issue the predicted inner steps of every SolveM1 call as one
-                              HIP graph (captured once per solve and chunk length, replayed on the
-                              solve's stream). Same kernels and results as the eager launches.
-                              No effect on MSP_GENERAL solves. Default 0. */
+  int32_t use_graph;       /* level2_form 1: issue the predicted steps of every inner solve on a
+                              formed operator (the PSD level 2, the general level 3) as one HIP
+                              graph, captured once per solve, operator and chunk length and
+                              replayed on the solve's stream. Same kernels and results as the
+                              eager launches. Default 0. */
   int32_t batch_teams;     /* msp_solve_batched: a workgroup whose system is finished helps the
                               A-sweeps of a larger unfinished system (same results bit for bit;
                               chunked partials in a fixed order). Default 1. */

@@ -675,6 +675,39 @@ L2Step l2step_for(SolveCtx& c, Level& L, const double* Minv, const double* W, do
 
 // iterations of an inner FCG on the sketch: chunk = predicted count, then pairs
 // M != null: the operator is the explicit s x s matrix M (a.nbC = 0, wscale = 1)
+// the first P steps of an inner solve on the explicit operator M as one graph (use_graph);
+// keyed by the step count, M, the preconditioner and the solution vector, which fix every
+// kernel argument of the steps within one solve
+msp_status l2_graph(SolveCtx& c, const L2Step& a, const double* M, int P, hipGraphExec_t* out) {
+  const auto key = std::make_tuple(P | (1 << 24), (const void*)M, (const void*)a.Minv, (const void*)a.y);
+  auto it = c.graphs.exec.find(key);
+  if (it != c.graphs.exec.end()) {
+    *out = it->second;
+    return MSP_OK;
+  }
+  c.graphs.st = c.st;
+  if (!c.graphs.cap) MSP_CHECK_HIP(hipStreamCreateWithFlags(&c.graphs.cap, hipStreamNonBlocking));
+  MSP_CHECK_HIP(hipStreamBeginCapture(c.graphs.cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < P && e == hipSuccess; ++i) {
+    e = l2_op_matrix(c.graphs.cap, M, c.s, a.p, c.k, a.S.done, a.wp, a.pqw, a.gscratch, a.gscratch_n);
+    if (e == hipSuccess) e = l2_step(c.graphs.cap, a);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c.graphs.cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    MSP_CHECK_HIP(e != hipSuccess ? e : e2);
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  MSP_CHECK_HIP(e);
+  c.graphs.exec[key] = ex;
+  *out = ex;
+  return MSP_OK;
+}
+
 msp_status run_l2(SolveCtx& c, const L2Step& a_in, const double* W, int slotid, int* last, int64_t* counter,
                   const double* M = nullptr) {
   const msp_precond* P = c.P;
@@ -685,6 +718,20 @@ msp_status run_l2(SolveCtx& c, const L2Step& a_in, const double* W, int slotid, 
   int issued = 0;
   int chunk = std::max(1, *last);
   const int cap = a.max_iter;
+  if (c.o->use_graph && M && chunk <= cap) {  // the predicted chunk as one graph launch
+    hipGraphExec_t ex = nullptr;
+    TRY(l2_graph(c, a, M, chunk, &ex));
+    MSP_CHECK_HIP(hipGraphLaunch(ex, c.st));
+    issued = chunk;
+    TRY(sync(c));
+    if (*slot(c, slotid) == 0 || issued >= cap) {
+      const int taken = *slot(c, slotid + 1);
+      *counter += taken;
+      if (taken > 0) *last = taken;
+      return MSP_OK;
+    }
+    chunk = 2;
+  }
   while (true) {
     for (int i = 0; i < chunk && issued < cap; ++i, ++issued) {
       if (M)

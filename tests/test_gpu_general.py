@@ -166,10 +166,10 @@ def test_general_block_rhs_matrix_core_sweeps():
         assert np.linalg.norm(a @ x[j] - bm[j]) <= 1e-10 * np.linalg.norm(bm[j])
 
 
-def test_general_use_graph_leaves_the_solution_unchanged():
-    # the general level-3 solves take direct products (the one-kernel recurrence step is
-    # PSD only), so use_graph must leave the general solution bit for bit unchanged
-    say("case general use_graph n=400")
+def test_general_graph_replayed_level3_steps_match_eager():
+    # the level-3 step chunks of both product-form solves replayed as graphs (one per
+    # operator and chunk length) give the eager solution bit for bit
+    say("case general graph-replayed level-3 steps n=400")
     n, k, s = 400, 12, 32
     a, sv, _, _ = W.general_outlier(n, k, config_id=103, big=(1e2, 1e4))
     lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
