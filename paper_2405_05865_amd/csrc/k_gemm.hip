@@ -281,7 +281,7 @@ template <class TA, class TC, int RT, int KT>
 hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X,
                   int64_t ldx, double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip,
                   double* dot_part, int* nblocks, double* scratch, size_t scratch_doubles, int min_seg,
-                  int force_nseg) {
+                  int force_nseg, int* nseg_out, bool defer_sum) {
   static_assert(16 * RT == WAVE, "the segment sum takes 64-row sets");
   const int nrs = (int)((rows + 16 * RT - 1) / (16 * RT));
   const int ngroups = (k + 15) / 16;
@@ -303,10 +303,11 @@ hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64
   else
     hipLaunchKernelGGL((k_gemm<TA, TC, RT, KT, false>), dim3(blocks), dim3(256), 0, st, A, lda, (int)rows, (int)cols,
                        X, ldx, Y, ldy, k, lam, diag ? 1 : 0, skip, dot_part, nrs, ncs, nseg, seg_cols, scratch);
-  if (nseg > 1)
+  if (nseg > 1 && !defer_sum)
     hipLaunchKernelGGL(k_gemm_sum, dim3((unsigned)nrs, (unsigned)k), dim3(WAVE), 0, st, scratch, nseg, (int)rows, k, X,
                        ldx, Y, ldy, lam, diag ? 1 : 0, skip, dot_part);
   if (nblocks) *nblocks = nrs;
+  if (nseg_out) *nseg_out = nseg;
   return hipGetLastError();
 }
 
@@ -315,15 +316,16 @@ hipError_t gemm_t(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64
 template <class TA, class TC>
 hipError_t gemm_k(hipStream_t st, const TA* A, int64_t rows, int64_t cols, int64_t lda, const double* X, int64_t ldx,
                   double* Y, int64_t ldy, int k, double lam, bool diag, const int32_t* skip, double* dot_part,
-                  int* nblocks, double* scratch, size_t scratch_doubles, int min_seg = 1024, int force_nseg = 0) {
+                  int* nblocks, double* scratch, size_t scratch_doubles, int min_seg = 1024, int force_nseg = 0,
+                  int* nseg_out = nullptr, bool defer_sum = false) {
   if (k <= 16)
     return gemm_t<TA, TC, 4, 1>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
-                                scratch_doubles, min_seg, force_nseg);
+                                scratch_doubles, min_seg, force_nseg, nseg_out, defer_sum);
   if (sizeof(TC) == 8 || k <= 32)
     return gemm_t<TA, TC, 4, 2>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
-                                scratch_doubles, min_seg, force_nseg);
+                                scratch_doubles, min_seg, force_nseg, nseg_out, defer_sum);
   return gemm_t<TA, TC, 4, 4>(st, A, rows, cols, lda, X, ldx, Y, ldy, k, lam, diag, skip, dot_part, nblocks, scratch,
-                              scratch_doubles, min_seg, force_nseg);
+                              scratch_doubles, min_seg, force_nseg, nseg_out, defer_sum);
 }
 
 // column groups per wavefront as gemm_k picks them (KT)
@@ -524,7 +526,7 @@ size_t gemm_split_doubles(int64_t rows, int64_t k) { return (size_t)16 * rows * 
 
 hipError_t launch_gemm_seg(hipStream_t st, const double* M, int64_t rows, int64_t cols, const double* X,
                            int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip, double* scratch,
-                           size_t scratch_doubles, int min_seg) {
+                           size_t scratch_doubles, int min_seg, int* nseg_out, bool defer_sum) {
   return gemm_k<double, double>(st, M, rows, cols, cols, X, ldx, Y, ldy, (int)k, 0.0, false, skip, nullptr, nullptr,
-                                scratch, scratch_doubles, min_seg);
+                                scratch, scratch_doubles, min_seg, 0, nseg_out, defer_sum);
 }

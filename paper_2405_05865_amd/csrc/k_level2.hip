@@ -450,9 +450,10 @@ __global__ void __launch_bounds__(256) k_l2_prec(L2Args a, int decide) {
   }
 }
 
-// ---- after z = Minv r on the matrix cores: the decision of k_l2_prec for column
-// blockIdx.y and the partials of <z, r> and <z, r_old> over 256 rows per block
-__global__ void __launch_bounds__(256) k_l2_dots(L2Args a, int decide) {
+// ---- after z = Minv r on the matrix cores: z from the product's segment partials (when
+// it was split), the decision of k_l2_prec for column blockIdx.y and the partials of
+// <z, r> and <z, r_old> over 256 rows per block
+__global__ void __launch_bounds__(256) k_l2_dots(L2Args a, int decide, const double* __restrict__ zpart, int nseg) {
   __shared__ double sh[4];
   __shared__ int live_sh;
   const int j = blockIdx.y;
@@ -491,7 +492,14 @@ __global__ void __launch_bounds__(256) k_l2_dots(L2Args a, int decide) {
   double zr = 0.0, zro = 0.0;
   if (live_sh && i < a.s) {
     const int64_t o = (int64_t)j * a.s + i;
-    const double t = a.z[o];
+    double t;
+    if (nseg > 1) {  // the product's segment partials, added in segment order (k_gemm_sum's order)
+      t = 0.0;
+      for (int sg = 0; sg < nseg; ++sg) t += zpart[((int64_t)sg * a.k + j) * a.s + i];
+      a.z[o] = t;
+    } else {
+      t = a.z[o];
+    }
     zr = t * a.r[o];
     zro = (decide == 2) ? 0.0 : t * a.ro[o];
   }
@@ -686,10 +694,13 @@ hipError_t prec_launch(hipStream_t st, const L2Step& a, int decide) {
   L2Args x = make_args(a);
   if (mfma_prec(a)) {
     // columns already done keep their z; at the first application every column is new
+    // the segment sum of z is left to k_l2_dots (one launch less per step)
+    int nseg = 1;
     hipError_t e = launch_gemm_seg(st, a.Minv, a.s, a.s, a.r, a.s, a.z, a.s, a.k, decide == 2 ? nullptr : a.S.done,
-                                   a.gscratch, a.gscratch_n, kSegSmall);
+                                   a.gscratch, a.gscratch_n, kSegSmall, &nseg, true);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_l2_dots, dim3((unsigned)dblocks((int)a.s), (unsigned)a.k), dim3(256), 0, st, x, decide);
+    hipLaunchKernelGGL(k_l2_dots, dim3((unsigned)dblocks((int)a.s), (unsigned)a.k), dim3(256), 0, st, x, decide,
+                       a.gscratch, nseg);
     return hipGetLastError();
   }
   if (cpl <= 1) hipLaunchKernelGGL(k_l2_prec<1>, dim3(blocks), dim3(256), 0, st, x, decide);

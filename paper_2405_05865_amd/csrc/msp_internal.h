@@ -132,9 +132,11 @@ hipError_t tune_block_sweep(hipStream_t st, const void* A, msp_dtype a_t, bool f
 // until about 2048 wavefronts run (scratch of at least gemm_split_doubles(rows, k)
 // doubles). The level-1 sweep keeps min_seg = 1024 (long streams from HBM); the s x s
 // inner operators, which stay in cache, take 64; the s x n level-2 factor takes 256.
+// With defer_sum and more than one segment the segment partials stay in the scratch
+// (layout [segment][column][row], *nseg_out segments) for the consumer to add in order.
 hipError_t launch_gemm_seg(hipStream_t st, const double* M, int64_t rows, int64_t cols, const double* X,
                            int64_t ldx, double* Y, int64_t ldy, int64_t k, const int32_t* skip, double* scratch,
-                           size_t scratch_doubles, int min_seg);
+                           size_t scratch_doubles, int min_seg, int* nseg_out = nullptr, bool defer_sum = false);
 constexpr int kSegSmall = 64;
 constexpr int kSegWide = 256;
 // Y[:, j] = A^T X[:, j] on the matrix cores for k >= kGemmMinK (same contract as
