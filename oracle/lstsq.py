@@ -7,7 +7,7 @@ Steps in the corollary's order:
   2. An outer iterative least-squares solver on A^T A x = A^T b preconditioned by
      (A~^T A~)^{-1}; each application is a ridge-free normal-equation solve with A~, done by
      the three-level MSP of Algorithms 3-5 to a constant relative accuracy.
-Readings (listed with the others in the design notes): the outer solver is the flexible
+Readings where the corollary leaves the solver open: the outer solver is the flexible
 PCG used at every other level; it stops on |A^T (b - A x)| <= tol |A^T b|, confirmed on the
 recomputed residual; the inner accuracy is a parameter (inner_rel).
 

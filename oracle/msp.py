@@ -5,7 +5,7 @@ PsdMsp      Algorithm 1 (two-level MSP for (A + lam I) x = b, A PSD) with
 GeneralMsp  Algorithm 3 (three-level MSP for (A^T A + lam I) x = c) with
             Algorithm 4 (SolveM1) and Algorithm 5 (SolveM2, level 3).
 
-Readings taken where the paper is silent or loose (each listed in the design notes):
+Readings taken where the paper is silent or loose:
   * lam~ = lam + lam0 everywhere, including M2 and M3b (Section 4 uses lam once).
   * Phi is a Definition 2.1 sketch with phi rows and phi_gamma nonzeros per column,
     drawn from its own seed (Lemma 2.2 only cites a construction).
