@@ -197,7 +197,9 @@ extern "C" msp_status msp_lstsq(void* stream, const msp_precond* P, const double
     msp_solve_info ii{};
     const msp_status s_ = msp_solve(stream, P, At, MSP_F64, At, MSP_F64, ldat, r, d, k, z, d, &io, w.inner, inner,
                                     &ii);
-    if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) return s_;
+    // an inner solve that stops early (cap or breakdown) still returns its iterate, which the
+    // flexible outer iteration can use
+    if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE && s_ != MSP_ERR_BREAKDOWN) return s_;
     acc.inner_iters += ii.outer_iters;
     acc.level3_iters += ii.inner_iters + ii.level3_iters;
     return MSP_OK;
