@@ -9,7 +9,6 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int WAVE = 64;
-constexpr int MAXK = 1024;  // columns per level handled by the single-block finalisers
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

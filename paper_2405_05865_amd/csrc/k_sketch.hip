@@ -110,13 +110,6 @@ __global__ void k_bucket_place(const int32_t* __restrict__ rows, const int8_t* _
 }
 
 // ---- Y = A S^T: LDS-staged row tiles, one thread per sketch row (bucket) ----------
-template <class T>
-__device__ __forceinline__ float to_f32(T v);
-template <>
-__device__ __forceinline__ float to_f32<float>(float v) { return v; }
-template <>
-__device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 v) { return __bfloat162float(v); }
-
 template <class TA, class TACC>
 __device__ __forceinline__ TACC load_as(const TA v);
 template <>
@@ -125,8 +118,6 @@ template <>
 __device__ __forceinline__ float load_as<float, float>(const float v) { return v; }
 template <>
 __device__ __forceinline__ float load_as<__hip_bfloat16, float>(const __hip_bfloat16 v) { return __bfloat162float(v); }
-template <>
-__device__ __forceinline__ double load_as<float, double>(const float v) { return (double)v; }
 
 template <class TA, class TACC, class TY, int R, int BPT>
 __global__ void __launch_bounds__(256) k_sketch_apply(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
