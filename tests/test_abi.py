@@ -102,3 +102,19 @@ def test_least_squares_validation_before_device_work():
     info = B.SolveInfo()
     assert L.msp_lstsq(None, None, None, 0, None, 0, 10, 10, None, 10, 1, None, 10, ctypes.byref(o), None, 0,
                        ctypes.byref(info)) == 1
+
+
+@pytest.mark.parametrize("cc,std", [("gcc", "-std=c99"), ("g++", "-std=c++17")])
+def test_header_compiles_as_c_and_cpp(tmp_path, cc, std):
+    # the boundary is plain C: no HIP or torch types, usable from C and C++ callers
+    import shutil
+    import subprocess
+    if shutil.which(cc) is None:
+        pytest.skip(f"{cc} not available")
+    src = tmp_path / ("t.c" if cc == "gcc" else "t.cpp")
+    src.write_text('#include "msp.h"\nint main(void) { msp_solve_opts o; msp_solve_opts_default(&o); '
+                   'return (int)sizeof(msp_solve_info) > 0 ? 0 : 1; }\n')
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([cc, std, "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I", inc, str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
