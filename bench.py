@@ -133,8 +133,8 @@ def main():
                     help="batched: systems timed with the plain FP64 single-RHS solve for comparison")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharded design is described, not built). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(row sharding is designed, not implemented). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -36,7 +36,7 @@ typedef enum {
   MSP_ERR_NO_CONVERGENCE = 4,/* iteration cap reached; best iterate returned */
   MSP_ERR_NONFINITE = 5,     /* NaN/Inf in an input scalar or a residual */
   MSP_ERR_WORKSPACE = 6,     /* workspace too small or misaligned */
-  MSP_ERR_UNSUPPORTED = 7,   /* valid request outside what this build implements */
+  MSP_ERR_UNSUPPORTED = 7,   /* valid request outside what the library implements */
   MSP_ERR_HIP = 8            /* a HIP runtime call failed */
 } msp_status;
 
