@@ -215,3 +215,28 @@ def test_general_ridge_normal_equations():
     res = P.solve_normal(c)
     xs = dense.solve_ridge(a, c, lam)
     assert np.linalg.norm(res.x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_level3_preconditioner_quality():
+    # Section 5: A^ = Phi A~ embeds the column space of A~ (phi = 4s rows), so M3a = A^T A^
+    # and M3b = M3a + lam~ I are within a constant of W = A~^T A~ and W + lam~ I:
+    # kappa(M3a^{-1} W), kappa(M3b^{-1} (W + lam~ I)) <= ((1+eps)/(1-eps))^2 = 9 at eps = 1/2
+    a, sv, _, _ = W.general_outlier(400, 12, config_id=104, big=(1e2, 1e4))
+    lam0 = msp.paper_lambda0(np.sort(sv)[::-1] ** 2, 16)
+    P = _general(a, 0.0, lam0, 32)
+    wm = P.at.T @ P.at
+    for minv, op in ((P.m3a_inv, wm), (P.m3b_inv, wm + P.lt * np.eye(32))):
+        ev = np.linalg.eigvals(minv @ op).real
+        assert ev.min() > 0 and ev.max() / ev.min() <= 9.0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_effective_dimension_bound_at_lambda0(seed):
+    # with the paper's lam0 = (2/l) sum_{i>l} lambda_i: d_lam0 = sum_i lambda_i/(lambda_i + lam0)
+    # <= l (the top l terms) + sum_{i>l} lambda_i / lam0 = l + l/2
+    r = np.random.default_rng(seed)
+    for l in (4, 16, 64):
+        eigs = np.sort(np.concatenate([10.0 ** r.uniform(1, 6, size=l // 2), r.uniform(0, 1, size=500)]))[::-1]
+        lam0 = msp.paper_lambda0(eigs, l)
+        d = dense.effective_dimension(eigs, lam0)
+        assert d <= 1.5 * l + 1e-9
