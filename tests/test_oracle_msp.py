@@ -240,3 +240,19 @@ def test_effective_dimension_bound_at_lambda0(seed):
         lam0 = msp.paper_lambda0(eigs, l)
         d = dense.effective_dimension(eigs, lam0)
         assert d <= 1.5 * l + 1e-9
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_effective_dimension_lemma(seed):
+    # Lemma 2.1: (1) j >= (1 + 1/g) d_lam implies lambda_j <= g lam; (2) k >= d_lam implies
+    # sum_{i>k} lambda_i <= lam d_lam (eigenvalues non-increasing, indices from 1)
+    r = np.random.default_rng(seed)
+    eigs = np.sort(np.concatenate([10.0 ** r.uniform(0, 5, size=40), r.uniform(0, 1e-1, size=400)]))[::-1]
+    for lam in (1e-3, 1e-1, 10.0):
+        d = dense.effective_dimension(eigs, lam)
+        for g in (0.25, 1.0, 4.0):
+            j = int(np.ceil((1 + 1 / g) * d))
+            if j <= eigs.size:
+                assert eigs[j - 1] <= g * lam * (1 + 1e-12)
+        k = int(np.ceil(d))
+        assert eigs[k:].sum() <= lam * d * (1 + 1e-12)
