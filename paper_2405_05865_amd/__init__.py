@@ -379,6 +379,10 @@ def lstsq(P: Precond, At: torch.Tensor, A: torch.Tensor, Bv: torch.Tensor, **opt
     _rowmajor(At, "A~")
     if At.dtype != torch.float64:
         raise ValueError("A~ must be float64")
+    if P.structure != "general" or tuple(At.shape) != (P.m, P.n):
+        raise ValueError("P must be the MSP_GENERAL handle built from this A~ (shape (q, d))")
+    if A.shape[1] != P.n or A.shape[0] < P.n:
+        raise ValueError("A must be tall (n x d, n >= d) with the d columns of A~")
     n = A.shape[0]
     o = _opts(**opts)
     k, ldb = _vectors(Bv, n, "B")
