@@ -765,12 +765,17 @@ struct Batch {
         }
         zr = wsum(zr);
         zro = wsum(zro);
-        const double beta = (zr - zro) / D->rz[w];
-        _Pragma("unroll 4") for (int i = lane; i < c.s; i += WAVE) {
-          const int64_t o = (int64_t)w * c.lds + i;
-          c.p2[o] = fma(beta, c.p2[o], c.z2[o]);
+        const double rzo = D->rz[w];
+        if (rzo != 0.0 && isfinite(rzo)) {
+          const double beta = (zr - zro) / rzo;
+          _Pragma("unroll 4") for (int i = lane; i < c.s; i += WAVE) {
+            const int64_t o = (int64_t)w * c.lds + i;
+            c.p2[o] = fma(beta, c.p2[o], c.z2[o]);
+          }
+          if (lane == 0) D->rz[w] = zr;
+        } else if (lane == 0) {
+          D->done[w] = 2;  // beta's denominator vanished: breakdown, the iterate is kept
         }
-        if (lane == 0) D->rz[w] = zr;
       }
     }
     if (threadIdx.x == 0) {
@@ -900,12 +905,17 @@ struct Batch {
         }
         zr = wsum(zr);
         zro = wsum(zro);
-        const double beta = (zr - zro) / C->rz[w];
-        _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
-          const int64_t o = (int64_t)w * c.ldn + i;
-          c.p1[o] = fma(beta, c.p1[o], c.z1[o]);
+        const double rzo = C->rz[w];
+        if (rzo != 0.0 && isfinite(rzo)) {
+          const double beta = (zr - zro) / rzo;
+          _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
+            const int64_t o = (int64_t)w * c.ldn + i;
+            c.p1[o] = fma(beta, c.p1[o], c.z1[o]);
+          }
+          if (lane == 0) C->rz[w] = zr;
+        } else if (lane == 0) {
+          C->done[w] = 2;  // beta's denominator vanished: breakdown, the iterate is kept
         }
-        if (lane == 0) C->rz[w] = zr;
       }
     }
     if (threadIdx.x == 0) {
@@ -1031,12 +1041,17 @@ struct Batch {
         }
         zr = wsum(zr);
         zro = wsum(zro);
-        const double beta = (zr - zro) / R->rz[w];
-        _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
-          const int64_t o = (int64_t)w * c.ldn + i;
-          c.ph[o] = fma(beta, c.ph[o], c.zh[o]);
+        const double rzo = R->rz[w];
+        if (rzo != 0.0 && isfinite(rzo)) {
+          const double beta = (zr - zro) / rzo;
+          _Pragma("unroll 4") for (int i = lane; i < c.n; i += WAVE) {
+            const int64_t o = (int64_t)w * c.ldn + i;
+            c.ph[o] = fma(beta, c.ph[o], c.zh[o]);
+          }
+          if (lane == 0) R->rz[w] = zr;
+        } else if (lane == 0) {
+          R->done[w] = 2;  // beta's denominator vanished: breakdown, the iterate is kept
         }
-        if (lane == 0) R->rz[w] = zr;
       }
     }
     if (threadIdx.x == 0) {

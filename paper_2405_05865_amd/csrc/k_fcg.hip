@@ -284,7 +284,11 @@ __global__ void __launch_bounds__(NT) k_beta(FcgState S, int64_t len, const doub
 }
 
 // beta = <z, r - r_old> / rz and rz = <z, r> from the partials of k_beta, in one block (a
-// separate launch instead of a fenced last-block hand-off)
+// separate launch instead of a fenced last-block hand-off). When the denominator
+// rz = <r_old, z_old> is zero or not finite no conjugate direction exists (an inexact
+// preconditioner that is not positive definite): the column stops as a breakdown and
+// keeps its iterate; k_pupdate then leaves p alone and the next decision recounts the
+// active columns.
 __global__ void __launch_bounds__(NT) k_beta_fin(FcgState S, int nblocks) {
   __shared__ double sh[NT / WAVE];
   for (int64_t jj = 0; jj < S.k; ++jj) {
@@ -292,8 +296,14 @@ __global__ void __launch_bounds__(NT) k_beta_fin(FcgState S, int nblocks) {
     const double zr = strided_sum(S.part + jj * 2 + 0, nblocks, S.k * 2, sh);
     const double zro = strided_sum(S.part + jj * 2 + 1, nblocks, S.k * 2, sh);
     if (threadIdx.x == 0) {
-      S.beta[jj] = (zr - zro) / S.rz[jj];
-      S.rz[jj] = zr;
+      const double rz = S.rz[jj];
+      if (rz != 0.0 && isfinite(rz)) {
+        S.beta[jj] = (zr - zro) / rz;
+        S.rz[jj] = zr;
+      } else {
+        S.beta[jj] = 0.0;
+        S.done[jj] = 2;
+      }
     }
   }
 }

@@ -185,7 +185,11 @@ __global__ void __launch_bounds__(NT) k_l2x_step(L2xArgs a, int par, int first) 
       zu = fma(zv[q], uv[q], zu);
     }
     block_sum2(zr, zu, sh);
-    const double beta = first ? 0.0 : -a.al[cur][j] * zu / a.rz[cur][j];
+    // beta's denominator <r_{t-1}, z_{t-1}> zero or not finite: no conjugate direction
+    // exists; the column stops as a breakdown below (alpha = 0 keeps its iterate)
+    const double rzo = a.rz[cur][j];
+    const bool rzbad = !first && !(rzo != 0.0 && isfinite(rzo));
+    const double beta = (first || rzbad) ? 0.0 : -a.al[cur][j] * zu / rzo;
     double pq = 0.0;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -196,7 +200,7 @@ __global__ void __launch_bounds__(NT) k_l2x_step(L2xArgs a, int par, int first) 
       pq = fma(pv[q], uv[q], pq);
     }
     pq = block_sum1(pq, sh);
-    const bool brk = !(pq > 0.0);
+    const bool brk = rzbad || !(pq > 0.0);
     const double alpha = brk ? 0.0 : zr / pq;
     double rr = 0.0;
 #pragma unroll

@@ -540,11 +540,20 @@ __global__ void __launch_bounds__(256) k_l2_dir(L2Args a, int first) {
   __shared__ double shs[4];
   const int j = blockIdx.x;
   const int np = a.ndp;
-  const int dj = a.S.done_next[j];
+  int dj = a.S.done_next[j];
+  // beta's denominator <r_old, z_old> zero or not finite: no conjugate direction exists
+  // (an inexact preconditioner that is not positive definite); the column stops as a
+  // breakdown and keeps its iterate
+  const double rzo = a.S.rz[j];
+  if (dj == 0 && !first && !(rzo != 0.0 && isfinite(rzo))) {
+    dj = 2;
+    __syncthreads();  // every thread has read done_next[j] before thread 0 rewrites it
+    if (threadIdx.x == 0) a.S.done_next[j] = 2;
+  }
   if (dj == 0) {
     const double zr = strided_sum<256>(a.dpart + (int64_t)j * 2 + 0, np, (int64_t)a.k * 2, shs);
     const double zro = strided_sum<256>(a.dpart + (int64_t)j * 2 + 1, np, (int64_t)a.k * 2, shs);
-    const double beta = first ? 0.0 : (zr - zro) / a.S.rz[j];
+    const double beta = first ? 0.0 : (zr - zro) / rzo;
     for (int c = threadIdx.x; c < a.s; c += 256) {
       const int64_t o = (int64_t)j * a.s + c;
       a.p[o] = first ? a.z[o] : fma(beta, a.p[o], a.z[o]);
