@@ -11,7 +11,12 @@
  *   - Every call enqueues its device work on `stream` (hipStream_t passed as void*);
  *     calls that fill [host] outputs synchronise the stream before returning.
  *   - The caller owns all device memory, including the workspaces whose sizes the
- *     *_workspace queries return; the library never allocates device memory.
+ *     *_workspace queries return; the library never allocates device memory. On the
+ *     host, msp_nystrom allocates one 4 KiB page of pinned, device-mapped memory per
+ *     handle (the mirror through which solves read convergence flags), solves with
+ *     profile != 0 create HIP events (kept in the handle), and solves with use_graph
+ *     != 0 create a capture stream and graphs (freed at return); msp_precond_destroy
+ *     frees the rest.
  *   - Errors: every call returns an msp_status; no call throws or aborts.
  *     Arguments are validated before any device work is enqueued. msp_last_error()
  *     returns a thread-local message describing the last failure.
@@ -139,9 +144,20 @@ msp_status msp_precond_set_lambda(void* stream, msp_precond* P, double lambda);
  * after two steps that fail to halve the residual it switches to Krylov refinement
  * (flexible PCG on A_hi with MSP_lo as preconditioner). A_hi may equal A_lo.
  *
+ *   lambda   lam >= 0 of the system solved: (A + lam I) (PSD) or A^T A + lam I (general with
+ *            normal != 0; A x = b needs lam = 0). The preconditioner is the handle's, built
+ *            for lam~ = lam_P + lam0 (msp_nystrom / msp_precond_set_lambda); with lam != lam_P
+ *            it is reused as it is (still symmetric positive definite, so the iteration
+ *            converges; the step count grows as lam moves away from lam_P).
  *   B        k right-hand sides (PSD: n each, general: m each), ld ldb, FP64
  *   X        out, k solutions of length n, ld ldx, FP64
  *   info     [host] out, may be NULL
+ * Under refinement, max_outer caps the level-1 steps of all inner solves together. A
+ * refinement step "stalls" when it fails to halve some unconverged residual; after two
+ * stalled steps the PSD path switches to Krylov refinement and the general path tightens
+ * refine_inner_tol by 100x (floor 1e-12) once per stall; it stops with
+ * MSP_ERR_NO_CONVERGENCE and the best iterate seen when the step after a tightening also
+ * stalls, at the floor, or (level2_form 2, no inner level to tighten) at the first stall.
  * Synchronises the stream before returning.
  * ------------------------------------------------------------------------------ */
 typedef struct {
@@ -208,13 +224,15 @@ typedef struct {
   int64_t timed_sweeps;     /* profile != 0: number of sweeps in sweep_ms */
   int32_t sweep_segments;   /* k >= 8: reduction segments of the level-1 block sweep (tuned with
                                autotune, else the built-in rule); 0 for the other sweeps */
+  double seconds;           /* host wall-clock time of the call, entry to return (the call
+                               synchronises before returning, so this includes the device work) */
 } msp_solve_info;
 
 void msp_solve_opts_default(msp_solve_opts* o /*host*/);
 msp_status msp_solve_workspace(const msp_precond* P, int64_t k, const msp_solve_opts* opts, size_t* bytes /*host*/);
 msp_status msp_solve(void* stream, const msp_precond* P,
                      const void* A_hi, msp_dtype hi_t, const void* A_lo, msp_dtype lo_t, int64_t lda,
-                     const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx,
+                     double lambda, const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx,
                      const msp_solve_opts* opts, void* ws, size_t ws_bytes, msp_solve_info* info /*host*/);
 
 /* ---------------------------------------------------------------------------------
@@ -303,14 +321,14 @@ msp_status msp_solve_batched_backward(void* stream, int32_t nsys, const msp_syst
  * msp_solve_backward -- adjoint of X = (A + lam I)^{-1} B for symmetric PSD A.
  *
  * Given G = dL/dX: dB = (A + lam I)^{-T} G = (A + lam I)^{-1} G (A symmetric), solved
- * with the same handle and iteration as msp_solve; dlambda = -sum_j <dB_j, X_j>;
+ * with the same handle, lam and iteration as msp_solve; dlambda = -sum_j <dB_j, X_j>;
  * dA = -dB X^T, written densely (n x n, ld ldda) only when dA != NULL.
  *   dlambda  [host] out, may be NULL
  * MSP_GENERAL handles return MSP_ERR_UNSUPPORTED.
  * ------------------------------------------------------------------------------ */
 msp_status msp_solve_backward(void* stream, const msp_precond* P,
                               const void* A_hi, msp_dtype hi_t, const void* A_lo, msp_dtype lo_t, int64_t lda,
-                              const double* X, int64_t ldx, const double* G, int64_t ldg, int64_t k,
+                              double lambda, const double* X, int64_t ldx, const double* G, int64_t ldg, int64_t k,
                               double* dB, int64_t lddb, double* dlambda /*host*/, double* dA, int64_t ldda,
                               const msp_solve_opts* opts, void* ws, size_t ws_bytes, msp_solve_info* info /*host*/);
 

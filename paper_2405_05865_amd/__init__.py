@@ -46,6 +46,43 @@ def _rowmajor(A: torch.Tensor, name: str):
         raise ValueError(f"{name} must be a CUDA (HIP) tensor")
 
 
+def _check_layout(P, A: torch.Tensor, name: str, rows: int | None = None):
+    """A is the handle's matrix: (n, n) for a "psd" handle, (m, n) for a "general" one (or
+    `rows` x n), a supported dtype, row-major with ld >= n. The C-ABI cannot see A's extent,
+    so this is checked before any launch."""
+    if not isinstance(A, torch.Tensor) or A.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D tensor")
+    if rows is None:
+        rows = P.m if P.structure == "general" else P.n
+    if tuple(A.shape) != (rows, P.n):
+        raise ValueError(f"{name} must have shape ({rows}, {P.n}) for this handle, got {tuple(A.shape)}")
+    if A.dtype not in _DT:
+        raise TypeError(f"{name}: unsupported dtype {A.dtype}")
+    if A.stride(1) != 1 or A.stride(0) < P.n:
+        raise ValueError(f"{name} must be row-major with leading dimension >= {P.n}")
+
+
+def _check_device(A: torch.Tensor, name: str, dev=None):
+    if not A.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if dev is not None and A.device != dev:
+        raise ValueError(f"{name} is on {A.device}, the vectors on {dev}")
+
+
+def _pair(P, A_hi, A_lo, dev, rows=None):
+    """Checks A_hi and A_lo (A_lo None: A_hi) against the handle and returns A_lo."""
+    A_lo = A_hi if A_lo is None else A_lo
+    _check_layout(P, A_hi, "A_hi", rows)
+    _check_layout(P, A_lo, "A_lo", rows)
+    if A_hi.dtype == torch.bfloat16:
+        raise TypeError("A_hi must be float64 or float32")
+    if A_hi.stride(0) != A_lo.stride(0):
+        raise ValueError("A_hi and A_lo must share the leading dimension")
+    _check_device(A_hi, "A_hi", dev)
+    _check_device(A_lo, "A_lo", dev)
+    return A_lo
+
+
 def _workspace(nbytes: int, dev) -> torch.Tensor:
     ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
@@ -169,15 +206,14 @@ def nystrom(structure, S_rows, S_signs, Y, lam, lam0, phi, phi_gamma, phi_seed) 
 # -----------------------------------------------------------------------------------
 # msp_solve / msp_solve_backward
 # -----------------------------------------------------------------------------------
-def solve(P: Precond, A_hi: torch.Tensor, Bv: torch.Tensor, A_lo: torch.Tensor | None = None, **opts):
-    """X solving the system of P's structure for the right-hand sides Bv ((n,) or (k, n)).
-    Returns (X, info dict)."""
+def solve(P: Precond, A_hi: torch.Tensor, Bv: torch.Tensor, A_lo: torch.Tensor | None = None,
+          lam: float | None = None, **opts):
+    """X solving the system of P's structure for the right-hand sides Bv ((n,) or (k, n)),
+    with regulariser lam (default: the handle's; another value reuses the handle's
+    preconditioner). Returns (X, info dict)."""
     L = library()
-    A_lo = A_hi if A_lo is None else A_lo
-    _rowmajor(A_hi, "A_hi")
-    _rowmajor(A_lo, "A_lo")
-    if A_hi.stride(0) != A_lo.stride(0):
-        raise ValueError("A_hi and A_lo must share the leading dimension")
+    A_lo = _pair(P, A_hi, A_lo, Bv.device)
+    lam = P.lam if lam is None else float(lam)
     o = _opts(**opts)
     blen = P.m if (P.structure == "general" and not o.normal) else P.n
     k, ldb = _vectors(Bv, blen, "B")
@@ -187,8 +223,8 @@ def solve(P: Precond, A_hi: torch.Tensor, Bv: torch.Tensor, A_lo: torch.Tensor |
     ws = _workspace(need.value, Bv.device)
     info = SolveInfo()
     code = L.msp_solve(_stream(Bv.device), P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(), _code(A_lo),
-                       A_hi.stride(0), Bv.data_ptr(), ldb, k, X.data_ptr(), P.n, ctypes.byref(o), ws.data_ptr(),
-                       ws.numel(), ctypes.byref(info))
+                       A_hi.stride(0), lam, Bv.data_ptr(), ldb, k, X.data_ptr(), P.n, ctypes.byref(o),
+                       ws.data_ptr(), ws.numel(), ctypes.byref(info))
     if code not in (0, 3, 4):
         B.check(code)
     d = info.as_dict()
@@ -216,13 +252,9 @@ def solve_batched(systems, **opts):
     for i, (P, A_hi, A_lo, Bv) in enumerate(systems):
         if P.structure != "psd":
             raise ValueError("batched solves take 'psd' handles")
-        A_lo = A_hi if A_lo is None else A_lo
-        _rowmajor(A_hi, "A_hi")
-        _rowmajor(A_lo, "A_lo")
-        if A_hi.stride(0) != A_lo.stride(0):
-            raise ValueError("A_hi and A_lo must share the leading dimension")
         if Bv.dim() != 2:
             raise ValueError("Bv must be (k, n)")
+        A_lo = _pair(P, A_hi, A_lo, Bv.device)
         kk, ldb = _vectors(Bv, P.n, "B")
         if k is None:
             k, hi_t, lo_t, dev = kk, _code(A_hi), _code(A_lo), Bv.device
@@ -263,11 +295,7 @@ def solve_batched_backward(systems, Xs, Gs, want_dA: bool = False, **opts):
         P, A_hi, A_lo = sysd[0], sysd[1], sysd[2]
         if P.structure != "psd":
             raise ValueError("batched adjoints take 'psd' handles")
-        A_lo = A_hi if A_lo is None else A_lo
-        _rowmajor(A_hi, "A_hi")
-        _rowmajor(A_lo, "A_lo")
-        if A_hi.stride(0) != A_lo.stride(0):
-            raise ValueError("A_hi and A_lo must share the leading dimension")
+        A_lo = _pair(P, A_hi, A_lo, Gs[i].device)
         kx, ldx = _vectors(Xs[i], P.n, "X")
         kg, ldg = _vectors(Gs[i], P.n, "G")
         if kx != kg:
@@ -296,10 +324,12 @@ def solve_batched_backward(systems, Xs, Gs, want_dA: bool = False, **opts):
     return dbs, [dl[i] for i in range(nsys)], das, [infos[i].as_dict() for i in range(nsys)]
 
 
-def solve_backward(P: Precond, A_hi, X, G, A_lo=None, want_dA: bool = False, **opts):
-    """Adjoint of X = (A + lam I)^{-1} B for PSD A. Returns (dB, dlam, dA or None, info)."""
+def solve_backward(P: Precond, A_hi, X, G, A_lo=None, want_dA: bool = False, lam: float | None = None, **opts):
+    """Adjoint of X = (A + lam I)^{-1} B for PSD A (lam default: the handle's). Returns
+    (dB, dlam, dA or None, info)."""
     L = library()
-    A_lo = A_hi if A_lo is None else A_lo
+    A_lo = _pair(P, A_hi, A_lo, G.device)
+    lam = P.lam if lam is None else float(lam)
     o = _opts(**opts)
     k, ldx = _vectors(X, P.n, "X")
     k2, ldg = _vectors(G, P.n, "G")
@@ -313,7 +343,8 @@ def solve_backward(P: Precond, A_hi, X, G, A_lo=None, want_dA: bool = False, **o
     ws = _workspace(need.value, G.device)
     info = SolveInfo()
     code = L.msp_solve_backward(_stream(G.device), P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(),
-                                _code(A_lo), A_hi.stride(0), X.data_ptr(), ldx, G.data_ptr(), ldg, k, dB.data_ptr(),
+                                _code(A_lo), A_hi.stride(0), lam, X.data_ptr(), ldx, G.data_ptr(), ldg, k,
+                                dB.data_ptr(),
                                 P.n, ctypes.byref(dl), dA.data_ptr() if dA is not None else None, P.n,
                                 ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(info))
     if code not in (0, 3, 4):
@@ -326,7 +357,7 @@ def schatten(P: Precond, A_hi, probes, p: float = 1.0, A_lo=None, h: float = 1.5
     """Hutchinson + quadrature estimate of ||A||_p^p (kind "schatten", P general) or of
     d_lam (kind "effdim", P psd; p is lam). Returns (estimate, std_err, info)."""
     L = library()
-    A_lo = A_hi if A_lo is None else A_lo
+    A_lo = _pair(P, A_hi, A_lo, probes.device)
     o = _opts(**opts)
     N, ldg = _vectors(probes, P.n, "probes")
     need = B.size_out()
@@ -426,13 +457,20 @@ def msp_solve(A: torch.Tensor, Bv: torch.Tensor, lam: float, lam0: float, sp: Sk
 
 class MSPSolve(torch.autograd.Function):
     """X = (A + lam I)^{-1} B for symmetric PSD A through MSP, with the adjoint solve
-    (msp_solve_backward) reusing the same preconditioner."""
+    (msp_solve_backward) reusing the same preconditioner. The solve and its adjoint use the
+    value of `lam` (a float or a 0-d tensor), whatever the handle was built for; a value
+    far from the handle's lambda only costs iterations. A solve or adjoint that does not
+    reach its tolerance raises MspError."""
 
     @staticmethod
     def forward(ctx, A, Bv, lam, P, opts):
-        X, info = solve(P, A, Bv, **opts)
+        lv = float(lam.detach().item() if isinstance(lam, torch.Tensor) else lam)
+        X, info = solve(P, A, Bv, lam=lv, **opts)
+        if info["status"] != "MSP_OK":
+            raise MspError(B.STATUS_CODE[info["status"]], f"forward solve: {info['status']}")
         ctx.save_for_backward(A, X)
         ctx.P = P
+        ctx.lam = lv
         ctx.opts = opts
         ctx.info = info
         return X
@@ -441,6 +479,8 @@ class MSPSolve(torch.autograd.Function):
     def backward(ctx, G):
         A, X = ctx.saved_tensors
         want_dA = ctx.needs_input_grad[0]
-        dB, dlam, dA, _ = solve_backward(ctx.P, A, X, G.contiguous(), want_dA=want_dA, **ctx.opts)
+        dB, dlam, dA, info = solve_backward(ctx.P, A, X, G.contiguous(), want_dA=want_dA, lam=ctx.lam, **ctx.opts)
+        if info["status"] != "MSP_OK":
+            raise MspError(B.STATUS_CODE[info["status"]], f"adjoint solve: {info['status']}")
         dl = torch.tensor(dlam, dtype=torch.float64, device=G.device) if ctx.needs_input_grad[2] else None
         return dA, dB, dl, None, None

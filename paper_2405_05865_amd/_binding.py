@@ -37,6 +37,9 @@ EXPORTS = (
 )
 
 
+STATUS_CODE = {v: k for k, v in STATUS.items()}
+
+
 class MspError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -112,6 +115,7 @@ class SolveInfo(ctypes.Structure):
         ("sweep_ms", ctypes.c_double),
         ("timed_sweeps", ctypes.c_int64),
         ("sweep_segments", ctypes.c_int32),
+        ("seconds", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -155,7 +159,7 @@ def load(path: str | None = None):
     L.msp_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
     L.msp_solve_opts_default.restype = None
     L.msp_solve_workspace.argtypes = [P, I64, ctypes.POINTER(SolveOpts), SZ]
-    L.msp_solve.argtypes = [P, P, P, ctypes.c_int, P, ctypes.c_int, I64, P, I64, I64, P, I64,
+    L.msp_solve.argtypes = [P, P, P, ctypes.c_int, P, ctypes.c_int, I64, D, P, I64, I64, P, I64,
                             ctypes.POINTER(SolveOpts), P, ctypes.c_size_t, ctypes.POINTER(SolveInfo)]
     L.msp_solve_batched_workspace.argtypes = [I32, ctypes.POINTER(System), I64, ctypes.POINTER(SolveOpts), SZ]
     L.msp_solve_batched.argtypes = [P, I32, ctypes.POINTER(System), ctypes.c_int, ctypes.c_int, I64,
@@ -165,7 +169,7 @@ def load(path: str | None = None):
     L.msp_solve_batched_backward.argtypes = [P, I32, ctypes.POINTER(SystemGrad), ctypes.c_int, ctypes.c_int, I64,
                                              ctypes.POINTER(SolveOpts), P, ctypes.c_size_t, ctypes.POINTER(D),
                                              ctypes.POINTER(SolveInfo)]
-    L.msp_solve_backward.argtypes = [P, P, P, ctypes.c_int, P, ctypes.c_int, I64, P, I64, P, I64, I64, P, I64,
+    L.msp_solve_backward.argtypes = [P, P, P, ctypes.c_int, P, ctypes.c_int, I64, D, P, I64, P, I64, I64, P, I64,
                                      ctypes.POINTER(D), P, I64, ctypes.POINTER(SolveOpts), P, ctypes.c_size_t,
                                      ctypes.POINTER(SolveInfo)]
     L.msp_schatten_workspace.argtypes = [P, I64, ctypes.POINTER(SolveOpts), SZ]

@@ -5,6 +5,8 @@
 // residual; finished columns are skipped by every kernel.
 #include "msp_internal.h"
 
+#include <algorithm>
+
 namespace {
 
 constexpr int NT = 256;
@@ -385,25 +387,45 @@ __global__ void k_outer_neg(int64_t n, int k, const double* __restrict__ dB, int
     }
 }
 
-// out[0] = max_i sum_j |A[i, j]| (FP64; one block, fixed order)
+// part[b] = max over the rows of block b (a wavefront per row, rows strided by the grid)
+// of sum_j |A[i, j]| in FP64; a max is exact, so the result does not depend on the grid
 template <class TA>
 __global__ void __launch_bounds__(NT) k_row_abs_max(const TA* __restrict__ A, int64_t rows, int64_t cols, int64_t lda,
-                                                   double* out) {
+                                                   double* part) {
   __shared__ double sh[NT / WAVE];
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   double mx = 0.0;
-  for (int64_t r = w; r < rows; r += NT / WAVE) {
-    double t = 0.0;
-    for (int64_t c = lane; c < cols; c += WAVE) t += fabs((double)A[r * lda + c]);
-    mx = fmax(mx, wave_sum(t));
+  for (int64_t r = (int64_t)blockIdx.x * (NT / WAVE) + w; r < rows; r += (int64_t)gridDim.x * (NT / WAVE)) {
+    const TA* row = A + r * lda;
+    double t0 = 0.0, t1 = 0.0;
+    int64_t c = lane;
+    for (; c + WAVE < cols; c += 2 * WAVE) {
+      t0 += fabs((double)row[c]);
+      t1 += fabs((double)row[c + WAVE]);
+    }
+    if (c < cols) t0 += fabs((double)row[c]);
+    mx = fmax(mx, wave_sum(t0 + t1));
   }
   if (lane == 0) sh[w] = mx;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = 0.0;
     for (int q = 0; q < NT / WAVE; ++q) m = fmax(m, sh[q]);
-    out[0] = m;
+    part[blockIdx.x] = m;
   }
+}
+
+__global__ void __launch_bounds__(NT) k_max_parts(const double* __restrict__ part, int nparts, double* out) {
+  __shared__ double sh[NT];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += NT) m = fmax(m, part[b]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 unsigned grid_x(int64_t len) {
@@ -556,13 +578,18 @@ hipError_t launch_outer_neg(hipStream_t st, int64_t n, int64_t k, const double* 
   return hipGetLastError();
 }
 hipError_t launch_row_abs_max(hipStream_t st, const void* A, msp_dtype t, int64_t rows, int64_t cols, int64_t lda,
-                              double* out) {
+                              double* part, int64_t part_doubles, double* out) {
+  int64_t nb = std::min<int64_t>(2048, (rows + NT / WAVE - 1) / (NT / WAVE));
+  nb = std::max<int64_t>(1, std::min(nb, part_doubles));
   if (t == MSP_F64)
-    hipLaunchKernelGGL(k_row_abs_max<double>, dim3(1), dim3(NT), 0, st, (const double*)A, rows, cols, lda, out);
+    hipLaunchKernelGGL(k_row_abs_max<double>, dim3((unsigned)nb), dim3(NT), 0, st, (const double*)A, rows, cols, lda,
+                       part);
   else if (t == MSP_F32)
-    hipLaunchKernelGGL(k_row_abs_max<float>, dim3(1), dim3(NT), 0, st, (const float*)A, rows, cols, lda, out);
+    hipLaunchKernelGGL(k_row_abs_max<float>, dim3((unsigned)nb), dim3(NT), 0, st, (const float*)A, rows, cols, lda,
+                       part);
   else
     return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_max_parts, dim3(1), dim3(NT), 0, st, part, (int)nb, out);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -52,6 +53,9 @@ namespace {
 size_t dsize(msp_dtype t) { return t == MSP_F64 ? 8 : (t == MSP_F32 ? 4 : 2); }
 bool valid_dtype(int t) { return t == MSP_F64 || t == MSP_F32 || t == MSP_BF16; }
 bool isfin(double v) { return std::isfinite(v); }
+double wall_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 constexpr int kMaxGammaDraw = 32;
 
@@ -1186,69 +1190,112 @@ msp_status rel_norms(SolveCtx& c, const double* v, int64_t len, std::vector<doub
   return MSP_OK;
 }
 
-// x += MSP_lo(b - A_hi x) until |b - A_hi x| <= tol |b|; Krylov refinement (PSD) or a
-// tighter inner tolerance (general) after two steps that fail to halve the residual
+// x += MSP_lo(b - A_hi x) until |b - A_hi x| <= tol |b|. A step "stalls" when it fails to
+// halve some unconverged column's residual. After two stalled steps: PSD switches to Krylov
+// refinement; general tightens the inner tolerance by 100x (not below kInnerFloor), and
+// gives up (MSP_ERR_NO_CONVERGENCE, best iterate) when the step after a tightening stalls
+// too, when the floor is reached, or at once for the one-level form, which has no inner
+// level a tighter tolerance could improve. The level-1 steps of all inner solves together
+// are capped by max_outer.
+constexpr double kInnerFloor = 1e-12;
+
 msp_status refine(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const double* B, int64_t ldb, double tol,
                   std::vector<double>& rel) {
   const int64_t n = c.n, k = c.k;
   const bool psd = c.P->structure == MSP_SYM_PSD;
   const int64_t blen = (!psd && !c.o->normal) ? c.m : n;
+  const int budget = c.o->max_outer;
+  const int used0 = c.acc.outer_iters;
+  auto left = [&]() { return budget - (c.acc.outer_iters - used0); };
   MSP_CHECK_HIP(launch_coldots(c.st, blen, k, B, ldb, B, ldb, c.bn));
   MSP_CHECK_HIP(launch_axpby(c.st, n, k, 0.0, c.xh, n, 0.0, nullptr, 0, c.xh, n, nullptr));
   MSP_CHECK_HIP(launch_copy_block(c.st, blen, k, B, ldb, c.rh, blen));
   double inner = c.o->refine_inner_tol;
-  std::vector<double> prev(k, 1.0);
+  std::vector<double> prev(k, 1.0), best_rel;
   std::vector<int> slow(k, 0);
-  bool krylov = false;
-  for (int step = 0; step < c.o->max_refine; ++step) {
-    TRY(core(c, c.rh, blen, inner, c.o->max_outer));
+  double best = INFINITY;
+  bool krylov = false, tightened = false, give_up = false;
+  for (int step = 0; step < c.o->max_refine && left() > 0; ++step) {
+    TRY(core(c, c.rh, blen, inner, left()));
     MSP_CHECK_HIP(launch_axpby(c.st, n, k, 1.0, c.xh, n, 1.0, c.L1.x, n, c.xh, n, nullptr));
     TRY(hi_residual(c, A_hi, hi_t, B, ldb, c.rh));
     TRY(rel_norms(c, c.rh, blen, rel));
     c.acc.refine_steps += 1;
-    if (log_on()) {
-      double wv = 0.0;
-      for (double v : rel) wv = std::max(wv, v);
-      fprintf(stderr, "[msp] refine step %d: max rel residual %.3e (inner tol %.1e)\n", step + 1, wv, inner);
+    double worst = 0.0;
+    for (double v : rel) worst = std::max(worst, v);
+    if (log_on())
+      fprintf(stderr, "[msp] refine step %d: max rel residual %.3e (inner tol %.1e, %d level-1 steps left)\n",
+              step + 1, worst, inner, left());
+    if (!psd && worst < best) {  // the general path keeps its best iterate for a give-up
+      best = worst;
+      best_rel = rel;
+      MSP_CHECK_HIP(launch_copy_block(c.st, n, k, c.xh, n, c.L0.x, n));
     }
-    bool all = true, stalled = false;
+    bool all = true, stalled = false, halved = true;
     for (int64_t j = 0; j < k; ++j) {
       if (rel[j] > tol) all = false;
-      slow[j] = (rel[j] > 0.5 * prev[j]) ? slow[j] + 1 : 0;
+      const bool slow_step = rel[j] > 0.5 * prev[j];
+      slow[j] = slow_step ? slow[j] + 1 : 0;
+      if (slow_step && rel[j] > tol) halved = false;
       if (slow[j] >= 2 && rel[j] > tol) stalled = true;
       prev[j] = rel[j];
     }
     if (all) return MSP_OK;
-    if (stalled) {
-      if (psd) {
+    if (psd) {
+      if (stalled) {
         krylov = true;
         break;
       }
-      inner *= 1e-2;  // general path: ask the inner solve for more accuracy
+      continue;
+    }
+    if (tightened) {
+      if (!halved) {  // the tighter inner solve did not help either
+        give_up = true;
+        break;
+      }
+      tightened = false;
+    }
+    if (stalled) {
+      if (c.form == 2 || inner <= kInnerFloor) {
+        give_up = true;
+        break;
+      }
+      inner = std::max(inner * 1e-2, kInnerFloor);  // ask the inner solve for more accuracy
+      tightened = true;
       std::fill(slow.begin(), slow.end(), 0);
     }
   }
-  if (!krylov) return MSP_OK;
+  if (!krylov) {
+    if (!psd && (give_up || left() <= 0) && best < INFINITY) {
+      double worst = 0.0;
+      for (double v : rel) worst = std::max(worst, v);
+      if (best < worst) {  // return the best iterate seen, with its residual
+        MSP_CHECK_HIP(launch_copy_block(c.st, n, k, c.L0.x, n, c.xh, n));
+        rel = best_rel;
+      }
+    }
+    if (give_up && log_on()) fprintf(stderr, "[msp] refinement stalled: giving up\n");
+    return MSP_OK;  // the caller reports MSP_ERR_NO_CONVERGENCE from the residuals
+  }
+  if (left() <= 0) return MSP_OK;
   // Krylov refinement: FCG in FP64 on (A_hi + lam I) e = rh, preconditioned by MSP_lo
   c.acc.krylov_refine = 1;
   Level& L = c.L0;
   MSP_CHECK_HIP(fcg_init(c.st, L.S, n, c.rh, n, L.r, L.x, nullptr, c.df + SLOT_L0));
-  TRY(core(c, L.r, n, inner, c.o->max_outer));
+  TRY(core(c, L.r, n, inner, left()));
   MSP_CHECK_HIP(launch_copy_block(c.st, n, k, c.L1.x, n, L.z, n));
   MSP_CHECK_HIP(fcg_first_dir(c.st, L.S, n, L.r, L.z, L.p));
   // target: |rh - A e| <= tol |B| / |rh| relative to the current residual
   double worst = 0.0;
   for (double v : rel) worst = std::max(worst, v);
   const double ktol = worst > 0 ? tol / worst : tol;
-  for (int it = 0; it < c.o->max_outer; ++it) {
+  for (int it = 0; it < c.o->max_outer && left() > 0; ++it) {
     TRY(sync(c));
     if (*slot(c, SLOT_L0) == 0) break;
-    const double lam = c.lam;
-    (void)lam;
     TRY(sweep(c, A_hi, hi_t, n, n, L.p, n, L.q, n, true, L.S.done, true, true, false));
     MSP_CHECK_HIP(fcg_update(c.st, L.S, n, L.x, L.r, L.ro, L.p, L.q, ktol, c.o->max_outer, c.df + SLOT_L0, c.gpart,
                              c.nb_last));
-    TRY(core(c, L.r, n, inner, c.o->max_outer));
+    TRY(core(c, L.r, n, inner, left()));
     MSP_CHECK_HIP(launch_copy_block(c.st, n, k, c.L1.x, n, L.z, n));
     MSP_CHECK_HIP(fcg_direction(c.st, L.S, n, L.r, L.ro, L.z, L.p));
   }
@@ -1259,7 +1306,7 @@ msp_status refine(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const double* B
 }
 
 msp_status validate_solve(const msp_precond* P, const void* A_hi, msp_dtype hi_t, const void* A_lo, msp_dtype lo_t,
-                          int64_t lda, const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx,
+                          int64_t lda, double lambda, const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx,
                           const msp_solve_opts* o) {
   REQUIRE(P, "P is null");
   REQUIRE(A_hi && A_lo && B && X && o, "null pointer argument");
@@ -1273,7 +1320,9 @@ msp_status validate_solve(const msp_precond* P, const void* A_hi, msp_dtype hi_t
     return msp_fail(MSP_ERR_NONFINITE, "non-finite tolerance");
   REQUIRE(o->tol > 0 && o->inner_tol > 0 && o->level3_tol > 0 && o->refine_inner_tol > 0, "tolerances must be > 0");
   REQUIRE(o->max_outer >= 1 && o->max_inner >= 1 && o->max_level3 >= 1 && o->max_refine >= 1, "caps must be >= 1");
-  REQUIRE(!(P->structure == MSP_GENERAL && !o->normal && P->lam != 0.0),
+  if (!isfin(lambda)) return msp_fail(MSP_ERR_NONFINITE, "lambda not finite");
+  REQUIRE(lambda >= 0.0, "need lambda >= 0");
+  REQUIRE(!(P->structure == MSP_GENERAL && !o->normal && lambda != 0.0),
           "A x = b needs lambda = 0 (use normal = 1 for (A^T A + lam I) x = c)");
   return MSP_OK;
 }
@@ -1318,7 +1367,7 @@ msp_status solve_into(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const doubl
       // inner operator A_lo + (lam + delta) I with delta = u_lo ||A_hi||_inf >= ||A_lo - A_hi||_2
       // (elementwise rounding of a symmetric matrix): it dominates A_hi + lam I, so the
       // low-precision MSP stays a positive definite preconditioner of the FP64 refinement
-      MSP_CHECK_HIP(launch_row_abs_max(c.st, A_hi, hi_t, c.n, c.n, c.lda, c.relres));
+      MSP_CHECK_HIP(launch_row_abs_max(c.st, A_hi, hi_t, c.n, c.n, c.lda, c.L0.q, c.n * c.k, c.relres));
       double ninf = 0.0;
       MSP_CHECK_HIP(hipMemcpyAsync(&ninf, c.relres, sizeof(double), hipMemcpyDeviceToHost, c.st));
       MSP_CHECK_HIP(hipStreamSynchronize(c.st));
@@ -1363,8 +1412,8 @@ msp_status solve_into(SolveCtx& c, const void* A_hi, msp_dtype hi_t, const doubl
 }
 
 msp_status make_ctx(SolveCtx& c, void* stream, const msp_precond* P, const void* A_hi, msp_dtype hi_t,
-                    const void* A_lo, msp_dtype lo_t, int64_t lda, int64_t k, const msp_solve_opts* o, void* ws,
-                    size_t ws_bytes) {
+                    const void* A_lo, msp_dtype lo_t, int64_t lda, double lambda, int64_t k, const msp_solve_opts* o,
+                    void* ws, size_t ws_bytes) {
   c.st = (hipStream_t)stream;
   c.P = P;
   c.o = o;
@@ -1378,8 +1427,8 @@ msp_status make_ctx(SolveCtx& c, void* stream, const msp_precond* P, const void*
   c.A_cf = A_hi;
   c.cf_t = hi_t;
   c.lda = lda;
-  c.lam = P->lam;
-  c.lam_sw = P->lam;
+  c.lam = lambda;  // the preconditioner keeps the handle's lam~ = lam_P + lam0
+  c.lam_sw = lambda;
   c.hf = P->host_flags;
   c.df = P->dev_view_flags;
   c.evpool = (std::vector<hipEvent_t>*)P->events;
@@ -1410,28 +1459,32 @@ extern "C" msp_status msp_solve_workspace(const msp_precond* P, int64_t k, const
 }
 
 extern "C" msp_status msp_solve(void* stream, const msp_precond* P, const void* A_hi, msp_dtype hi_t,
-                                const void* A_lo, msp_dtype lo_t, int64_t lda, const double* B, int64_t ldb,
-                                int64_t k, double* X, int64_t ldx, const msp_solve_opts* opts, void* ws,
+                                const void* A_lo, msp_dtype lo_t, int64_t lda, double lambda, const double* B,
+                                int64_t ldb, int64_t k, double* X, int64_t ldx, const msp_solve_opts* opts, void* ws,
                                 size_t ws_bytes, msp_solve_info* info) {
+  const double t0 = wall_seconds();
   msp_solve_opts dflt;
   msp_solve_opts_default(&dflt);
   const msp_solve_opts* o = opts ? opts : &dflt;
-  TRY(validate_solve(P, A_hi, hi_t, A_lo, lo_t, lda, B, ldb, k, X, ldx, o));
+  TRY(validate_solve(P, A_hi, hi_t, A_lo, lo_t, lda, lambda, B, ldb, k, X, ldx, o));
   REQUIRE(ws, "workspace is null");
   size_t need = 0;
   TRY(msp_solve_workspace(P, k, o, &need));
   if (ws_bytes < need || ((uintptr_t)ws & 255))
     return msp_fail(MSP_ERR_WORKSPACE, "solve workspace needs %zu bytes, 256-B aligned", need);
   SolveCtx c;
-  TRY(make_ctx(c, stream, P, A_hi, hi_t, A_lo, lo_t, lda, k, o, ws, ws_bytes));
-  return solve_into(c, A_hi, hi_t, B, ldb, X, ldx, info);
+  TRY(make_ctx(c, stream, P, A_hi, hi_t, A_lo, lo_t, lda, lambda, k, o, ws, ws_bytes));
+  const msp_status st = solve_into(c, A_hi, hi_t, B, ldb, X, ldx, info);
+  if (info) info->seconds = wall_seconds() - t0;
+  return st;
 }
 
 extern "C" msp_status msp_solve_backward(void* stream, const msp_precond* P, const void* A_hi, msp_dtype hi_t,
-                                         const void* A_lo, msp_dtype lo_t, int64_t lda, const double* X, int64_t ldx,
-                                         const double* G, int64_t ldg, int64_t k, double* dB, int64_t lddb,
-                                         double* dlambda, double* dA, int64_t ldda, const msp_solve_opts* opts,
-                                         void* ws, size_t ws_bytes, msp_solve_info* info) {
+                                         const void* A_lo, msp_dtype lo_t, int64_t lda, double lambda, const double* X,
+                                         int64_t ldx, const double* G, int64_t ldg, int64_t k, double* dB,
+                                         int64_t lddb, double* dlambda, double* dA, int64_t ldda,
+                                         const msp_solve_opts* opts, void* ws, size_t ws_bytes, msp_solve_info* info) {
+  const double t0 = wall_seconds();
   msp_solve_opts dflt;
   msp_solve_opts_default(&dflt);
   const msp_solve_opts* o = opts ? opts : &dflt;
@@ -1441,13 +1494,13 @@ extern "C" msp_status msp_solve_backward(void* stream, const msp_precond* P, con
   REQUIRE(X && G && dB, "null pointer argument");
   REQUIRE(ldx >= P->n && ldg >= P->n && lddb >= P->n, "leading dimension too small");
   REQUIRE(!dA || ldda >= P->n, "ldda < n");
-  TRY(validate_solve(P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, k, dB, lddb, o));
+  TRY(validate_solve(P, A_hi, hi_t, A_lo, lo_t, lda, lambda, G, ldg, k, dB, lddb, o));
   size_t need = 0;
   TRY(msp_solve_workspace(P, k, o, &need));
   if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
     return msp_fail(MSP_ERR_WORKSPACE, "solve workspace needs %zu bytes, 256-B aligned", need);
   SolveCtx c;
-  TRY(make_ctx(c, stream, P, A_hi, hi_t, A_lo, lo_t, lda, k, o, ws, ws_bytes));
+  TRY(make_ctx(c, stream, P, A_hi, hi_t, A_lo, lo_t, lda, lambda, k, o, ws, ws_bytes));
   // dB = (A + lam I)^{-T} G = (A + lam I)^{-1} G for symmetric A, same handle
   msp_status st = solve_into(c, A_hi, hi_t, G, ldg, dB, lddb, info);
   if (st != MSP_OK && st != MSP_ERR_NO_CONVERGENCE) return st;
@@ -1464,6 +1517,7 @@ extern "C" msp_status msp_solve_backward(void* stream, const msp_precond* P, con
     MSP_CHECK_HIP(launch_outer_neg(c.st, c.n, k, dB, lddb, X, ldx, dA, ldda));
     MSP_CHECK_HIP(hipStreamSynchronize(c.st));
   }
+  if (info) info->seconds = wall_seconds() - t0;
   return st;
 }
 
@@ -1491,6 +1545,7 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
                                    const double* G, int64_t ldg, int64_t N, double h, double u_lo, double u_hi,
                                    const msp_solve_opts* opts, void* ws, size_t ws_bytes, double* estimate,
                                    double* std_err, msp_solve_info* info) {
+  const double t0 = wall_seconds();
   msp_solve_opts dflt;
   msp_solve_opts_default(&dflt);
   msp_solve_opts o = opts ? *opts : dflt;
@@ -1531,7 +1586,7 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
     REQUIRE(p > 0.0, "lam > 0");
     if (P->lam != p) TRY(msp_precond_set_lambda(stream, P, p));
     msp_solve_info i{};
-    msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
+    msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, p, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
     if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) return s_;
     if (s_ != MSP_OK) unconverged = true;
     add_info(i);
@@ -1589,7 +1644,7 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
       const double w = h * std::sin(M_PI * p / 2.0) / M_PI * std::exp(0.5 * p * u);
       TRY(msp_precond_set_lambda(stream, P, t));
       msp_solve_info i{};
-      msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
+      msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, t, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
       if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) {
         (void)msp_precond_set_lambda(stream, P, lam_save);
         return s_;
@@ -1617,6 +1672,7 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
   *estimate = mean;
   if (std_err) *std_err = N > 1 ? std::sqrt(var / (double)(N - 1) / (double)N) : NAN;
   acc.status = unconverged ? MSP_ERR_NO_CONVERGENCE : MSP_OK;
+  acc.seconds = wall_seconds() - t0;
   if (info) *info = acc;
   if (unconverged) return msp_fail(MSP_ERR_NO_CONVERGENCE, "a ridge solve stopped at its iteration cap");
   return MSP_OK;

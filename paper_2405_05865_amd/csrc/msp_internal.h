@@ -243,9 +243,10 @@ hipError_t launch_coldots(hipStream_t st, int64_t len, int64_t k, const double* 
 // dA = -dB X^T (n x n dense, ld ldda)
 hipError_t launch_outer_neg(hipStream_t st, int64_t n, int64_t k, const double* dB, int64_t lddb, const double* X,
                             int64_t ldx, double* dA, int64_t ldda);
-// out[0] = max_i sum_j |A[i, j]| for an F64 or F32 matrix (one block; device scalar)
+// out[0] = max_i sum_j |A[i, j]| for an F64 or F32 matrix (device scalar): a grid of blocks
+// (at most part_doubles, each writing its maximum to part) and a one-block maximum
 hipError_t launch_row_abs_max(hipStream_t st, const void* A, msp_dtype t, int64_t rows, int64_t cols, int64_t lda,
-                              double* out);
+                              double* part, int64_t part_doubles, double* out);
 // out (cols x rows, FP64, ld ldo) = transpose of X (rows x cols, F64 or F32, ld ldx)
 hipError_t launch_transpose_f64(hipStream_t st, const void* X, msp_dtype x_t, int64_t rows, int64_t cols,
                                 int64_t ldx, double* out, int64_t ldo);

@@ -195,7 +195,7 @@ extern "C" msp_status msp_lstsq(void* stream, const msp_precond* P, const double
   // the preconditioner: z = (A~^T A~)^{-1} r by the three-level MSP on A~
   auto prec = [&](const double* r, double* z) -> msp_status {
     msp_solve_info ii{};
-    const msp_status s_ = msp_solve(stream, P, At, MSP_F64, At, MSP_F64, ldat, r, d, k, z, d, &io, w.inner, inner,
+    const msp_status s_ = msp_solve(stream, P, At, MSP_F64, At, MSP_F64, ldat, 0.0, r, d, k, z, d, &io, w.inner, inner,
                                     &ii);
     // an inner solve that stops early (cap or breakdown) still returns its iterate, which the
     // flexible outer iteration can use

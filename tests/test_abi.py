@@ -86,7 +86,7 @@ def test_nystrom_validation():
 def test_solve_rejects_null_handle():
     L = msp.library()
     info = B.SolveInfo()
-    assert L.msp_solve(None, None, None, 0, None, 0, 10, None, 10, 1, None, 10, None, None, 0,
+    assert L.msp_solve(None, None, None, 0, None, 0, 10, 0.0, None, 10, 1, None, 10, None, None, 0,
                        ctypes.byref(info)) == 1
 
 

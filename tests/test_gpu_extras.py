@@ -105,6 +105,46 @@ def test_autograd_function_and_finite_differences():
     assert lamt.grad.item() == pytest.approx((f(lam + h) - f(lam - h)) / (2 * h), rel=1e-6)
 
 
+def test_autograd_at_a_lambda_other_than_the_handles():
+    # the solve and its adjoint take lam from the autograd input; the handle (built for
+    # lam_P) is reused as the preconditioner
+    say("case autograd lam != handle lam n=256")
+    n, s, lam_p, lam = 256, 32, 0.1, 0.37
+    a, eigs, _, lam0, A, _, P = _psd(n=n, k=8, s=s, lam=lam_p, cid=303)
+    B = torch.from_numpy(W.gaussian(n, 303)).to(DEV).requires_grad_(True)
+    Ar = A.clone().requires_grad_(True)
+    lamt = torch.tensor(lam, dtype=torch.float64, device=DEV, requires_grad=True)
+    X = msp.MSPSolve.apply(Ar, B, lamt, P, {"tol": 1e-12, "inner_tol": 1e-13})
+    loss = (X * X).sum()
+    loss.backward()
+    b = B.detach().cpu().numpy()
+    x = np.linalg.solve(a + lam * np.eye(n), b)
+    assert np.linalg.norm(X.detach().cpu().numpy() - x) <= 1e-9 * np.linalg.norm(x)
+    db, da, dl = dense.gradients(a, lam, x, 2.0 * x)
+    assert np.linalg.norm(B.grad.cpu().numpy() - db) <= 1e-9 * np.linalg.norm(db)
+    assert np.linalg.norm(Ar.grad.cpu().numpy() - da) <= 1e-9 * np.linalg.norm(da)
+    assert lamt.grad.item() == pytest.approx(dl, rel=1e-9)
+    assert P.lam == lam_p
+
+
+def test_autograd_raises_when_the_solve_does_not_converge():
+    say("case autograd cap n=256")
+    n, s = 256, 32
+    a, eigs, _, lam0, A, _, P = _psd(n=n, k=8, s=s, lam=1e-3, cid=304)
+    B = torch.from_numpy(W.gaussian(n, 304)).to(DEV)
+    lamt = torch.tensor(1e-3, dtype=torch.float64, device=DEV)
+    with pytest.raises(msp.MspError) as e:
+        msp.MSPSolve.apply(A, B, lamt, P, {"tol": 1e-14, "max_outer": 1})
+    assert e.value.status == "MSP_ERR_NO_CONVERGENCE"
+
+
+def test_solve_reports_wall_seconds():
+    say("case solve seconds n=512")
+    a, eigs, _, lam0, A, _, P = _psd(n=512, k=16, s=32, lam=1e-2, cid=305)
+    X, info = msp.solve(P, A, torch.from_numpy(W.gaussian(512, 305)).to(DEV), tol=1e-10)
+    assert info["status"] == "MSP_OK" and 0.0 < info["seconds"] < 60.0
+
+
 def test_schatten1_matches_oracle_estimator(monkeypatch):
     say("case schatten-1 n=200 N=32")
     monkeypatch.setenv("MSP_LOG", "1")

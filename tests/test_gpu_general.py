@@ -183,3 +183,48 @@ def test_general_graph_replayed_level3_steps_match_eager():
     for x, info in out[1:]:
         assert np.array_equal(x, out[0][0])
         assert info["level3_iters"] == out[0][1]["level3_iters"]
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_refinement_stops_on_a_stall(form):
+    # kappa(A) ~ 1e6 (so kappa(A)^4 is far beyond FP64) with an FP32 copy inside MSP: the
+    # refinement either converges or stops with the best iterate within a few steps (a
+    # stall is two steps that fail to halve the residual; one tightening of the inner
+    # tolerance for the multi-level forms, none for the one-level form)
+    say(f"case general refinement stall n=512 level2_form={form}")
+    n, s = 512, 64
+    a, sv, _, _ = W.general_outlier(n, 16, config_id=108)
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    b = W.gaussian(n, 108)
+    A = torch.from_numpy(a).to(DEV)
+    A32 = A.float()
+    rows, signs, Y = msp.sketch(A32, s, 8, 41)
+    P = msp.Precond("general", rows, signs, Y, 0.0, lam0, 4 * s, 8, 43)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), A_lo=A32, refine=1, tol=1e-12, level2_form=form,
+                        max_outer=20000, max_refine=30)
+    say(info)
+    assert info["code"] in ("MSP_OK", "MSP_ERR_NO_CONVERGENCE"), info
+    assert info["refine_steps"] <= 12, info
+    x = X.cpu().numpy()
+    host = np.linalg.norm(b - a @ x) / np.linalg.norm(b)
+    assert np.isfinite(host) and host < 1.0
+    assert abs(info["rel_residual_max"] - host) <= 1e-8 * host + 1e-15
+    if info["code"] == "MSP_OK":
+        assert host <= 1e-12
+
+
+def test_refinement_level1_budget_across_steps():
+    # max_outer caps the level-1 steps of all inner solves of one refined solve together
+    say("case general refinement budget n=512")
+    n, s = 512, 64
+    a, sv, _, _ = W.general_outlier(n, 16, config_id=108)
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    b = W.gaussian(n, 108)
+    A = torch.from_numpy(a).to(DEV)
+    A32 = A.float()
+    rows, signs, Y = msp.sketch(A32, s, 8, 41)
+    P = msp.Precond("general", rows, signs, Y, 0.0, lam0, 4 * s, 8, 43)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), A_lo=A32, refine=1, tol=1e-14, max_outer=7)
+    say(info)
+    assert info["code"] == "MSP_ERR_NO_CONVERGENCE", info
+    assert info["outer_iters"] <= 7
