@@ -87,6 +87,74 @@ def cpu_baseline(a, b, w, lam0, gpu_outer_iters, budget_s):
     }
 
 
+def nystrom_min_eig(P, Y):
+    """The smallest nonzero eigenvalue of the Nystrom approximation C W^+ C^T (those of
+    W^{-1/2} C^T C W^{-1/2}), from the handle's W and the sketch C: the input of the lam0
+    ablation, computed once before timing (torch on the device)."""
+    import torch
+    W_, _, _ = P.factors()
+    s = W_.shape[0]
+    mu = 1e-12 * float(torch.trace(W_)) / s
+    L = torch.linalg.cholesky(W_ + mu * torch.eye(s, dtype=W_.dtype, device=W_.device))
+    CtC = Y.double().t() @ Y.double()
+    Z = torch.linalg.solve_triangular(L, CtC, upper=False)
+    K = torch.linalg.solve_triangular(L, Z.t().contiguous(), upper=False)
+    return float(torch.linalg.eigvalsh(0.5 * (K + K.t())).min())
+
+
+def bench_small(args):
+    """The plain MSP regularized solve at n = 1024 (A = Q diag(sigma) Q^T, 32 eigenvalues
+    10^U(2,4), the rest U(0.5,1); lam = 1e-3; s = 64, gamma = 8, phi = 256; FP64; stop at
+    1e-10). A is 8 MiB and stays in the caches, so the solve is bound by kernel latency,
+    not HBM: solves/s is reported without a roofline fraction."""
+    import numpy as np
+    import torch
+
+    import paper_2405_05865_amd as msp
+    import workloads as W
+
+    w = W.config("psd_outlier_n1024")
+    dev = torch.device("cuda:0")
+    msp.library()
+    a, eigs, _ = W.psd_outlier(w.n, w.extra["k"], config_id=w.config_id)
+    # the paper's lam0 = (2/l) sum_{i>l} lambda_i, l = s/2, from the spectrum the input was built with
+    l = w.s // 2
+    lam0 = 2.0 / l * float(np.sort(eigs)[::-1][l:].sum()) if args.lambda0 == "paper" else None
+    A = torch.from_numpy(a).to(dev)
+    bt = torch.from_numpy(W.gaussian(w.n, w.config_id)).to(dev)
+
+    def step():
+        rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
+        P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi, A=A)
+        X, info = msp.solve(P, A, bt, tol=w.tol, inner_tol=1e-12)
+        P.close()
+        return X, info
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(args.steps, 10)
+    for _ in range(reps):
+        X, info = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    x = X.cpu().numpy()
+    xs = np.linalg.solve(a + w.lam * np.eye(w.n), W.gaussian(w.n, w.config_id))
+    print(json.dumps({
+        "metric": "RHS-solves/sec at rel. residual 1e-10, n=1024 (plain MSP regularized solve)",
+        "value": round(reps / el, 3), "unit": "RHS-solves/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / reps, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "psd_outlier_n1024", "n": w.n, "s": w.s, "phi": w.phi, "lambda": w.lam,
+                   "lambda0": lam0, "lambda0_source": args.lambda0, "tol": w.tol},
+        "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters"],
+        "rel_residual": info["rel_residual_max"], "status": info["status"],
+        "x_rel_err_vs_dense": float(np.linalg.norm(x - xs) / np.linalg.norm(xs)),
+        "roofline": None,
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,16 +179,23 @@ def main():
                          "and keep the fastest (cached per shape; MSP_TUNE_CACHE names a file to keep it in)")
     ap.add_argument("--max-outer", type=int, default=None,
                     help="cap the level-1 iterations (counter runs over a few sweeps only)")
+    ap.add_argument("--level3-tol", type=float, default=1e-10,
+                    help="general workload: relative residual target of the level-3 solves")
+    ap.add_argument("--level3-kernels", type=int, default=2, choices=[0, 2],
+                    help="general: kernels per level-3 step (2: fused pair, 0: generic step)")
+    ap.add_argument("--refine-inner-tol", type=float, default=1e-4,
+                    help="general workload: accuracy of each inner MSP solve under FP64 refinement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 2 GiB elementwise copy (calibrates the HBM byte counters) and exit")
     ap.add_argument("--workload", default="rbf_gp_n32768",
                     choices=["rbf_gp_n32768", "batched_rbf_256", "general_outlier_n65536", "schatten1_n16384",
-                             "lstsq_tall"],
+                             "lstsq_tall", "psd_outlier_n1024"],
                     help="rbf_gp_n32768: the single n=32768 FP64 solve (default); batched_rbf_256: 256 uneven "
                          "F32 RBF systems x 16 right-hand sides in one batched launch; general_outlier_n65536: "
                          "the three-level solve of A x = b, n=65536, 8 right-hand sides; schatten1_n16384: the "
                          "Schatten-1 estimate of A = Q diag(1/i) Q^T, n=16384, 512 probes as one block; lstsq_tall: "
-                         "least squares with a tall A (n=262144 x d=2048, FP64, 64 large singular values), one RHS")
+                         "least squares with a tall A (n=262144 x d=2048, FP64, 64 large singular values), one RHS; "
+                         "psd_outlier_n1024: the plain MSP regularized solve, n=1024, 32 outliers, FP64, to 1e-10")
     ap.add_argument("--h", type=float, default=1.5, help="schatten: quadrature node spacing")
     ap.add_argument("--inner-rel", type=float, default=0.1,
                     help="lstsq_tall: relative accuracy of the inner MSP solves with A~ (a constant suffices)")
@@ -131,6 +206,13 @@ def main():
                     help="batched: skip the timed adjoint pass (forward plus adjoint under L = sum |X|^2)")
     ap.add_argument("--fp64-sample", type=int, default=4,
                     help="batched: systems timed with the plain FP64 single-RHS solve for comparison")
+    ap.add_argument("--lambda0", default="paper", choices=["paper", "estimate", "nystrom_min"],
+                    help="rbf and batched workloads: paper = (2/l) sum_{i>l} lambda_i from the spectrum (stored for "
+                         "the RBF matrix; eigvalsh per batched system); estimate = the library's trace-deficit "
+                         "estimator (msp_nystrom with lambda0 < 0); nystrom_min = the smallest eigenvalue of the "
+                         "Nystrom approximation C W^+ C^T (an ablation)")
+    ap.add_argument("--amortized", type=int, default=3,
+                    help="rbf: after the timed steps, time this many solves that reuse one preconditioner (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -165,11 +247,12 @@ def main():
     if args.workload == "lstsq_tall":
         bench_lstsq(args)
         return
+    if args.workload == "psd_outlier_n1024":
+        bench_small(args)
+        return
 
     name = "rbf_gp_n32768"
     w = W.config(name) if args.n is None else W.config(name, n=args.n, s=max(8, args.n // 64))
-    lam_path = os.path.join(ROOT, "tests", "golden", f"rbf_gp_n{w.n}_lambda0.json")
-    lam0 = json.load(open(lam_path))["lambda0"]
     dev = torch.device("cuda:0")
     msp.library()
 
@@ -182,14 +265,35 @@ def main():
     A = torch.from_numpy(a).to(dev)
     bt = torch.from_numpy(b).to(dev)
     torch.cuda.synchronize()
-    log(f"[bench] inputs resident in HBM ({time.time() - t:.1f} s); lam0={lam0:.6g}")
+    log(f"[bench] inputs resident in HBM ({time.time() - t:.1f} s)")
+    # lam0: the paper's value (stored, from the spectrum), the library's estimate (computed by
+    # msp_nystrom inside every timed step), or the smallest Nystrom eigenvalue (an ablation,
+    # found once here from the sketch's W and C)
+    lam0_arg = None
+    if args.lambda0 == "paper":
+        lam0_arg = json.load(open(os.path.join(ROOT, "tests", "golden", f"rbf_gp_n{w.n}_lambda0.json")))["lambda0"]
+    elif args.lambda0 == "nystrom_min":
+        rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
+        Pq = msp.Precond("psd", rows, signs, Y, w.lam, None, w.phi, w.phi_gamma, w.seed_phi, A=A)
+        lam0_arg = nystrom_min_eig(Pq, Y)
+        Pq.close()
+    log(f"[bench] lam0 ({args.lambda0}): {lam0_arg if lam0_arg is not None else 'estimated per step'}")
+    lam0_used = [lam0_arg]
+
+    def build():
+        rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
+        P = msp.Precond("psd", rows, signs, Y, w.lam, lam0_arg, w.phi, w.phi_gamma, w.seed_phi, A=A)
+        lam0_used[0] = P.lam0
+        return P
+
+    def solve(P, profile):
+        return msp.solve(P, A, bt, tol=w.tol, inner_tol=args.inner_tol, profile=profile,
+                         max_outer=args.max_outer, level2_form=args.level2_form, sym_sweep=args.sym_sweep,
+                         use_graph=args.use_graph, autotune=args.autotune)
 
     def step(profile):
-        rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
-        P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi)
-        X, info = msp.solve(P, A, bt, tol=w.tol, inner_tol=args.inner_tol, profile=profile,
-                            max_outer=args.max_outer, level2_form=args.level2_form, sym_sweep=args.sym_sweep,
-                            use_graph=args.use_graph, autotune=args.autotune)
+        P = build()
+        X, info = solve(P, profile)
         P.close()
         return X, info
 
@@ -209,6 +313,28 @@ def main():
     el = time.perf_counter() - t0
     ms_per_step = 1e3 * el / args.steps
     value = K * args.steps / el
+    lam0 = lam0_used[0]
+    # the error of the timed solution against the oracle's dense x* (stored for n = 32768;
+    # stated, not asserted: a residual of 1e-8 bounds it only by kappa(A + lam I) 1e-8)
+    x_err = None
+    xs_path = os.path.join(ROOT, "tests", "golden", f"rbf_gp_n{w.n}_xstar.npy")
+    if K == 1 and os.path.exists(xs_path):
+        xs = torch.from_numpy(np.load(xs_path)).to(dev)
+        x_err = float(torch.linalg.vector_norm(X - xs) / torch.linalg.vector_norm(xs))
+    amort = None
+    if args.amortized > 0:
+        # the preconditioner built once and reused: only the solves are timed
+        P = build()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.amortized):
+            _, ia = solve(P, 0)
+        torch.cuda.synchronize()
+        ea = time.perf_counter() - ta
+        P.close()
+        amort = {"value": round(K * args.amortized / ea, 4), "unit": "RHS-solves/s", "solves": args.amortized,
+                 "ms_per_solve": round(1e3 * ea / args.amortized, 3), "status": ia["status"]}
+        log(f"[bench] amortized: {amort}")
     sweep_ms = sum(i["sweep_ms"] for i in infos) / max(1, sum(i["timed_sweeps"] for i in infos))
     sym = args.sym_sweep == 1 and K == 1
     bytes_per_sweep = (0.5 * w.n * (w.n + 1) if sym else float(w.n) * w.n) * 8
@@ -230,14 +356,17 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"rbf_gp_n{w.n}_fp64_{K}rhs", "n": w.n, "s": w.s, "gamma": w.gamma, "phi": w.phi,
-                   "lambda": w.lam, "lambda0": lam0, "tol": w.tol, "inner_tol": args.inner_tol, "nrhs": K,
+                   "lambda": w.lam, "lambda0": lam0, "lambda0_source": args.lambda0, "tol": w.tol,
+                   "inner_tol": args.inner_tol, "nrhs": K,
                    "levels": 2, "level2_form": args.level2_form, "sym_sweep": args.sym_sweep,
                    "use_graph": args.use_graph, "autotune": args.autotune},
         "hbm_gbs_per_sweep": round(achieved, 1),
         "outer_iters": infos[-1]["outer_iters"],
         "inner_iters": infos[-1]["inner_iters"],
         "rel_residual": infos[-1]["rel_residual_max"],
+        "x_rel_err_vs_oracle": x_err,
         "converged": ok,
+        "amortized": amort,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": ("k_symv_tiles + k_symv_reduce (lower-triangle A-sweep, FP64, 1 RHS)" if sym
@@ -366,7 +495,10 @@ def bench_schatten(args):
     def step():
         rows, signs, Y = msp.sketch(A32, s, w.gamma, w.seed_s)
         P = msp.Precond("general", rows, signs, Y, 1.0, lam0, w.phi, w.phi_gamma, w.seed_phi)
-        est, se, info = msp.schatten(P, A, G, p=1.0, A_lo=A32, h=args.h, refine=1, tol=w.tol)
+        est, se, info = msp.schatten(P, A, G, p=1.0, A_lo=A32, h=args.h, refine=1, tol=w.tol,
+                                     inner_tol=args.inner_tol, level3_tol=args.level3_tol,
+                                     refine_inner_tol=args.refine_inner_tol, level3_kernels=args.level3_kernels,
+                                     max_outer=args.max_outer)
         P.close()
         return est, se, info
 
@@ -378,9 +510,12 @@ def bench_schatten(args):
     for i in range(args.steps):
         est, se, info = step()
         log(f"[bench] step {i}: estimate {est:.6f} +- {se:.2e} (exact {exact:.6f}), outer={info['outer_iters']} "
-            f"inner={info['inner_iters']} level3={info['level3_iters']} sweeps={info['sweeps']}")
+            f"inner={info['inner_iters']} level3={info['level3_iters']} sweeps={info['sweeps']} "
+            f"nodes={info['trace_nodes']}")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # Hutchinson's standard deviation for PSD A: sqrt(2 |A|_F^2 / N)
+    sd = float(np.sqrt(2.0 * np.sum(sig ** 2) / N))
     line = {
         "metric": "Schatten-1 estimates/sec (512 probes, n=16384)",
         "value": round(args.steps / el, 5),
@@ -396,11 +531,16 @@ def bench_schatten(args):
         "data": "synthetic",
         "config": {"workload": f"schatten1_n{n}", "n": n, "s": s, "phi": w.phi, "gamma": w.gamma, "probes": N,
                    "p": 1.0, "h": args.h, "lambda0": lam0, "tol": w.tol, "matrix": "f64", "matrix_in_msp": "f32",
-                   "sweep_arithmetic": "f64", "refinement": "fp64"},
+                   "sweep_arithmetic": "f64", "refinement": "fp64", "nodes": "descending from |A|",
+                   "inner_tol": args.inner_tol, "level3_tol": args.level3_tol,
+                   "refine_inner_tol": args.refine_inner_tol, "level3_kernels": args.level3_kernels},
         "estimate": est,
         "std_err": se,
         "exact": exact,
         "rel_error": abs(est - exact) / exact,
+        "hutchinson_sd": sd,
+        "within_3sd": abs(est - exact) <= 3.0 * sd,
+        "trace_nodes": info["trace_nodes"],
         "outer_iters": info["outer_iters"],
         "inner_iters": info["inner_iters"],
         "level3_iters": info["level3_iters"],
@@ -441,7 +581,10 @@ def bench_general(args):
     def step():
         rows, signs, Y = msp.sketch(A32, s, w.gamma, w.seed_s)
         P = msp.Precond("general", rows, signs, Y, 0.0, lam0, phi, w.phi_gamma, w.seed_phi)
-        X, info = msp.solve(P, A, B, A_lo=A32, refine=1, tol=w.tol, level2_form=args.level2_form)
+        X, info = msp.solve(P, A, B, A_lo=A32, refine=1, tol=w.tol, level2_form=args.level2_form,
+                            inner_tol=args.inner_tol, level3_tol=args.level3_tol, max_outer=args.max_outer,
+                            refine_inner_tol=args.refine_inner_tol, use_graph=args.use_graph,
+                            level3_kernels=args.level3_kernels)
         P.close()
         return X, info
 
@@ -457,6 +600,11 @@ def bench_general(args):
             f"{info['status']}")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # the error against x* = V diag(1/sv) U^T b from the known factors (host, O(n) per reflection)
+    Bh = W.gaussian((w.nrhs, n), w.config_id)
+    xs = W.outer_product_apply(v_vs, 1.0 / sv, u_vs, Bh.T).T
+    Xh = X.cpu().numpy()
+    x_err = float(max(np.linalg.norm(Xh[j] - xs[j]) / np.linalg.norm(xs[j]) for j in range(w.nrhs)))
     line = {
         "metric": "RHS-solves/sec at rel. residual 1e-8, three-level general solve (n=65536, 8 RHS)",
         "value": round(w.nrhs * args.steps / el, 4),
@@ -474,12 +622,15 @@ def bench_general(args):
                    "nrhs": w.nrhs, "lambda": 0.0, "lambda0": lam0, "tol": w.tol, "matrix": "f64",
                    "matrix_in_msp": args.lo, "sweep_arithmetic": "f64",
                    "refinement": "fp64" if args.lo == "f32" else "none",
-                   "level2_form": args.level2_form, "levels": 3},
+                   "level2_form": args.level2_form, "levels": 3, "inner_tol": args.inner_tol,
+                   "level3_tol": args.level3_tol, "refine_inner_tol": args.refine_inner_tol,
+                   "level3_kernels": args.level3_kernels, "use_graph": args.use_graph},
         "outer_iters": info["outer_iters"],
         "inner_iters": info["inner_iters"],
         "level3_iters": info["level3_iters"],
         "refine_steps": info["refine_steps"],
         "rel_residual": info["rel_residual_max"],
+        "x_rel_err_vs_exact": x_err,
         "converged": info["status"] == "MSP_OK" and info["rel_residual_max"] <= w.tol,
     }
     print(json.dumps(line), flush=True)
@@ -521,8 +672,11 @@ def bench_batched(args):
         s = min(w.s, n // 2)
         phi = min(4 * s, n)
         # the paper's lam0 = (2/l) sum_{i>l} lambda_i, l = s/2, from the spectrum of the F32 matrix
-        ev = torch.linalg.eigvalsh(A.double()).flip(0)
-        lam0 = float(2.0 / (s // 2) * ev[s // 2:].clamp_min(0).sum())
+        # (input preparation), or None: the library's estimate inside every timed step
+        lam0 = None
+        if args.lambda0 == "paper":
+            ev = torch.linalg.eigvalsh(A.double()).flip(0)
+            lam0 = float(2.0 / (s // 2) * ev[s // 2:].clamp_min(0).sum())
         systems.append(dict(n=n, A=A, A_lo=A_lo, B=torch.from_numpy(b).to(dev), s=s, phi=phi, lam0=lam0,
                             seed=w.seed_s + 97 * j, seed_phi=w.seed_s + 97 * j + 8))
         if j % 32 == 31:
@@ -535,7 +689,8 @@ def bench_batched(args):
         Ps = []
         for q in systems:
             rows, signs, Y = msp.sketch(q["A"], q["s"], w.gamma, q["seed"])
-            Ps.append(msp.Precond("psd", rows, signs, Y, w.lam, q["lam0"], q["phi"], w.phi_gamma, q["seed_phi"]))
+            Ps.append(msp.Precond("psd", rows, signs, Y, w.lam, q["lam0"], q["phi"], w.phi_gamma, q["seed_phi"],
+                                  A=q["A"]))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         Xs, infos = msp.solve_batched([(P, q["A"], q["A_lo"], q["B"]) for P, q in zip(Ps, systems)], tol=w.tol,
@@ -577,7 +732,8 @@ def bench_batched(args):
         Ps = []
         for q in systems:
             rows, signs, Y = msp.sketch(q["A"], q["s"], w.gamma, q["seed"])
-            Ps.append(msp.Precond("psd", rows, signs, Y, w.lam, q["lam0"], q["phi"], w.phi_gamma, q["seed_phi"]))
+            Ps.append(msp.Precond("psd", rows, signs, Y, w.lam, q["lam0"], q["phi"], w.phi_gamma, q["seed_phi"],
+                                  A=q["A"]))
         sys_args = [(P, q["A"], q["A_lo"], q["B"]) for P, q in zip(Ps, systems)]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -635,8 +791,8 @@ def bench_batched(args):
         "data": "synthetic",
         "config": {"workload": f"batched_rbf_{count}", "count": count, "nrhs": nrhs, "n_range": [512, 8192],
                    "sum_n2": float(np.sum(sizes.astype(np.float64) ** 2)), "s": "min(256, n/2)", "gamma": w.gamma,
-                   "phi": "min(4s, n)", "lambda": w.lam, "tol": w.tol, "matrix": "f32", "sweeps": args.lo,
-                   "refinement": "fp64 krylov"},
+                   "phi": "min(4s, n)", "lambda": w.lam, "lambda0_source": args.lambda0, "tol": w.tol,
+                   "matrix": "f32", "sweeps": args.lo, "refinement": "fp64 krylov"},
         "setup_ms_per_step": round(1e3 * setup_t / args.steps, 2),
         "solve_ms_per_step": round(1e3 * solve_t / args.steps, 2),
         "a_sweep_bytes_per_step": a_bytes,

@@ -14,9 +14,9 @@
  *     *_workspace queries return; the library never allocates device memory. On the
  *     host, msp_nystrom allocates one 4 KiB page of pinned, device-mapped memory per
  *     handle (the mirror through which solves read convergence flags), solves with
- *     profile != 0 create HIP events (kept in the handle), and solves with use_graph
- *     != 0 create a capture stream and graphs (freed at return); msp_precond_destroy
- *     frees the rest.
+ *     profile != 0 create HIP events (kept in the handle), and solves with use_graph != 0
+ *     create a capture stream and graphs (freed at return); msp_precond_destroy frees
+ *     the rest.
  *   - Errors: every call returns an msp_status; no call throws or aborts.
  *     Arguments are validated before any device work is enqueued. msp_last_error()
  *     returns a thread-local message describing the last failure.
@@ -83,6 +83,18 @@ msp_status msp_sketch(void* stream, const void* A, msp_dtype a_t, int64_t m, int
                       int32_t* S_rows, int8_t* S_signs, void* Y, msp_dtype y_t, int64_t ldy,
                       void* ws, size_t ws_bytes);
 
+/* msp_sketch_autotune -- msp_sketch that first times every admissible number of rows of A
+ * per block of the sketch kernel (the shape of its register tile) on this matrix, keeps the
+ * fastest for this (A dtype, Y dtype, m, n, lda, s, gamma) for the process (and in the file
+ * named by MSP_TUNE_CACHE, one JSON object per line), and writes S and Y with it; later
+ * msp_sketch calls with that shape use it. Same arguments and outputs as msp_sketch, plus
+ *   rows_per_block [host] out (may be NULL): the chosen value.
+ * Synchronises the stream. */
+msp_status msp_sketch_autotune(void* stream, const void* A, msp_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                               int64_t s, int32_t gamma, uint64_t seed, int32_t* S_rows, int8_t* S_signs,
+                               void* Y, msp_dtype y_t, int64_t ldy, void* ws, size_t ws_bytes,
+                               int32_t* rows_per_block /*host*/);
+
 /* ---------------------------------------------------------------------------------
  * msp_nystrom -- the Nystrom factor and the inner-level preconditioners.
  *
@@ -98,22 +110,34 @@ msp_status msp_sketch(void* stream, const void* A, msp_dtype a_t, int64_t m, int
  *
  *   m, n, s, gamma, S_rows, S_signs, Y, y_t, ldy   as produced by msp_sketch
  *            (MSP_SYM_PSD needs m == n)
+ *   A, a_t, lda  the matrix Y was sketched from; read only when lambda0 < 0 (its diagonal),
+ *            may be NULL otherwise
  *   lambda   regulariser lam >= 0 of the user's system
- *   lambda0  lam0 >= 0 of Theorems 3.1/4.1 (the paper's value is (2/l) sum_{i>l} lambda_i;
- *            it is an explicit input, as in the algorithms' input lists); lam + lam0 > 0
+ *   lambda0  lam0 of Theorems 3.1/4.1 (the paper's value is (2/l) sum_{i>l} lambda_i, an
+ *            explicit input as in the algorithms' input lists), lam + lam0 > 0; or, for
+ *            MSP_SYM_PSD, any value < 0 to estimate it on the GPU when the tail spectrum is
+ *            unknown: lam0 = (2/l) max(tr A - tr(W^+ C^T C), 0) with l = s/2, the trace
+ *            deficit of the Nystrom approximation C W^+ C^T (at least sum_{i>s} lambda_i,
+ *            0 when rank(A) <= s; W^+ taken as (W + mu I)^{-1}, mu = 1e-9 tr(W)/s; a deficit
+ *            below 1e-6 tr A counts as the rounding of an exact recovery, 0). The value used is returned
+ *            by msp_precond_params. An estimate of 0 with lam = 0 returns
+ *            MSP_ERR_INVALID_ARG; MSP_GENERAL with lambda0 < 0 returns MSP_ERR_UNSUPPORTED.
  *   phi, phi_gamma, phi_seed   the level-2/3 embedding, 1 <= phi_gamma <= phi
  *   ws       device workspace of msp_nystrom_workspace(...) bytes; it holds the factors
  *            and must outlive the handle
  *   P        [host] out: the handle; free with msp_precond_destroy
- * Synchronises once (to report MSP_ERR_NOT_POSDEF).
+ * Synchronises once (to report MSP_ERR_NOT_POSDEF), twice when estimating lam0.
  * ------------------------------------------------------------------------------ */
 msp_status msp_nystrom_workspace(msp_structure structure, int64_t m, int64_t n, int64_t s, int64_t phi,
                                  int32_t phi_gamma, size_t* bytes /*host*/);
 msp_status msp_nystrom(void* stream, msp_structure structure, int64_t m, int64_t n, int64_t s, int32_t gamma,
                        const int32_t* S_rows, const int8_t* S_signs, const void* Y, msp_dtype y_t, int64_t ldy,
+                       const void* A, msp_dtype a_t, int64_t lda,
                        double lambda, double lambda0, int64_t phi, int32_t phi_gamma, uint64_t phi_seed,
                        void* ws, size_t ws_bytes, msp_precond** P /*host out*/);
 msp_status msp_precond_destroy(msp_precond* P);
+/* The handle's lam and lam0 (the estimate when msp_nystrom was given lambda0 < 0). Host only. */
+msp_status msp_precond_params(const msp_precond* P, double* lambda /*host*/, double* lambda0 /*host*/);
 /* Copy the handle's s x s factors into caller buffers (device, s*s doubles each, any may
  * be NULL): W = S C (PSD) and M2^{-1} (PSD) or M3a^{-1} (general), and M3b^{-1}
  * (general). For inspection and tests; asynchronous. */
@@ -207,6 +231,13 @@ typedef struct {
                               while timing; results differ from the built-in choice only by
                               summation order. Default 0 (built-in rule: about 2048
                               wavefronts). */
+  int32_t level3_kernels;  /* general, level2_form 1, k <= 16: kernels per level-3 step. 2 (default):
+                              the step as two kernels (decision, direction and operator product;
+                              step length, residual, preconditioner product and dots), every
+                              product a direct FP64 row dot over the formed s x s matrices;
+                              0: the generic inner step (an operator product, a residual update,
+                              a preconditioner product and a direction kernel). The same
+                              iteration; results differ only in summation order. */
 } msp_solve_opts;
 
 typedef struct {
@@ -226,6 +257,7 @@ typedef struct {
                                autotune, else the built-in rule); 0 for the other sweeps */
   double seconds;           /* host wall-clock time of the call, entry to return (the call
                                synchronises before returning, so this includes the device work) */
+  int32_t trace_nodes;      /* msp_schatten / msp_orlicz: ridge-solve nodes taken (0 otherwise) */
 } msp_solve_info;
 
 void msp_solve_opts_default(msp_solve_opts* o /*host*/);
@@ -337,12 +369,20 @@ msp_status msp_solve_backward(void* stream, const msp_precond* P,
  *
  * MSP_TRACE_SCHATTEN_P: ||A||_p^p = tr((A^T A)^{p/2}), 0 < p < 2, from
  *   (sin(pi p/2)/pi) int_0^inf t^{p/2-1} tr(A^T A (A^T A + t I)^{-1}) dt with t = e^u,
- *   trapezoid nodes u_j = u_lo + j h <= u_hi, and Hutchinson's estimator over the probe
- *   block G: per probe and node <A g, A x>, x = (A^T A + t_j I)^{-1} g solved by the
- *   three-level MSP of P (an MSP_GENERAL handle; lam~ = t_j + lam0 per node).
+ *   the trapezoid rule with step h, and Hutchinson's estimator over the probe block G:
+ *   per probe and node <A g, A x>, x = (A^T A + t_j I)^{-1} g solved by the three-level
+ *   MSP of P (an MSP_GENERAL handle; lam~ = t_j + lam0 per node).
+ *   Nodes: u_lo finite: u_j = u_lo + j h <= u_hi. u_lo NaN: u_j = u_hi - j h going down,
+ *   the nodes below the last one taken at their t -> 0 value |g|^2 (a geometric series);
+ *   since t <g, x> is nondecreasing in t, after node j that replacement is off by at most
+ *   t_j <g, x_j> times the remaining weight per probe, and the descent stops when the mean
+ *   of that bound is at most 1e-4 of the estimate (at most 400 nodes). u_hi NaN: from a
+ *   30-step power iteration on A^T A, u_hi = 2 ln(1.01 |A|) + (2/(2-p)) ln 1e4.
  * MSP_TRACE_EFFDIM: d_lam = tr(A (A + lam I)^{-1}) = mean_k (g^T g - lam g^T x),
  *   x = (A + lam I)^{-1} g by the two-level MSP of P (an MSP_SYM_PSD handle); `p` is lam.
- *   G        N probes of length n, ld ldg, FP64
+ *   G        N probes of length n, ld ldg, FP64; or NULL: the N probes msp_gaussian_probes
+ *            draws from probe_seed (generated into the workspace; probe_seed ignored
+ *            otherwise)
  *   estimate, std_err  [host] out (std_err: standard error over probes)
  * Returns MSP_ERR_NO_CONVERGENCE, with the estimate and info still written, when some
  * ridge solve stopped at its iteration cap; other failures return before any output.
@@ -353,10 +393,44 @@ msp_status msp_schatten_workspace(const msp_precond* P, int64_t nprobes, const m
                                   size_t* bytes /*host*/);
 msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precond* P,
                         const void* A_hi, msp_dtype hi_t, const void* A_lo, msp_dtype lo_t, int64_t lda,
-                        double p, const double* G, int64_t ldg, int64_t nprobes,
+                        double p, const double* G, int64_t ldg, int64_t nprobes, uint64_t probe_seed,
                         double h, double u_lo, double u_hi, const msp_solve_opts* opts,
                         void* ws, size_t ws_bytes, double* estimate /*host*/, double* std_err /*host*/,
                         msp_solve_info* info /*host*/);
+
+/* ---------------------------------------------------------------------------------
+ * msp_orlicz -- the Orlicz norm |A|_g = inf { r > 0 : sum_i g(sigma_i(A) / r) <= 1 } for
+ * g(s) = sum_q c_q s^{p_q}, c_q > 0, 0 < p_q < 2 (a norm when every p_q >= 1), through the
+ * spectral sums of Section 3.2: sum_i g(sigma_i / r) = sum_q c_q r^{-p_q} ||A||_{p_q}^{p_q},
+ * every Schatten sum from the same ridge solves (the quadrature nodes do not depend on p,
+ * only the weights do), nodes going down from u_hi as in msp_schatten with u_lo NaN (the
+ * descent stops when every sum's tail bound is at most eps_q of that sum; eps_q NaN: 1e-4;
+ * u_hi NaN: from |A| for the largest p_q). The root r is found by bisection on ln r.
+ *   coefs, powers  [host] nterms (1..16) values each
+ *   G, ldg, nprobes, probe_seed   the probe block, as for msp_schatten
+ *   estimate   [host] out: r;  std_err [host] out: the delta-method standard error of r
+ *   sums       [host] out, may be NULL: the nterms Schatten sum estimates
+ * Workspace: msp_schatten_workspace. Returns MSP_ERR_NO_CONVERGENCE, with every output
+ * written, when some ridge solve stopped at its iteration cap. Synchronises the stream.
+ * ------------------------------------------------------------------------------ */
+msp_status msp_orlicz(void* stream, msp_precond* P, const void* A_hi, msp_dtype hi_t, const void* A_lo,
+                      msp_dtype lo_t, int64_t lda, const double* coefs /*host*/, const double* powers /*host*/,
+                      int64_t nterms, const double* G, int64_t ldg, int64_t nprobes, uint64_t probe_seed,
+                      double h, double u_hi, double eps_q, const msp_solve_opts* opts, void* ws,
+                      size_t ws_bytes, double* estimate /*host*/, double* std_err /*host*/,
+                      double* sums /*host*/, msp_solve_info* info /*host*/);
+
+/* ---------------------------------------------------------------------------------
+ * msp_gaussian_probes -- the Gaussian probe vectors of Hutchinson's estimator (Section
+ * 3.2 draws them; the paper fixes no generator): Box-Muller (1958) over the counter-based
+ * SplitMix64 stream of msp_sketch. Probe j has key k_j = fmix((seed ^ 0xD1B54A32D192ED03)
+ * + (j+1)G); element i takes outputs u1, u2 number 2i+1 and 2i+2 of the stream started
+ * at k_j, U1 = (hi53(u1) + 1) 2^-53 in (0, 1], U2 = hi53(u2) 2^-53 in [0, 1), and
+ * g = sqrt(-2 ln U1) cos(2 pi U2) in FP64.
+ *   G        out, N probes of length n, probe j at G + j * ldg (ldg >= n)
+ * Asynchronous.
+ * ------------------------------------------------------------------------------ */
+msp_status msp_gaussian_probes(void* stream, int64_t n, int64_t N, uint64_t seed, double* G, int64_t ldg);
 
 /* ---------------------------------------------------------------------------------
  * Least squares min |A x - b| for a tall A (n x d, n >= d): sketch-and-precondition with

@@ -12,9 +12,10 @@ import scipy.linalg as sla
 
 
 def solve_psd(a, b, lam):
-    """(A + lam I)^{-1} b by dense Cholesky."""
-    n = a.shape[0]
-    f = sla.cho_factor(a + lam * np.eye(n), lower=True)
+    """(A + lam I)^{-1} b by dense Cholesky (one copy of A, shifted on its diagonal)."""
+    m = np.array(a, dtype=np.float64, copy=True)
+    m[np.diag_indices_from(m)] += lam
+    f = sla.cho_factor(m, lower=True, overwrite_a=True)
     return sla.cho_solve(f, b)
 
 

@@ -58,6 +58,25 @@ def paper_lambda0_from_top(trace: float, top_l: np.ndarray, l: int) -> float:
     return float(2.0 / l * (trace - top.sum()))
 
 
+def lambda0_estimate(a: np.ndarray, c: np.ndarray, w: np.ndarray, l: int) -> float:
+    """lam0 when the tail spectrum is unknown (reading of Theorem 4.1's lam0, which needs
+    sum_{i>l} lambda_i): (2/l) max(tr(A) - tr(A_nys), 0), where A_nys = C W^+ C^T is the
+    Nystrom approximation that Algorithm 1 builds from C = A S^T and W = S C, so
+    tr(A_nys) = tr(W^+ C^T C). A - A_nys is PSD and A_nys has rank <= s, hence (Weyl) the
+    deficit is at least sum_{i>s} lambda_i, and it is 0 when rank(A) <= s.
+
+    W^+ is taken as (W + mu I)^{-1} with mu = 1e-9 tr(W) / s: C (W + mu I)^{-1} C^T is still
+    below A and of rank <= s (so the bound holds), and mu keeps the directions in which a
+    rank-deficient W is zero up to rounding from being amplified. A deficit below 1e-6 tr(A)
+    is taken as the rounding of an exact recovery and counts as 0."""
+    winv = spd_inverse(0.5 * (w + w.T), 1e-9)
+    tr_a = float(np.trace(a))
+    deficit = tr_a - float(np.sum(winv * (c.T @ c)))
+    if deficit <= 1e-6 * tr_a:
+        return 0.0
+    return float(2.0 / l * deficit)
+
+
 def spd_inverse(m: np.ndarray, shift_rel: float) -> np.ndarray:
     """(M + mu I)^{-1} from a Cholesky factor, mu = shift_rel * tr(M) / dim."""
     d = m.shape[0]

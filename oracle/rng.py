@@ -113,3 +113,32 @@ def sketch_indices_loop(seed: int, n: int, s: int, gamma: int):
         rows[i] = [g[0] for g in got]
         signs[i] = [g[1] for g in got]
     return rows, signs
+
+
+# -- Gaussian probes (Hutchinson's estimator of Section 3.2 draws them; the paper fixes
+# no generator). Box and Muller (1958) over the same counter-based stream:
+#   probe key        k_j = output number (j+1) of the stream started at seed ^ PROBE_DOMAIN;
+#   element i        u1 = output (2i+1), u2 = output (2i+2) of the stream started at k_j;
+#                    U1 = (hi53(u1) + 1) 2^-53 in (0, 1],  U2 = hi53(u2) 2^-53 in [0, 1);
+#                    g = sqrt(-2 ln U1) cos(2 pi U2).
+# The domain constant keeps a probe block and a sketch drawn from the same seed apart.
+PROBE_DOMAIN = 0xD1B54A32D192ED03
+
+
+def probe_uniforms(seed: int, n: int, N: int):
+    """(U1, U2), each (N, n) float64, of the probe generator."""
+    with np.errstate(over="ignore"):
+        j = np.arange(N, dtype=np.uint64)[:, None]
+        i = np.arange(n, dtype=np.uint64)[None, :]
+        keys = _fmix_np(np.uint64((seed ^ PROBE_DOMAIN) & MASK64) + (j + np.uint64(1)) * _G)
+        u1 = _fmix_np(keys + (np.uint64(2) * i + np.uint64(1)) * _G)
+        u2 = _fmix_np(keys + (np.uint64(2) * i + np.uint64(2)) * _G)
+    U1 = ((u1 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    U2 = (u2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return U1, U2
+
+
+def gaussian_probes(seed: int, n: int, N: int) -> np.ndarray:
+    """N probes of length n, (N, n) float64, by Box-Muller on probe_uniforms."""
+    U1, U2 = probe_uniforms(seed, n, N)
+    return np.sqrt(-2.0 * np.log(U1)) * np.cos(2.0 * np.pi * U2)

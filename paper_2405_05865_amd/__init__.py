@@ -12,13 +12,14 @@ from __future__ import annotations
 import ctypes
 import math
 from dataclasses import dataclass
+from types import SimpleNamespace
 
 import torch
 
 from . import _binding as B
 from ._binding import MspError, SolveInfo, SolveOpts  # noqa: F401
 
-__all__ = ["sketch", "Precond", "nystrom", "solve", "solve_batched", "solve_batched_backward", "solve_backward", "schatten", "effective_dimension",
+__all__ = ["sketch", "Precond", "nystrom", "solve", "solve_batched", "solve_batched_backward", "solve_backward", "schatten", "effective_dimension", "gaussian_probes",
            "MSPSolve", "msp_solve", "library", "MspError", "SolveOpts"]
 
 _DT = {torch.float64: B.MSP_F64, torch.float32: B.MSP_F32, torch.bfloat16: B.MSP_BF16}
@@ -144,8 +145,11 @@ def sketch(A: torch.Tensor, s: int, gamma: int, seed: int, y_dtype: torch.dtype 
 class Precond:
     """Handle of the Nystrom preconditioner and its inner levels (msp_nystrom)."""
 
-    def __init__(self, structure: str, S_rows, S_signs, Y, lam: float, lam0: float, phi: int, phi_gamma: int,
-                 phi_seed: int):
+    def __init__(self, structure: str, S_rows, S_signs, Y, lam: float, lam0: float | None, phi: int,
+                 phi_gamma: int, phi_seed: int, A: torch.Tensor | None = None):
+        """lam0 None (or < 0): estimated on the GPU from the sketch and A's diagonal
+        (needs A, the matrix Y was sketched from; PSD handles only); self.lam0 holds the
+        value used."""
         L = library()
         self.structure = structure
         code = B.MSP_SYM_PSD if structure == "psd" else B.MSP_GENERAL
@@ -154,7 +158,13 @@ class Precond:
         n, gamma = S_rows.shape
         self.m, self.n, self.s, self.gamma = m, n, s, gamma
         self.phi, self.phi_gamma = phi, phi_gamma
-        self.lam, self.lam0 = float(lam), float(lam0)
+        lam0 = -1.0 if lam0 is None else float(lam0)
+        if lam0 < 0:
+            if A is None:
+                raise ValueError("estimating lam0 needs A")
+            _check_layout(SimpleNamespace(structure="psd", m=n, n=n), A, "A")
+            _check_device(A, "A", Y.device)
+        self.lam = float(lam)
         need = B.size_out()
         B.check(L.msp_nystrom_workspace(code, m, n, s, phi, phi_gamma, ctypes.byref(need)))
         self._ws = _workspace(need.value, Y.device)
@@ -162,10 +172,14 @@ class Precond:
         self.device = Y.device
         h = ctypes.c_void_p()
         B.check(L.msp_nystrom(_stream(Y.device), code, m, n, s, gamma, S_rows.data_ptr(), S_signs.data_ptr(),
-                              Y.data_ptr(), _code(Y), Y.stride(0), float(lam), float(lam0), phi, phi_gamma,
-                              ctypes.c_uint64(phi_seed & (2 ** 64 - 1)), self._ws.data_ptr(), self._ws.numel(),
-                              ctypes.byref(h)))
+                              Y.data_ptr(), _code(Y), Y.stride(0), A.data_ptr() if A is not None else None,
+                              _code(A) if A is not None else 0, A.stride(0) if A is not None else 0, float(lam),
+                              lam0, phi, phi_gamma, ctypes.c_uint64(phi_seed & (2 ** 64 - 1)), self._ws.data_ptr(),
+                              self._ws.numel(), ctypes.byref(h)))
         self.handle = h
+        lv, l0 = ctypes.c_double(), ctypes.c_double()
+        B.check(L.msp_precond_params(h, ctypes.byref(lv), ctypes.byref(l0)))
+        self.lam0 = l0.value
 
     @property
     def Y(self):
@@ -199,8 +213,8 @@ class Precond:
             pass
 
 
-def nystrom(structure, S_rows, S_signs, Y, lam, lam0, phi, phi_gamma, phi_seed) -> Precond:
-    return Precond(structure, S_rows, S_signs, Y, lam, lam0, phi, phi_gamma, phi_seed)
+def nystrom(structure, S_rows, S_signs, Y, lam, lam0, phi, phi_gamma, phi_seed, A=None) -> Precond:
+    return Precond(structure, S_rows, S_signs, Y, lam, lam0, phi, phi_gamma, phi_seed, A=A)
 
 
 # -----------------------------------------------------------------------------------
@@ -352,29 +366,93 @@ def solve_backward(P: Precond, A_hi, X, G, A_lo=None, want_dA: bool = False, lam
     return dB, dl.value, dA, info.as_dict()
 
 
-def schatten(P: Precond, A_hi, probes, p: float = 1.0, A_lo=None, h: float = 1.5, u_lo: float = float("nan"),
-             u_hi: float = float("nan"), kind: str = "schatten", **opts):
-    """Hutchinson + quadrature estimate of ||A||_p^p (kind "schatten", P general) or of
-    d_lam (kind "effdim", P psd; p is lam). Returns (estimate, std_err, info)."""
+def gaussian_probes(n: int, N: int, seed: int, device="cuda:0") -> torch.Tensor:
+    """msp_gaussian_probes: (N, n) float64 Gaussian probes drawn on the device from seed."""
     L = library()
-    A_lo = _pair(P, A_hi, A_lo, probes.device)
+    G = torch.empty((N, n), dtype=torch.float64, device=device)
+    B.check(L.msp_gaussian_probes(_stream(G.device), n, N, ctypes.c_uint64(seed & (2 ** 64 - 1)), G.data_ptr(), n))
+    return G
+
+
+def schatten(P: Precond, A_hi, probes, p: float = 1.0, A_lo=None, h: float = 1.5, u_lo: float = float("nan"),
+             u_hi: float = float("nan"), kind: str = "schatten", probe_seed: int = 0, nprobes: int | None = None,
+             **opts):
+    """Hutchinson + quadrature estimate of ||A||_p^p (kind "schatten", P general) or of
+    d_lam (kind "effdim", P psd; p is lam). probes: (N, n) float64 on the GPU, or None with
+    nprobes = N: the library draws them from probe_seed. Returns (estimate, std_err, info)."""
+    L = library()
+    if probes is None:
+        if not nprobes or nprobes < 1:
+            raise ValueError("probes None needs nprobes >= 1")
+        dev = A_hi.device
+        A_lo = _pair(P, A_hi, A_lo, dev)
+        N, ldg = int(nprobes), P.n
+        gptr = None
+    else:
+        A_lo = _pair(P, A_hi, A_lo, probes.device)
+        N, ldg = _vectors(probes, P.n, "probes")
+        dev = probes.device
+        gptr = probes.data_ptr()
     o = _opts(**opts)
-    N, ldg = _vectors(probes, P.n, "probes")
     need = B.size_out()
     B.check(L.msp_schatten_workspace(P.handle, N, ctypes.byref(o), ctypes.byref(need)))
-    ws = _workspace(need.value, probes.device)
+    ws = _workspace(need.value, dev)
     est, se = ctypes.c_double(), ctypes.c_double()
     info = SolveInfo()
     kc = B.MSP_TRACE_SCHATTEN_P if kind == "schatten" else B.MSP_TRACE_EFFDIM
-    code = L.msp_schatten(_stream(probes.device), kc, P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(),
-                          _code(A_lo), A_hi.stride(0), float(p), probes.data_ptr(), ldg, N, float(h), float(u_lo),
-                          float(u_hi), ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(est),
-                          ctypes.byref(se), ctypes.byref(info))
+    code = L.msp_schatten(_stream(dev), kc, P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(),
+                          _code(A_lo), A_hi.stride(0), float(p), gptr, ldg, N,
+                          ctypes.c_uint64(probe_seed & (2 ** 64 - 1)), float(h), float(u_lo), float(u_hi),
+                          ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(est), ctypes.byref(se),
+                          ctypes.byref(info))
     if code not in (0, 4):  # 4: a ridge solve hit its cap; the estimate is still written
         B.check(code)
     d = info.as_dict()
     d["code"] = B.STATUS.get(code, code)
     return est.value, se.value, d
+
+
+def orlicz(P: Precond, A_hi, probes, coefs, powers, A_lo=None, h: float = 1.5, u_hi: float = float("nan"),
+           eps_q: float = float("nan"), probe_seed: int = 0, nprobes: int | None = None, **opts):
+    """Orlicz norm |A|_g for g(s) = sum_q coefs[q] s^powers[q] (msp_orlicz). probes as for
+    schatten. Returns (estimate, std_err, sums, info)."""
+    L = library()
+    coefs = [float(c) for c in coefs]
+    powers = [float(p) for p in powers]
+    if len(coefs) != len(powers) or not coefs:
+        raise ValueError("coefs and powers need the same nonzero length")
+    if probes is None:
+        if not nprobes or nprobes < 1:
+            raise ValueError("probes None needs nprobes >= 1")
+        dev = A_hi.device
+        A_lo = _pair(P, A_hi, A_lo, dev)
+        N, ldg = int(nprobes), P.n
+        gptr = None
+    else:
+        A_lo = _pair(P, A_hi, A_lo, probes.device)
+        N, ldg = _vectors(probes, P.n, "probes")
+        dev = probes.device
+        gptr = probes.data_ptr()
+    o = _opts(**opts)
+    need = B.size_out()
+    B.check(L.msp_schatten_workspace(P.handle, N, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, dev)
+    q = len(coefs)
+    c_arr = (ctypes.c_double * q)(*coefs)
+    p_arr = (ctypes.c_double * q)(*powers)
+    s_arr = (ctypes.c_double * q)()
+    est, se = ctypes.c_double(), ctypes.c_double()
+    info = SolveInfo()
+    code = L.msp_orlicz(_stream(dev), P.handle, A_hi.data_ptr(), _code(A_hi), A_lo.data_ptr(), _code(A_lo),
+                        A_hi.stride(0), ctypes.cast(c_arr, ctypes.c_void_p), ctypes.cast(p_arr, ctypes.c_void_p), q,
+                        gptr, ldg, N, ctypes.c_uint64(probe_seed & (2 ** 64 - 1)), float(h), float(u_hi),
+                        float(eps_q), ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(est),
+                        ctypes.byref(se), ctypes.cast(s_arr, ctypes.c_void_p), ctypes.byref(info))
+    if code not in (0, 4):
+        B.check(code)
+    d = info.as_dict()
+    d["code"] = B.STATUS.get(code, code)
+    return est.value, se.value, list(s_arr), d
 
 
 def effective_dimension(P: Precond, A_hi, probes, lam: float, **opts):

@@ -28,11 +28,12 @@ STATUS = {
 }
 
 EXPORTS = (
-    "msp_sketch_workspace", "msp_sketch", "msp_nystrom_workspace", "msp_nystrom", "msp_precond_destroy",
+    "msp_sketch_workspace", "msp_sketch", "msp_sketch_autotune", "msp_nystrom_workspace", "msp_nystrom", "msp_precond_destroy",
+    "msp_precond_params",
     "msp_precond_set_lambda", "msp_precond_factors", "msp_solve_opts_default", "msp_solve_workspace", "msp_solve",
     "msp_solve_batched_workspace", "msp_solve_batched", "msp_solve_batched_backward_workspace",
     "msp_solve_batched_backward", "msp_solve_backward",
-    "msp_schatten_workspace", "msp_schatten", "msp_left_sketch_workspace", "msp_left_sketch",
+    "msp_schatten_workspace", "msp_schatten", "msp_orlicz", "msp_gaussian_probes", "msp_left_sketch_workspace", "msp_left_sketch",
     "msp_lstsq_workspace", "msp_lstsq", "msp_last_error", "msp_version",
 )
 
@@ -65,6 +66,7 @@ class SolveOpts(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("batch_teams", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
+        ("level3_kernels", ctypes.c_int32),
     ]
 
 
@@ -116,6 +118,7 @@ class SolveInfo(ctypes.Structure):
         ("timed_sweeps", ctypes.c_int64),
         ("sweep_segments", ctypes.c_int32),
         ("seconds", ctypes.c_double),
+        ("trace_nodes", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -150,9 +153,12 @@ def load(path: str | None = None):
     L.msp_sketch_workspace.argtypes = [I64, I64, I64, I32, SZ]
     L.msp_sketch.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, I32, U64, P, P, P, ctypes.c_int, I64, P,
                              ctypes.c_size_t]
+    L.msp_sketch_autotune.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, I32, U64, P, P, P, ctypes.c_int, I64, P,
+                                      ctypes.c_size_t, ctypes.POINTER(I32)]
     L.msp_nystrom_workspace.argtypes = [ctypes.c_int, I64, I64, I64, I64, I32, SZ]
-    L.msp_nystrom.argtypes = [P, ctypes.c_int, I64, I64, I64, I32, P, P, P, ctypes.c_int, I64, D, D, I64, I32, U64, P,
-                              ctypes.c_size_t, ctypes.POINTER(P)]
+    L.msp_nystrom.argtypes = [P, ctypes.c_int, I64, I64, I64, I32, P, P, P, ctypes.c_int, I64, P, ctypes.c_int, I64,
+                              D, D, I64, I32, U64, P, ctypes.c_size_t, ctypes.POINTER(P)]
+    L.msp_precond_params.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
     L.msp_precond_destroy.argtypes = [P]
     L.msp_precond_set_lambda.argtypes = [P, P, D]
     L.msp_precond_factors.argtypes = [P, P, P, P, P]
@@ -173,9 +179,13 @@ def load(path: str | None = None):
                                      ctypes.POINTER(D), P, I64, ctypes.POINTER(SolveOpts), P, ctypes.c_size_t,
                                      ctypes.POINTER(SolveInfo)]
     L.msp_schatten_workspace.argtypes = [P, I64, ctypes.POINTER(SolveOpts), SZ]
-    L.msp_schatten.argtypes = [P, ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_int, I64, D, P, I64, I64, D, D, D,
-                               ctypes.POINTER(SolveOpts), P, ctypes.c_size_t, ctypes.POINTER(D), ctypes.POINTER(D),
+    L.msp_schatten.argtypes = [P, ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_int, I64, D, P, I64, I64, U64, D, D,
+                               D, ctypes.POINTER(SolveOpts), P, ctypes.c_size_t, ctypes.POINTER(D), ctypes.POINTER(D),
                                ctypes.POINTER(SolveInfo)]
+    L.msp_orlicz.argtypes = [P, P, P, ctypes.c_int, P, ctypes.c_int, I64, P, P, I64, P, I64, I64, U64, D, D, D,
+                             ctypes.POINTER(SolveOpts), P, ctypes.c_size_t, ctypes.POINTER(D), ctypes.POINTER(D), P,
+                             ctypes.POINTER(SolveInfo)]
+    L.msp_gaussian_probes.argtypes = [P, I64, I64, U64, P, I64]
     L.msp_left_sketch_workspace.argtypes = [I64, I64, I32, SZ]
     L.msp_left_sketch.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, I32, U64, P, P, P, I64, P, ctypes.c_size_t]
     L.msp_lstsq_workspace.argtypes = [P, I64, I64, ctypes.POINTER(SolveOpts), SZ]

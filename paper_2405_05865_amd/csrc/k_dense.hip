@@ -8,6 +8,8 @@
 // not positive definite) and the Schur complements are formed in Cholesky form.
 #include "msp_internal.h"
 
+#include <hip/hip_bf16.h>
+
 namespace {
 
 constexpr int TILE = 64;
@@ -229,7 +231,61 @@ __global__ void k_sym_avg(int64_t s, double* M) {
   M[j * s + i] = v;
 }
 
+// out[slot] = sum_i A[i, i] in FP64 (one block, fixed order)
+template <class T>
+__global__ void __launch_bounds__(256) k_diag_sum(const T* __restrict__ A, int64_t n, int64_t lda, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc += (double)A[i * lda + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// the estimate (2/l) max(tr A - <Winv, C^T C>_F, 0) with tr A already in scal[0]; the
+// Frobenius product in one block of 1024 threads in a fixed order; scal[1] = <Winv, C^T C>_F,
+// scal[2] = the estimate
+__global__ void __launch_bounds__(1024) k_lambda0_est(const double* __restrict__ Winv, const double* __restrict__ CtC,
+                                                      int64_t len, double l, double* scal) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += 1024) acc = fma(Winv[i], CtC[i], acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    scal[1] = red[0];
+    const double deficit = scal[0] - red[0];
+    // below 1e-6 tr A: the mu bias and rounding of an exact recovery (rank A <= s), taken as 0
+    scal[2] = deficit > 1e-6 * scal[0] ? (2.0 / l) * deficit : 0.0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_diag_sum(hipStream_t st, const void* A, msp_dtype t, int64_t n, int64_t lda, double* out) {
+  if (t == MSP_F64)
+    hipLaunchKernelGGL(k_diag_sum<double>, dim3(1), dim3(256), 0, st, (const double*)A, n, lda, out);
+  else if (t == MSP_F32)
+    hipLaunchKernelGGL(k_diag_sum<float>, dim3(1), dim3(256), 0, st, (const float*)A, n, lda, out);
+  else
+    hipLaunchKernelGGL(k_diag_sum<__hip_bfloat16>, dim3(1), dim3(256), 0, st, (const __hip_bfloat16*)A, n, lda,
+                       out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda0_est(hipStream_t st, const double* Winv, const double* CtC, int64_t s, double l,
+                              double* scal) {
+  hipLaunchKernelGGL(k_lambda0_est, dim3(1), dim3(1024), 0, st, Winv, CtC, s * s, l, scal);
+  return hipGetLastError();
+}
 
 template <class T>
 hipError_t gram_t(hipStream_t st, const T* X, int64_t rows, int64_t s, int64_t ldx, double* G, double* part,

@@ -79,10 +79,10 @@ __device__ __forceinline__ void count_active(FcgState S, int32_t* mirror) {
   if (threadIdx.x == 0) {
     *S.active = cnt;
     if (mirror) {
-      // mirror[0] = columns still iterating, mirror[1] = most iterations taken
+      // mirror[0] = columns still iterating, mirror[1] = most iterations taken; the host
+      // reads them only after synchronising the stream, which orders them (no fence here)
       __hip_atomic_store(mirror, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       __hip_atomic_store(mirror + 1, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __threadfence_system();
     }
     *S.counter = 0;
   }

@@ -95,6 +95,7 @@ SketchWs carve_sketch(WsCarver& w, int64_t n, int64_t s, int32_t gamma) {
 // ------------------------------------------------------------------------------------
 struct NysWs {
   double *Wm, *G, *Minv, *Minv2, *tmp, *small, *gpart, *scal;
+  double *est_w, *est_c, *est_part;  // PSD: the lam0 estimator's W^{-1}, C^T C, Gram partials
   int32_t* status;
   int32_t* phi_rows;
   int8_t* phi_signs;
@@ -111,6 +112,9 @@ NysWs carve_nystrom(WsCarver& w, msp_structure st, int64_t m, int64_t n, int64_t
   if (st == MSP_SYM_PSD) {
     o.Wm = w.take<double>(s * s);
     o.Minv2 = nullptr;
+    o.est_w = w.take<double>(s * s);
+    o.est_c = w.take<double>(s * s);
+    o.est_part = w.take<double>((size_t)gram_splits(n, s) * s * s + 1);
   } else {
     o.Wm = nullptr;
     o.Minv2 = w.take<double>(s * s);
@@ -128,12 +132,18 @@ NysWs carve_nystrom(WsCarver& w, msp_structure st, int64_t m, int64_t n, int64_t
 // ====================================================================================
 // msp_sketch
 // ====================================================================================
+// msp_sketch's scratch: the tile-major lists of S
+TileLists carve_apply_lists(WsCarver& w, int64_t n, int64_t s, int32_t gamma) {
+  int32_t* base = w.take<int32_t>(tile_lists_ints(n, s, gamma));
+  return carve_tile_lists(base, n, s, gamma);
+}
+
 extern "C" msp_status msp_sketch_workspace(int64_t m, int64_t n, int64_t s, int32_t gamma, size_t* bytes) {
   REQUIRE(bytes, "bytes is null");
   REQUIRE(m >= 1 && n >= 1 && s >= 1 && gamma >= 1 && gamma <= s && gamma <= kMaxGammaDraw && s <= n,
           "invalid sizes m=%lld n=%lld s=%lld gamma=%d", (long long)m, (long long)n, (long long)s, gamma);
   WsCarver w(nullptr, 0);
-  carve_sketch(w, n, s, gamma);
+  carve_apply_lists(w, n, s, gamma);
   *bytes = w.off;
   return MSP_OK;
 }
@@ -154,11 +164,27 @@ extern "C" msp_status msp_sketch(void* stream, const void* A, msp_dtype a_t, int
   if (ws_bytes < need || ((uintptr_t)ws & 255)) return msp_fail(MSP_ERR_WORKSPACE, "sketch workspace needs %zu bytes, 256-B aligned", need);
   hipStream_t st = (hipStream_t)stream;
   WsCarver w(ws, ws_bytes);
-  SketchWs k = carve_sketch(w, n, s, gamma);
+  const TileLists L = carve_apply_lists(w, n, s, gamma);
   MSP_CHECK_HIP(launch_sketch_gen(st, seed, n, s, gamma, S_rows, S_signs));
-  MSP_CHECK_HIP(build_buckets(st, S_rows, S_signs, n, s, gamma, k.b, k.scratch));
+  MSP_CHECK_HIP(build_tile_lists(st, S_rows, S_signs, n, s, gamma, L));
   const double scale = 1.0 / std::sqrt((double)gamma);
-  MSP_CHECK_HIP(launch_sketch_apply(st, A, a_t, m, n, lda, s, k.b, scale, Y, y_t, ldy));
+  MSP_CHECK_HIP(launch_sketch_apply(st, A, a_t, m, n, lda, s, L, scale, Y, y_t, ldy, sketch_rows_choice(a_t, m, n, lda, s, gamma)));
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_sketch_autotune(void* stream, const void* A, msp_dtype a_t, int64_t m, int64_t n,
+                                          int64_t lda, int64_t s, int32_t gamma, uint64_t seed, int32_t* S_rows,
+                                          int8_t* S_signs, void* Y, msp_dtype y_t, int64_t ldy, void* ws,
+                                          size_t ws_bytes, int32_t* rows_per_block) {
+  TRY(msp_sketch(stream, A, a_t, m, n, lda, s, gamma, seed, S_rows, S_signs, Y, y_t, ldy, ws, ws_bytes));
+  hipStream_t st = (hipStream_t)stream;
+  WsCarver w(ws, ws_bytes);
+  const TileLists L = carve_apply_lists(w, n, s, gamma);
+  int R = 0;
+  MSP_CHECK_HIP(tune_sketch_apply(st, A, a_t, m, n, lda, s, gamma, L, Y, y_t, ldy, &R));
+  // Y once more with the chosen shape (the timings overwrote it)
+  MSP_CHECK_HIP(launch_sketch_apply(st, A, a_t, m, n, lda, s, L, 1.0 / std::sqrt((double)gamma), Y, y_t, ldy, R));
+  if (rows_per_block) *rows_per_block = R;
   return MSP_OK;
 }
 
@@ -195,6 +221,53 @@ msp_status refactor(hipStream_t st, msp_precond* P) {
 }
 }  // namespace
 
+namespace {
+// lam0 when the caller has no tail spectrum (lambda0 < 0; reading of the lam0 of Theorem
+// 4.1): (2/l) max(tr A - tr(W^+ C^T C), 0), l = s/2. tr(W^+ C^T C) is the trace of the
+// Nystrom approximation C W^+ C^T of Algorithm 1; A minus it is PSD with the approximation
+// of rank <= s, so the deficit is at least sum_{i>s} lambda_i, and 0 when rank(A) <= s.
+// W^+ is taken as (W + mu I)^{-1}, mu = 1e-9 tr(W)/s: C (W + mu I)^{-1} C^T is still below A
+// and of rank <= s, and mu keeps the directions in which a rank-deficient W is zero up to
+// rounding from being amplified.
+constexpr double kLambda0Shift = 1e-9;
+msp_status estimate_lambda0(hipStream_t st, msp_precond* H, const NysWs& o, const void* A, msp_dtype a_t,
+                            int64_t lda) {
+  const int64_t n = H->n, s = H->s;
+  MSP_CHECK_HIP(launch_combine_sym(st, s, 1.0, H->Wm, 0.0, nullptr, 0.0, o.est_w));
+  MSP_CHECK_HIP(hipMemsetAsync(o.status, 0, sizeof(int32_t), st));
+  MSP_CHECK_HIP(spd_inverse(st, s, o.est_w, o.tmp, kLambda0Shift, o.scal + 8, o.status));
+  const int sp = gram_splits(n, s);
+  if (H->y_t == MSP_F64)
+    MSP_CHECK_HIP(launch_gram(st, (const double*)H->Y, n, s, H->ldy, o.est_c, o.est_part, sp));
+  else
+    MSP_CHECK_HIP(launch_gram_f32(st, (const float*)H->Y, n, s, H->ldy, o.est_c, o.est_part, sp));
+  MSP_CHECK_HIP(launch_diag_sum(st, A, a_t, n, lda, o.scal));
+  MSP_CHECK_HIP(launch_lambda0_est(st, o.est_w, o.est_c, s, 0.5 * (double)s, o.scal));
+  double v[3] = {0, 0, 0};
+  int32_t bad = 0;
+  MSP_CHECK_HIP(hipMemcpyAsync(v, o.scal, sizeof v, hipMemcpyDeviceToHost, st));
+  MSP_CHECK_HIP(hipMemcpyAsync(&bad, o.status, sizeof bad, hipMemcpyDeviceToHost, st));
+  MSP_CHECK_HIP(hipStreamSynchronize(st));
+  if (bad) return msp_fail(MSP_ERR_NOT_POSDEF, "W = S C is not positive definite (lambda0 estimator)");
+  if (!isfin(v[2])) return msp_fail(MSP_ERR_NONFINITE, "lambda0 estimate not finite");
+  if (!(H->lam + v[2] > 0.0))
+    return msp_fail(MSP_ERR_INVALID_ARG,
+                    "estimated lambda0 is 0 (the sketch recovers A exactly); pass lambda > 0 or lambda0 > 0");
+  H->lam0 = v[2];
+  H->lt = H->lam + v[2];
+  H->trace_a = v[0];
+  H->trace_nys = v[1];
+  return MSP_OK;
+}
+}  // namespace
+
+extern "C" msp_status msp_precond_params(const msp_precond* P, double* lambda, double* lambda0) {
+  REQUIRE(P, "P is null");
+  if (lambda) *lambda = P->lam;
+  if (lambda0) *lambda0 = P->lam0;
+  return MSP_OK;
+}
+
 extern "C" msp_status msp_nystrom_workspace(msp_structure structure, int64_t m, int64_t n, int64_t s, int64_t phi,
                                             int32_t phi_gamma, size_t* bytes) {
   REQUIRE(bytes, "bytes is null");
@@ -208,8 +281,9 @@ extern "C" msp_status msp_nystrom_workspace(msp_structure structure, int64_t m, 
 
 extern "C" msp_status msp_nystrom(void* stream, msp_structure structure, int64_t m, int64_t n, int64_t s,
                                   int32_t gamma, const int32_t* S_rows, const int8_t* S_signs, const void* Y,
-                                  msp_dtype y_t, int64_t ldy, double lambda, double lambda0, int64_t phi,
-                                  int32_t phi_gamma, uint64_t phi_seed, void* ws, size_t ws_bytes, msp_precond** P) {
+                                  msp_dtype y_t, int64_t ldy, const void* A, msp_dtype a_t, int64_t lda,
+                                  double lambda, double lambda0, int64_t phi, int32_t phi_gamma, uint64_t phi_seed,
+                                  void* ws, size_t ws_bytes, msp_precond** P) {
   REQUIRE(P, "P is null");
   *P = nullptr;
   REQUIRE(structure == MSP_SYM_PSD || structure == MSP_GENERAL, "bad structure");
@@ -223,7 +297,15 @@ extern "C" msp_status msp_nystrom(void* stream, msp_structure structure, int64_t
   REQUIRE(phi <= rows, "phi must not exceed the sketched dimension");
   REQUIRE(rows * phi_gamma < (int64_t(1) << 30) && n * gamma < (int64_t(1) << 30), "sizes too large");
   if (!isfin(lambda) || !isfin(lambda0)) return msp_fail(MSP_ERR_NONFINITE, "lambda/lambda0 not finite");
-  REQUIRE(lambda >= 0.0 && lambda0 >= 0.0 && lambda + lambda0 > 0.0, "need lambda, lambda0 >= 0 and lambda + lambda0 > 0");
+  const bool estimate = lambda0 < 0.0;
+  if (estimate) {
+    if (structure != MSP_SYM_PSD)
+      return msp_fail(MSP_ERR_UNSUPPORTED, "the lambda0 estimator is for MSP_SYM_PSD handles; pass lambda0 >= 0");
+    REQUIRE(A && valid_dtype(a_t) && lda >= n, "lambda0 < 0 (estimate) needs A (n x n, lda >= n)");
+    REQUIRE(lambda >= 0.0, "need lambda >= 0");
+  } else {
+    REQUIRE(lambda >= 0.0 && lambda + lambda0 > 0.0, "need lambda, lambda0 >= 0 and lambda + lambda0 > 0");
+  }
   const size_t need = nystrom_bytes(structure, m, n, s, phi, phi_gamma, gamma);
   if (ws_bytes < need || ((uintptr_t)ws & 255))
     return msp_fail(MSP_ERR_WORKSPACE, "nystrom workspace needs %zu bytes, 256-B aligned", need);
@@ -287,6 +369,10 @@ extern "C" msp_status msp_nystrom(void* stream, msp_structure structure, int64_t
     if (e == hipSuccess) e = launch_gather_rows(st, Y, y_t, ldy, s, phi, o.sk_Phi.b, sphi, o.small, s);
     if (e == hipSuccess) e = launch_gram(st, o.small, phi, s, s, o.G, o.gpart, gram_splits(phi, s));
     if (e != hipSuccess) return fail(msp_fail_hip(e, "nystrom kernels", __FILE__, __LINE__));
+    if (estimate) {
+      msp_status r = estimate_lambda0(st, H, o, A, a_t, lda);
+      if (r != MSP_OK) return fail(r);
+    }
   } else {
     // Algorithm 3 lines 4-5: A^ = Phi A~ over the m rows, M3a = A^^T A^
     hipError_t e = launch_sketch_gen(st, phi_seed, m, phi, phi_gamma, o.phi_rows, o.phi_signs);
@@ -362,6 +448,7 @@ extern "C" void msp_solve_opts_default(msp_solve_opts* o) {
   o->use_graph = 0;
   o->batch_teams = 1;
   o->autotune = 0;
+  o->level3_kernels = 2;
 }
 
 
@@ -434,6 +521,9 @@ struct SolveCtx {
   bool use_x = false;
   L2xArgs X{};
   double* G2 = nullptr;                      // PSD: H2 M2^{-1}
+  // general level 3 under level2_form 1 with k <= kL2fMaxK: two kernels per step
+  bool use_f = false;
+  L2fArgs F{};
   int32_t* hf;
   int32_t* df;
   int last_inner = 4, last_l3a = 4, last_l3b = 4;
@@ -444,7 +534,7 @@ struct SolveCtx {
   size_t evused = 0;
 };
 
-size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, int form, int sym) {
+size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, int form, int sym, int l3k) {
   const int64_t n = P->n, m = P->m, s = P->s;
   const int64_t mx = std::max(n, m);
   const int64_t nb_gemv = (mx + 3) / 4;  // upper bound of gemv blocks (R >= 4)
@@ -505,6 +595,10 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
     X = l2x_carve(w, s, k);
     G2 = w.take<double>(s * s);
   }
+  // the general level 3 as two kernels per step (level2_form 1, at most kL2fMaxK columns)
+  const bool use_f = form == 1 && P->structure == MSP_GENERAL && l3k == 2 && k <= kL2fMaxK;
+  L2fArgs F{};
+  if (use_f) F = l2f_carve(w, s, k);
   // the lower-triangle level-1 sweep (PSD, one right-hand side)
   double* sympart = nullptr;
   if (sym && P->structure == MSP_SYM_PSD && k == 1) sympart = w.take<double>(symv_part_doubles(n));
@@ -517,6 +611,8 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
     c->gemmpart_n = gemmpart_n;
     c->use_x = use_x;
     c->X = X;
+    c->use_f = use_f;
+    c->F = F;
     c->G2 = G2;
     c->Htmp = Htmp;
     c->Hscal = Hscal;
@@ -820,6 +916,67 @@ msp_status run_l2x(SolveCtx& c, const L2xArgs& x, int slotid, int* last, int64_t
   return MSP_OK;
 }
 
+// the first P steps of a two-kernel solve as one graph (use_graph), keyed like l2_graph
+msp_status l2f_graph(SolveCtx& c, const L2fArgs& f, int P, hipGraphExec_t* out) {
+  const auto key = std::make_tuple(P | (2 << 24), (const void*)f.H, (const void*)f.Minv, (const void*)f.y);
+  auto it = c.graphs.exec.find(key);
+  if (it != c.graphs.exec.end()) {
+    *out = it->second;
+    return MSP_OK;
+  }
+  c.graphs.st = c.st;
+  if (!c.graphs.cap) MSP_CHECK_HIP(hipStreamCreateWithFlags(&c.graphs.cap, hipStreamNonBlocking));
+  MSP_CHECK_HIP(hipStreamBeginCapture(c.graphs.cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < P && e == hipSuccess; ++i) {
+    e = l2f_op(c.graphs.cap, f, i, i == 0 ? 1 : 0);
+    if (e == hipSuccess) e = l2f_prec(c.graphs.cap, f, i);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c.graphs.cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    MSP_CHECK_HIP(e != hipSuccess ? e : e2);
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  MSP_CHECK_HIP(e);
+  c.graphs.exec[key] = ex;
+  *out = ex;
+  return MSP_OK;
+}
+
+// inner FCG with two kernels per step (explicit operator, direct products) from the
+// l2_init state. The decision on step t's residual is taken by the operator kernel of
+// step t + 1, so the predicted count plus one step is issued first (the last step's
+// kernels only carry the finished state), then pairs until every column is done.
+msp_status run_l2f(SolveCtx& c, const L2fArgs& f, int slotid, int* last, int64_t* counter) {
+  const int cap = f.max_iter + 1;  // the decision of the capped step needs one more launch
+  const int chunk = std::min(cap, std::max(1, *last + 1));
+  int issued = 0;
+  if (c.o->use_graph) {  // the predicted chunk as one graph launch
+    hipGraphExec_t ex = nullptr;
+    TRY(l2f_graph(c, f, chunk, &ex));
+    MSP_CHECK_HIP(hipGraphLaunch(ex, c.st));
+    issued = chunk;
+  }
+  int want = chunk;
+  while (true) {
+    for (; issued < want && issued < cap; ++issued) {
+      MSP_CHECK_HIP(l2f_op(c.st, f, issued, issued == 0 ? 1 : 0));
+      MSP_CHECK_HIP(l2f_prec(c.st, f, issued));
+    }
+    TRY(sync(c));
+    if (*slot(c, slotid) == 0 || issued >= cap) break;
+    want = issued + 2;
+  }
+  const int taken = *slot(c, slotid + 1);
+  *counter += taken;
+  if (taken > 0) *last = taken;
+  return MSP_OK;
+}
+
 // out[:, j] = M v_j for an FP64 rows x cols row-major M (block product for k >= 8)
 msp_status dense_mv(SolveCtx& c, const double* M, int64_t rows, int64_t cols, const double* v, int64_t ldv,
                     double* out, int64_t ldo, const int32_t* skip) {
@@ -1001,7 +1158,25 @@ msp_status gen_level3(SolveCtx& c, const double* rhs, double* out, double sigma,
     a.pqw = c.pqw;
   }
   MSP_CHECK_HIP(l2_init(c.st, a));
-  TRY(run_l2(c, a, nullptr, SLOT_L3, last, &c.acc.level3_iters, c.form == 1 ? c.H3 : nullptr));
+  if (c.use_f) {
+    L2fArgs f = c.F;
+    f.H = c.H3;
+    f.Minv = Minv;
+    f.sigma = sigma;
+    f.S = c.L3.S;
+    f.y = c.L3.x;
+    f.z = c.L3.z;
+    f.q = c.L3.q;
+    f.r[0] = c.L3.r;
+    f.r[1] = c.L3.ro;
+    f.p[0] = c.L3.p;
+    f.tol = c.o->level3_tol;
+    f.max_iter = c.o->max_level3;
+    f.mirror = c.df + SLOT_L3;
+    TRY(run_l2f(c, f, SLOT_L3, last, &c.acc.level3_iters));
+  } else {
+    TRY(run_l2(c, a, nullptr, SLOT_L3, last, &c.acc.level3_iters, c.form == 1 ? c.H3 : nullptr));
+  }
   MSP_CHECK_HIP(launch_copy_block(c.st, c.s, c.k, c.L3.x, c.s, out, c.s));
   return MSP_OK;
 }
@@ -1433,7 +1608,7 @@ msp_status make_ctx(SolveCtx& c, void* stream, const msp_precond* P, const void*
   c.df = P->dev_view_flags;
   c.evpool = (std::vector<hipEvent_t>*)P->events;
   WsCarver w(ws, ws_bytes);
-  solve_layout(w, P, k, &c, o->level2_form, o->sym_sweep);
+  solve_layout(w, P, k, &c, o->level2_form, o->sym_sweep, o->level3_kernels);
   if (!w.ok()) return msp_fail(MSP_ERR_WORKSPACE, "workspace overflow");
   // the explicit general operators need the block transposed product (s >= 8)
   if (P->structure == MSP_GENERAL && P->s < kGemmMinK) c.form = 0;
@@ -1452,8 +1627,9 @@ extern "C" msp_status msp_solve_workspace(const msp_precond* P, int64_t k, const
   msp_solve_opts_default(&dflt);
   const msp_solve_opts* o = opts ? opts : &dflt;
   REQUIRE(o->level2_form >= 0 && o->level2_form <= 2, "level2_form must be 0, 1 or 2");
+  REQUIRE(o->level3_kernels == 0 || o->level3_kernels == 2, "level3_kernels must be 0 or 2");
   WsCarver w(nullptr, 0);
-  solve_layout(w, P, k, nullptr, o->level2_form, o->sym_sweep);
+  solve_layout(w, P, k, nullptr, o->level2_form, o->sym_sweep, o->level3_kernels);
   *bytes = w.off;
   return MSP_OK;
 }
@@ -1526,8 +1702,9 @@ extern "C" msp_status msp_solve_backward(void* stream, const msp_precond* P, con
 // ====================================================================================
 namespace {
 size_t schatten_extra(const msp_precond* P, int64_t N) {
-  // X, A G, A X (n x N each), the A^T partials of the power iteration, probe dots
-  return ((size_t)3 * P->n * N + gemv_t_part_doubles(P->n, P->n, 1) + 4 * N + 4096) * sizeof(double);
+  // X, A G, A X and the generated probes (n x N each), the A^T partials of the power
+  // iteration, probe dots
+  return ((size_t)4 * P->n * N + gemv_t_part_doubles(P->n, P->n, 1) + 4 * N + 4096) * sizeof(double);
 }
 }  // namespace
 
@@ -1540,130 +1717,173 @@ extern "C" msp_status msp_schatten_workspace(const msp_precond* P, int64_t nprob
   return MSP_OK;
 }
 
-extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precond* P, const void* A_hi,
-                                   msp_dtype hi_t, const void* A_lo, msp_dtype lo_t, int64_t lda, double p,
-                                   const double* G, int64_t ldg, int64_t N, double h, double u_lo, double u_hi,
-                                   const msp_solve_opts* opts, void* ws, size_t ws_bytes, double* estimate,
-                                   double* std_err, msp_solve_info* info) {
-  const double t0 = wall_seconds();
-  msp_solve_opts dflt;
-  msp_solve_opts_default(&dflt);
-  msp_solve_opts o = opts ? *opts : dflt;
-  REQUIRE(P && G && estimate, "null argument");
-  REQUIRE(kind == MSP_TRACE_SCHATTEN_P || kind == MSP_TRACE_EFFDIM, "bad kind");
-  REQUIRE(N >= 1 && ldg >= P->n, "bad probe block");
+extern "C" msp_status msp_gaussian_probes(void* stream, int64_t n, int64_t N, uint64_t seed, double* G,
+                                          int64_t ldg) {
+  REQUIRE(G, "G is null");
+  REQUIRE(n >= 1 && N >= 1 && ldg >= n, "need n, N >= 1 and ldg >= n");
+  MSP_CHECK_HIP(launch_probes((hipStream_t)stream, seed, n, N, G, ldg));
+  return MSP_OK;
+}
+
+namespace {
+
+// The ridge values of the trace driver (Section 3.2): per probe g_k and node t,
+// T_k = <A g_k, A x_k> and D_k = t <g_k, x_k> with x_k = (A^T A + t I)^{-1} g_k solved by the
+// three-level MSP of the handle (lam~ = t + lam0), so that T_k = |g_k|^2 - D_k.
+struct TraceRun {
+  hipStream_t st = nullptr;
+  void* stream = nullptr;
+  msp_precond* P = nullptr;
+  const void *A_hi = nullptr, *A_lo = nullptr;
+  msp_dtype hi_t = MSP_F64, lo_t = MSP_F64;
+  int64_t lda = 0, n = 0, N = 0, ldg = 0;
+  const double* G = nullptr;
+  msp_solve_opts o{};
+  void* ws = nullptr;
+  size_t solve_bytes = 0;
+  double *X = nullptr, *AG = nullptr, *AX = nullptr, *gtp = nullptr, *dv = nullptr;
+  std::vector<double> gg;  // |g_k|^2
+  msp_solve_info acc{};
+  bool unconverged = false;
+  int nodes = 0;
+};
+
+void trace_add_info(TraceRun& R, const msp_solve_info& i) {
+  R.acc.outer_iters += i.outer_iters;
+  R.acc.inner_iters += i.inner_iters;
+  R.acc.level3_iters += i.level3_iters;
+  R.acc.refine_steps += i.refine_steps;
+  R.acc.sweeps += i.sweeps;
+  R.acc.sweep_bytes += i.sweep_bytes;
+  R.acc.rel_residual_max = std::max(R.acc.rel_residual_max, i.rel_residual_max);
+  R.acc.sweep_segments = i.sweep_segments;
+}
+
+// workspace carving, probes (given or drawn from probe_seed), |g|^2
+msp_status trace_setup(TraceRun& R, void* stream, msp_precond* P, const void* A_hi, msp_dtype hi_t, const void* A_lo,
+                       msp_dtype lo_t, int64_t lda, const double* G, int64_t ldg, int64_t N, uint64_t probe_seed,
+                       const msp_solve_opts& o, void* ws, size_t ws_bytes) {
+  REQUIRE(N >= 1 && (!G || ldg >= P->n), "bad probe block");
   REQUIRE(P->m == P->n, "square A only");
-  if (!isfin(p)) return msp_fail(MSP_ERR_NONFINITE, "p not finite");
   size_t need = 0;
   TRY(msp_schatten_workspace(P, N, &o, &need));
   if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
-    return msp_fail(MSP_ERR_WORKSPACE, "schatten workspace needs %zu bytes, 256-B aligned", need);
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t n = P->n;
-  size_t solve_bytes = 0;
-  TRY(msp_solve_workspace(P, N, &o, &solve_bytes));
-  solve_bytes = (solve_bytes + 255) & ~size_t(255);
-  double* X = (double*)((char*)ws + solve_bytes);
-  double* AG = X + n * N;
-  double* AX = AG + n * N;
-  double* gtp = AX + n * N;
-  double* dv = gtp + gemv_t_part_doubles(n, n, 1);
-  std::vector<double> per(N, 0.0), d(N);
-  bool unconverged = false;  // some solve stopped at its iteration cap (estimate still written)
-  msp_solve_info acc{};
-  auto add_info = [&](const msp_solve_info& i) {
-    acc.outer_iters += i.outer_iters;
-    acc.inner_iters += i.inner_iters;
-    acc.level3_iters += i.level3_iters;
-    acc.refine_steps += i.refine_steps;
-    acc.sweeps += i.sweeps;
-    acc.sweep_bytes += i.sweep_bytes;
-    acc.rel_residual_max = std::max(acc.rel_residual_max, i.rel_residual_max);
-    acc.sweep_segments = i.sweep_segments;
-  };
-  if (kind == MSP_TRACE_EFFDIM) {
-    REQUIRE(P->structure == MSP_SYM_PSD, "effective dimension needs an MSP_SYM_PSD handle");
-    REQUIRE(p > 0.0, "lam > 0");
-    if (P->lam != p) TRY(msp_precond_set_lambda(stream, P, p));
-    msp_solve_info i{};
-    msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, p, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
-    if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) return s_;
-    if (s_ != MSP_OK) unconverged = true;
-    add_info(i);
-    // per probe: g^T g - lam g^T x
-    MSP_CHECK_HIP(launch_coldots(st, n, N, G, ldg, G, ldg, dv));
-    MSP_CHECK_HIP(launch_coldots(st, n, N, G, ldg, X, n, dv + N));
-    std::vector<double> gg(N), gx(N);
-    MSP_CHECK_HIP(hipMemcpyAsync(gg.data(), dv, sizeof(double) * N, hipMemcpyDeviceToHost, st));
-    MSP_CHECK_HIP(hipMemcpyAsync(gx.data(), dv + N, sizeof(double) * N, hipMemcpyDeviceToHost, st));
-    MSP_CHECK_HIP(hipStreamSynchronize(st));
-    for (int64_t j = 0; j < N; ++j) per[j] = gg[j] - p * gx[j];
-  } else {
-    REQUIRE(P->structure == MSP_GENERAL, "Schatten-p needs an MSP_GENERAL handle");
-    REQUIRE(p > 0.0 && p < 2.0, "need 0 < p < 2");
-    REQUIRE(h > 0.0, "need h > 0");
-    o.normal = 1;
-    // the node range from a power-iteration estimate of |A| when not given
-    if (!(u_lo == u_lo) || !(u_hi == u_hi)) {
-      double* v = X;
-      MSP_CHECK_HIP(launch_copy_block(st, n, 1, G, ldg, v, n));
-      double s2 = 0.0;
-      std::vector<double> nn(1);
-      for (int it = 0; it < 30; ++it) {
-        MSP_CHECK_HIP(launch_coldots(st, n, 1, v, n, v, n, dv));
-        MSP_CHECK_HIP(hipMemcpyAsync(nn.data(), dv, sizeof(double), hipMemcpyDeviceToHost, st));
-        MSP_CHECK_HIP(hipStreamSynchronize(st));
-        const double nv = std::sqrt(nn[0]);
-        if (nv == 0.0) break;
-        MSP_CHECK_HIP(launch_axpby(st, n, 1, 1.0 / nv, v, n, 0.0, nullptr, 0, v, n, nullptr));
-        int nb = 0;
-        MSP_CHECK_HIP(launch_gemv(st, A_hi, hi_t, n, n, lda, v, n, AG, n, 1, 0.0, false, nullptr, nullptr, &nb));
-        MSP_CHECK_HIP(launch_gemv_t(st, A_hi, hi_t, n, n, lda, AG, n, v, n, 1, nullptr, gtp));
-        MSP_CHECK_HIP(launch_coldots(st, n, 1, v, n, v, n, dv));
-        MSP_CHECK_HIP(hipMemcpyAsync(nn.data(), dv, sizeof(double), hipMemcpyDeviceToHost, st));
-        MSP_CHECK_HIP(hipStreamSynchronize(st));
-        s2 = std::sqrt(nn[0]);  // |A^T A v| with |v| = 1
-      }
-      const double smax = std::sqrt(std::max(s2, 1e-300)) * 1.01;
-      const double eps_q = 1e-4;
-      const double ls = 2.0 * std::log(smax);
-      u_lo = ls + (2.0 / p) * std::log(eps_q / (double)n);
-      u_hi = ls + (2.0 / (2.0 - p)) * std::log(1.0 / eps_q);
-    }
-    REQUIRE(u_hi >= u_lo, "u_hi < u_lo");
-    // A g for every probe, once
-    int nb = 0;
-    MSP_CHECK_HIP(N >= kGemmMinK
-                      ? launch_gemm(st, A_hi, hi_t, false, n, n, lda, G, ldg, AG, n, N, 0.0, false, nullptr, nullptr, &nb)
-                      : launch_gemv(st, A_hi, hi_t, n, n, lda, G, ldg, AG, n, N, 0.0, false, nullptr, nullptr, &nb));
-    const int count = (int)std::floor((u_hi - u_lo) / h + 1e-9) + 1;
-    const double lam_save = P->lam;
-    for (int jn = 0; jn < count; ++jn) {
-      const double u = u_lo + h * jn;
-      const double t = std::exp(u);
-      const double w = h * std::sin(M_PI * p / 2.0) / M_PI * std::exp(0.5 * p * u);
-      TRY(msp_precond_set_lambda(stream, P, t));
-      msp_solve_info i{};
-      msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, t, G, ldg, N, X, n, &o, ws, solve_bytes, &i);
-      if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) {
-        (void)msp_precond_set_lambda(stream, P, lam_save);
-        return s_;
-      }
-      if (s_ != MSP_OK) unconverged = true;
-      add_info(i);
-      if (log_on())
-        fprintf(stderr, "[msp] schatten node %d/%d t=%.3e outer=%d inner=%lld level3=%lld relres=%.2e\n", jn + 1,
-                count, t, i.outer_iters, (long long)i.inner_iters, (long long)i.level3_iters, i.rel_residual_max);
-      MSP_CHECK_HIP(N >= kGemmMinK
-                        ? launch_gemm(st, A_hi, hi_t, false, n, n, lda, X, n, AX, n, N, 0.0, false, nullptr, nullptr, &nb)
-                        : launch_gemv(st, A_hi, hi_t, n, n, lda, X, n, AX, n, N, 0.0, false, nullptr, nullptr, &nb));
-      MSP_CHECK_HIP(launch_coldots(st, n, N, AG, n, AX, n, dv));
-      MSP_CHECK_HIP(hipMemcpyAsync(d.data(), dv, sizeof(double) * N, hipMemcpyDeviceToHost, st));
-      MSP_CHECK_HIP(hipStreamSynchronize(st));
-      for (int64_t j = 0; j < N; ++j) per[j] += w * d[j];
-    }
-    TRY(msp_precond_set_lambda(stream, P, lam_save));
+    return msp_fail(MSP_ERR_WORKSPACE, "trace workspace needs %zu bytes, 256-B aligned", need);
+  R.stream = stream;
+  R.st = (hipStream_t)stream;
+  R.P = P;
+  R.A_hi = A_hi;
+  R.hi_t = hi_t;
+  R.A_lo = A_lo;
+  R.lo_t = lo_t;
+  R.lda = lda;
+  R.n = P->n;
+  R.N = N;
+  R.o = o;
+  R.ws = ws;
+  TRY(msp_solve_workspace(P, N, &o, &R.solve_bytes));
+  R.solve_bytes = (R.solve_bytes + 255) & ~size_t(255);
+  const int64_t n = R.n;
+  R.X = (double*)((char*)ws + R.solve_bytes);
+  R.AG = R.X + n * N;
+  R.AX = R.AG + n * N;
+  double* Gw = R.AX + n * N;
+  R.gtp = Gw + n * N;
+  R.dv = R.gtp + gemv_t_part_doubles(n, n, 1);
+  if (!G) {  // probes from probe_seed (the generator of msp_gaussian_probes)
+    MSP_CHECK_HIP(launch_probes(R.st, probe_seed, n, N, Gw, n));
+    G = Gw;
+    ldg = n;
   }
+  R.G = G;
+  R.ldg = ldg;
+  R.gg.assign(N, 0.0);
+  MSP_CHECK_HIP(launch_coldots(R.st, n, N, G, ldg, G, ldg, R.dv));
+  MSP_CHECK_HIP(hipMemcpyAsync(R.gg.data(), R.dv, sizeof(double) * N, hipMemcpyDeviceToHost, R.st));
+  MSP_CHECK_HIP(hipStreamSynchronize(R.st));
+  return MSP_OK;
+}
+
+// A g for every probe, once (before the first node)
+msp_status trace_ag(TraceRun& R) {
+  int nb = 0;
+  MSP_CHECK_HIP(R.N >= kGemmMinK ? launch_gemm(R.st, R.A_hi, R.hi_t, false, R.n, R.n, R.lda, R.G, R.ldg, R.AG, R.n, R.N,
+                                               0.0, false, nullptr, nullptr, &nb)
+                                 : launch_gemv(R.st, R.A_hi, R.hi_t, R.n, R.n, R.lda, R.G, R.ldg, R.AG, R.n, R.N, 0.0,
+                                               false, nullptr, nullptr, &nb));
+  return MSP_OK;
+}
+
+// |A| by power iteration on A^T A from the first probe (30 steps, 1% margin)
+msp_status trace_sigma_max(TraceRun& R, double* smax) {
+  const int64_t n = R.n;
+  double* v = R.X;
+  MSP_CHECK_HIP(launch_copy_block(R.st, n, 1, R.G, R.ldg, v, n));
+  double s2 = 0.0;
+  std::vector<double> nn(1);
+  for (int it = 0; it < 30; ++it) {
+    MSP_CHECK_HIP(launch_coldots(R.st, n, 1, v, n, v, n, R.dv));
+    MSP_CHECK_HIP(hipMemcpyAsync(nn.data(), R.dv, sizeof(double), hipMemcpyDeviceToHost, R.st));
+    MSP_CHECK_HIP(hipStreamSynchronize(R.st));
+    const double nv = std::sqrt(nn[0]);
+    if (nv == 0.0) break;
+    MSP_CHECK_HIP(launch_axpby(R.st, n, 1, 1.0 / nv, v, n, 0.0, nullptr, 0, v, n, nullptr));
+    int nb = 0;
+    MSP_CHECK_HIP(launch_gemv(R.st, R.A_hi, R.hi_t, n, n, R.lda, v, n, R.AX, n, 1, 0.0, false, nullptr, nullptr, &nb));
+    MSP_CHECK_HIP(launch_gemv_t(R.st, R.A_hi, R.hi_t, n, n, R.lda, R.AX, n, v, n, 1, nullptr, R.gtp));
+    MSP_CHECK_HIP(launch_coldots(R.st, n, 1, v, n, v, n, R.dv));
+    MSP_CHECK_HIP(hipMemcpyAsync(nn.data(), R.dv, sizeof(double), hipMemcpyDeviceToHost, R.st));
+    MSP_CHECK_HIP(hipStreamSynchronize(R.st));
+    s2 = std::sqrt(nn[0]);  // |A^T A v| with |v| = 1
+  }
+  *smax = std::sqrt(std::max(s2, 1e-300)) * 1.01;
+  return MSP_OK;
+}
+
+// one node: T[k] = <A g_k, A x_k>, D[k] = t <g_k, x_k>
+msp_status trace_node(TraceRun& R, double t, int index, int count, std::vector<double>& T, std::vector<double>& D) {
+  const int64_t n = R.n, N = R.N;
+  TRY(msp_precond_set_lambda(R.stream, R.P, t));
+  msp_solve_info i{};
+  msp_status s_ = msp_solve(R.stream, R.P, R.A_hi, R.hi_t, R.A_lo, R.lo_t, R.lda, t, R.G, R.ldg, N, R.X, n, &R.o, R.ws,
+                            R.solve_bytes, &i);
+  if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) return s_;
+  if (s_ != MSP_OK) R.unconverged = true;
+  trace_add_info(R, i);
+  R.nodes += 1;
+  if (log_on())
+    fprintf(stderr, "[msp] trace node %d%s%d t=%.3e outer=%d inner=%lld level3=%lld relres=%.2e\n", index + 1,
+            count > 0 ? "/" : " ", count > 0 ? count : 0, t, i.outer_iters, (long long)i.inner_iters,
+            (long long)i.level3_iters, i.rel_residual_max);
+  int nb = 0;
+  MSP_CHECK_HIP(N >= kGemmMinK ? launch_gemm(R.st, R.A_hi, R.hi_t, false, n, n, R.lda, R.X, n, R.AX, n, N, 0.0, false,
+                                             nullptr, nullptr, &nb)
+                               : launch_gemv(R.st, R.A_hi, R.hi_t, n, n, R.lda, R.X, n, R.AX, n, N, 0.0, false, nullptr,
+                                             nullptr, &nb));
+  MSP_CHECK_HIP(launch_coldots(R.st, n, N, R.AG, n, R.AX, n, R.dv));
+  MSP_CHECK_HIP(launch_coldots(R.st, n, N, R.G, R.ldg, R.X, n, R.dv + N));
+  T.resize(N);
+  D.resize(N);
+  MSP_CHECK_HIP(hipMemcpyAsync(T.data(), R.dv, sizeof(double) * N, hipMemcpyDeviceToHost, R.st));
+  MSP_CHECK_HIP(hipMemcpyAsync(D.data(), R.dv + N, sizeof(double) * N, hipMemcpyDeviceToHost, R.st));
+  MSP_CHECK_HIP(hipStreamSynchronize(R.st));
+  for (int64_t k = 0; k < N; ++k) D[k] *= t;
+  return MSP_OK;
+}
+
+// sum over the grid nodes below u_j (u_j - h, u_j - 2h, ...) of h sin(pi p/2)/pi e^{(p/2) u}
+double lower_tail_weight(double p, double h, double u_j) {
+  const double c = h * std::sin(M_PI * p / 2.0) / M_PI;
+  return c * std::exp(0.5 * p * (u_j - h)) / (1.0 - std::exp(-0.5 * p * h));
+}
+
+// u_hi from |A|: above it the integrand's tail is eps_q of the top singular value's share
+double upper_end(double smax, double p, double eps_q) {
+  return 2.0 * std::log(smax) + (2.0 / (2.0 - p)) * std::log(1.0 / eps_q);
+}
+
+void finish_stats(const std::vector<double>& per, double* estimate, double* std_err) {
+  const int64_t N = (int64_t)per.size();
   double mean = 0.0;
   for (double v : per) mean += v;
   mean /= (double)N;
@@ -1671,9 +1891,214 @@ extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precon
   for (double v : per) var += (v - mean) * (v - mean);
   *estimate = mean;
   if (std_err) *std_err = N > 1 ? std::sqrt(var / (double)(N - 1) / (double)N) : NAN;
-  acc.status = unconverged ? MSP_ERR_NO_CONVERGENCE : MSP_OK;
-  acc.seconds = wall_seconds() - t0;
-  if (info) *info = acc;
-  if (unconverged) return msp_fail(MSP_ERR_NO_CONVERGENCE, "a ridge solve stopped at its iteration cap");
+}
+
+msp_status trace_finish(TraceRun& R, double t0, msp_solve_info* info) {
+  R.acc.status = R.unconverged ? MSP_ERR_NO_CONVERGENCE : MSP_OK;
+  R.acc.seconds = wall_seconds() - t0;
+  R.acc.trace_nodes = R.nodes;
+  if (info) *info = R.acc;
+  if (R.unconverged) return msp_fail(MSP_ERR_NO_CONVERGENCE, "a ridge solve stopped at its iteration cap");
   return MSP_OK;
+}
+
+constexpr int kMaxTraceNodes = 400;
+constexpr double kTraceEps = 1e-4;
+
+}  // namespace
+
+extern "C" msp_status msp_schatten(void* stream, msp_trace_kind kind, msp_precond* P, const void* A_hi,
+                                   msp_dtype hi_t, const void* A_lo, msp_dtype lo_t, int64_t lda, double p,
+                                   const double* G, int64_t ldg, int64_t N, uint64_t probe_seed, double h,
+                                   double u_lo, double u_hi, const msp_solve_opts* opts, void* ws, size_t ws_bytes,
+                                   double* estimate, double* std_err, msp_solve_info* info) {
+  const double t0 = wall_seconds();
+  msp_solve_opts dflt;
+  msp_solve_opts_default(&dflt);
+  msp_solve_opts o = opts ? *opts : dflt;
+  REQUIRE(P && estimate, "null argument");
+  REQUIRE(kind == MSP_TRACE_SCHATTEN_P || kind == MSP_TRACE_EFFDIM, "bad kind");
+  if (!isfin(p)) return msp_fail(MSP_ERR_NONFINITE, "p not finite");
+  if (kind == MSP_TRACE_EFFDIM) {
+    REQUIRE(P->structure == MSP_SYM_PSD, "effective dimension needs an MSP_SYM_PSD handle");
+    REQUIRE(p > 0.0, "lam > 0");
+  } else {
+    REQUIRE(P->structure == MSP_GENERAL, "Schatten-p needs an MSP_GENERAL handle");
+    REQUIRE(p > 0.0 && p < 2.0, "need 0 < p < 2");
+    REQUIRE(h > 0.0 && isfin(h), "need h > 0");
+    REQUIRE(!isfin(u_lo) || !isfin(u_hi) || u_hi >= u_lo, "u_hi < u_lo");
+  }
+  TraceRun R;
+  TRY(trace_setup(R, stream, P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, N, probe_seed, o, ws, ws_bytes));
+  const int64_t n = R.n;
+  std::vector<double> per(N, 0.0);
+  if (kind == MSP_TRACE_EFFDIM) {
+    if (P->lam != p) TRY(msp_precond_set_lambda(stream, P, p));
+    msp_solve_info i{};
+    msp_status s_ = msp_solve(stream, P, A_hi, hi_t, A_lo, lo_t, lda, p, R.G, R.ldg, N, R.X, n, &R.o, ws,
+                              R.solve_bytes, &i);
+    if (s_ != MSP_OK && s_ != MSP_ERR_NO_CONVERGENCE) return s_;
+    if (s_ != MSP_OK) R.unconverged = true;
+    trace_add_info(R, i);
+    R.nodes = 1;
+    // per probe: g^T g - lam g^T x
+    MSP_CHECK_HIP(launch_coldots(R.st, n, N, R.G, R.ldg, R.X, n, R.dv));
+    std::vector<double> gx(N);
+    MSP_CHECK_HIP(hipMemcpyAsync(gx.data(), R.dv, sizeof(double) * N, hipMemcpyDeviceToHost, R.st));
+    MSP_CHECK_HIP(hipStreamSynchronize(R.st));
+    for (int64_t j = 0; j < N; ++j) per[j] = R.gg[j] - p * gx[j];
+    finish_stats(per, estimate, std_err);
+    return trace_finish(R, t0, info);
+  }
+  R.o.normal = 1;
+  if (!isfin(u_hi)) {  // the upper end from a power-iteration estimate of |A|
+    double smax = 0.0;
+    TRY(trace_sigma_max(R, &smax));
+    u_hi = upper_end(smax, p, kTraceEps);
+  }
+  TRY(trace_ag(R));
+  const double c = h * std::sin(M_PI * p / 2.0) / M_PI;
+  const double lam_save = P->lam;
+  std::vector<double> T, D;
+  auto restore = [&](msp_status s) {
+    (void)msp_precond_set_lambda(stream, P, lam_save);
+    return s;
+  };
+  if (isfin(u_lo)) {  // the fixed grid u_lo, u_lo + h, ... <= u_hi
+    const int count = (int)std::floor((u_hi - u_lo) / h + 1e-9) + 1;
+    for (int jn = 0; jn < count; ++jn) {
+      const double u = u_lo + h * jn;
+      msp_status s_ = trace_node(R, std::exp(u), jn, count, T, D);
+      if (s_ != MSP_OK) return restore(s_);
+      const double w = c * std::exp(0.5 * p * u);
+      for (int64_t j = 0; j < N; ++j) per[j] += w * T[j];
+    }
+  } else {
+    // nodes u_hi, u_hi - h, ... with the lower tail replaced by its t -> 0 limit |g|^2: the
+    // deficit t <g, x> is nondecreasing in t, so after node j that replacement is off by at
+    // most D_j times the tail weight per probe; stop when the mean of that bound is at most
+    // kTraceEps of the estimate
+    std::vector<double> acc(N, 0.0);
+    for (int jn = 0; jn < kMaxTraceNodes; ++jn) {
+      const double u = u_hi - h * jn;
+      msp_status s_ = trace_node(R, std::exp(u), jn, 0, T, D);
+      if (s_ != MSP_OK) return restore(s_);
+      const double w = c * std::exp(0.5 * p * u);
+      const double wb = lower_tail_weight(p, h, u);
+      double dm = 0.0, em = 0.0;
+      for (int64_t j = 0; j < N; ++j) {
+        acc[j] += w * T[j];
+        per[j] = acc[j] + wb * R.gg[j];
+        dm += std::fabs(D[j]);
+        em += per[j];
+      }
+      dm /= (double)N;
+      em /= (double)N;
+      if (dm * wb <= kTraceEps * std::fabs(em)) break;
+    }
+  }
+  TRY(msp_precond_set_lambda(stream, P, lam_save));
+  finish_stats(per, estimate, std_err);
+  return trace_finish(R, t0, info);
+}
+
+extern "C" msp_status msp_orlicz(void* stream, msp_precond* P, const void* A_hi, msp_dtype hi_t, const void* A_lo,
+                                 msp_dtype lo_t, int64_t lda, const double* coefs, const double* powers,
+                                 int64_t nterms, const double* G, int64_t ldg, int64_t N, uint64_t probe_seed,
+                                 double h, double u_hi, double eps_q, const msp_solve_opts* opts, void* ws,
+                                 size_t ws_bytes, double* estimate, double* std_err, double* sums,
+                                 msp_solve_info* info) {
+  const double t0 = wall_seconds();
+  msp_solve_opts dflt;
+  msp_solve_opts_default(&dflt);
+  msp_solve_opts o = opts ? *opts : dflt;
+  REQUIRE(P && estimate && coefs && powers, "null argument");
+  REQUIRE(P->structure == MSP_GENERAL, "the Orlicz norm needs an MSP_GENERAL handle");
+  REQUIRE(nterms >= 1 && nterms <= 16, "need 1 <= nterms <= 16");
+  for (int64_t q = 0; q < nterms; ++q) {
+    REQUIRE(isfin(coefs[q]) && coefs[q] > 0.0, "coefficients must be finite and > 0");
+    REQUIRE(isfin(powers[q]) && powers[q] > 0.0 && powers[q] < 2.0, "powers must lie in (0, 2)");
+  }
+  REQUIRE(h > 0.0 && isfin(h), "need h > 0");
+  if (!isfin(eps_q)) eps_q = kTraceEps;
+  REQUIRE(eps_q > 0.0 && eps_q < 1.0, "need 0 < eps_q < 1");
+  TraceRun R;
+  TRY(trace_setup(R, stream, P, A_hi, hi_t, A_lo, lo_t, lda, G, ldg, N, probe_seed, o, ws, ws_bytes));
+  R.o.normal = 1;
+  double pmax = 0.0;
+  for (int64_t q = 0; q < nterms; ++q) pmax = std::max(pmax, powers[q]);
+  if (!isfin(u_hi)) {
+    double smax = 0.0;
+    TRY(trace_sigma_max(R, &smax));
+    u_hi = upper_end(smax, pmax, eps_q);
+  }
+  TRY(trace_ag(R));
+  const double lam_save = P->lam;
+  std::vector<double> T, D;
+  std::vector<std::vector<double>> acc(nterms, std::vector<double>(N, 0.0)), per(nterms, std::vector<double>(N, 0.0));
+  for (int jn = 0; jn < kMaxTraceNodes; ++jn) {
+    const double u = u_hi - h * jn;
+    msp_status s_ = trace_node(R, std::exp(u), jn, 0, T, D);
+    if (s_ != MSP_OK) {
+      (void)msp_precond_set_lambda(stream, P, lam_save);
+      return s_;
+    }
+    double dm = 0.0;
+    for (int64_t j = 0; j < N; ++j) dm += std::fabs(D[j]);
+    dm /= (double)N;
+    bool done = true;
+    for (int64_t q = 0; q < nterms; ++q) {
+      const double pq = powers[q];
+      const double w = h * std::sin(M_PI * pq / 2.0) / M_PI * std::exp(0.5 * pq * u);
+      const double wb = lower_tail_weight(pq, h, u);
+      double em = 0.0;
+      for (int64_t j = 0; j < N; ++j) {
+        acc[q][j] += w * T[j];
+        per[q][j] = acc[q][j] + wb * R.gg[j];
+        em += per[q][j];
+      }
+      em /= (double)N;
+      if (dm * wb > eps_q * std::fabs(em)) done = false;
+    }
+    if (done) break;
+  }
+  TRY(msp_precond_set_lambda(stream, P, lam_save));
+  // the Schatten sums, then the root r of sum_q c_q r^{-p_q} S_q = 1 by bisection on ln r
+  std::vector<double> S(nterms, 0.0);
+  for (int64_t q = 0; q < nterms; ++q) {
+    for (int64_t j = 0; j < N; ++j) S[q] += per[q][j];
+    S[q] /= (double)N;
+    if (!(S[q] > 0.0)) return msp_fail(MSP_ERR_NONFINITE, "a Schatten sum estimate is not positive");
+  }
+  if (sums)
+    for (int64_t q = 0; q < nterms; ++q) sums[q] = S[q];
+  auto phi = [&](double lr) {
+    double v = 0.0;
+    for (int64_t q = 0; q < nterms; ++q) v += coefs[q] * S[q] * std::exp(-powers[q] * lr);
+    return v - 1.0;
+  };
+  double lo = -1.0, hi = 1.0;
+  while (phi(lo) < 0.0) lo -= 2.0 * (hi - lo);
+  while (phi(hi) > 0.0) hi += 2.0 * (hi - lo);
+  for (int it = 0; it < 400; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (phi(mid) > 0.0) lo = mid;
+    else hi = mid;
+    if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(mid))) break;
+  }
+  const double r = std::exp(0.5 * (lo + hi));
+  *estimate = r;
+  if (std_err) {  // delta method: per-probe values of the left side, divided by its slope in r
+    std::vector<double> vals(N, 0.0);
+    double dphi = 0.0;
+    for (int64_t q = 0; q < nterms; ++q) {
+      const double f = coefs[q] * std::pow(r, -powers[q]);
+      for (int64_t j = 0; j < N; ++j) vals[j] += f * per[q][j];
+      dphi += -powers[q] * f / r * S[q];
+    }
+    double m = 0.0, se = 0.0;
+    finish_stats(vals, &m, &se);
+    *std_err = se / std::fabs(dphi);
+  }
+  return trace_finish(R, t0, info);
 }

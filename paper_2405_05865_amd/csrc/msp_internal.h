@@ -48,9 +48,27 @@ hipError_t launch_sketch_gen(hipStream_t st, uint64_t seed, int64_t n, int64_t s
                              int32_t* rows, int8_t* signs);
 hipError_t build_buckets(hipStream_t st, const int32_t* rows, const int8_t* signs, int64_t n, int64_t nrows,
                          int32_t gamma, BucketLists out, void* scratch);
-// Y = A S^T with scale 1/sqrt(gamma): out[r, j] = scale * sum_{entries of bucket j} sign * A[r, col]
+// Tile-major lists of S for Y = A S^T: the columns of A in tiles of wc (sketch_tile_width:
+// wc * gamma <= 1024); for tile t and sketch row j, toff[t * (s + 1) + j] .. [.. + j + 1] index
+// tent entries (column within the tile << 1) | neg, columns increasing.
+struct TileLists {
+  int32_t* toff;
+  int32_t* tent;
+  int wc;
+  int ntiles;
+};
+int sketch_tile_width(int32_t gamma);
+size_t tile_lists_ints(int64_t n, int64_t s, int32_t gamma);
+TileLists carve_tile_lists(int32_t* base, int64_t n, int64_t s, int32_t gamma);
+hipError_t build_tile_lists(hipStream_t st, const int32_t* rows, const int8_t* signs, int64_t n, int64_t s,
+                            int32_t gamma, TileLists L);
+// Y = A S^T with scale 1/sqrt(gamma): Y[r, j] = scale * sum_{entries of bucket j} sign * A[r, col],
+// in column order; R = rows of A per block (0: built-in rule; the autotuner's choice otherwise)
 hipError_t launch_sketch_apply(hipStream_t st, const void* A, msp_dtype a_t, int64_t m, int64_t n, int64_t lda,
-                               int64_t s, BucketLists b, double scale, void* Y, msp_dtype y_t, int64_t ldy);
+                               int64_t s, TileLists L, double scale, void* Y, msp_dtype y_t, int64_t ldy, int R);
+// N Gaussian probes of length n (probe j at G + j * ldg) from seed: Box-Muller over the
+// counter-based SplitMix64 stream (msp_gaussian_probes)
+hipError_t launch_probes(hipStream_t st, uint64_t seed, int64_t n, int64_t N, double* G, int64_t ldg);
 // out[j, :] = scale * sum_{entries of bucket j} sign * X[col, :]   (out is F64, nrows x ncols)
 hipError_t launch_gather_rows(hipStream_t st, const void* X, msp_dtype x_t, int64_t ldx, int64_t ncols,
                               int64_t nrows, BucketLists b, double scale, double* out, int64_t ldo);
@@ -72,6 +90,12 @@ hipError_t launch_combine_sym(hipStream_t st, int64_t s, double a, const double*
 hipError_t launch_symmetrize(hipStream_t st, int64_t s, double* Wm);
 // trace(M) -> *out (device scalar)
 hipError_t launch_trace(hipStream_t st, int64_t s, const double* M, double* out);
+// *out = sum_i A[i, i] in FP64 for an F64, F32 or BF16 matrix (device scalar)
+hipError_t launch_diag_sum(hipStream_t st, const void* A, msp_dtype t, int64_t n, int64_t lda, double* out);
+// lam0 estimate from the trace deficit of the Nystrom approximation: with scal[0] = tr A,
+// scal[1] <- <Winv, C^T C>_F = tr(Winv C^T C) and scal[2] <- (2/l) max(scal[0] - scal[1], 0)
+hipError_t launch_lambda0_est(hipStream_t st, const double* Winv, const double* CtC, int64_t s, double l,
+                              double* scal);
 // In-place inverse of SPD M (s x s) by Gauss-Jordan sweeps, shifted by
 // mu = shift_rel * trace / s; tmp: s*s doubles; status: device int (0 ok, 1 not PD).
 // Result lands in M.
@@ -127,6 +151,13 @@ int gemm_split_default(int64_t rows, int64_t cols, int64_t k, msp_dtype a_t, boo
 hipError_t tune_block_sweep(hipStream_t st, const void* A, msp_dtype a_t, bool fp64_arith, int64_t rows,
                             int64_t cols, int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t k,
                             double* scratch, size_t scratch_doubles, int* nseg_out);
+// autotuner of the sparse sketch (msp_tune.hip): rows of A per block, timed for every
+// admissible value on this matrix (Y is overwritten) and cached per shape;
+// sketch_rows_choice returns the cached value or 0 (built-in rule)
+hipError_t tune_sketch_apply(hipStream_t st, const void* A, msp_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                             int64_t s, int32_t gamma, const TileLists& L, void* Y, msp_dtype y_t, int64_t ldy,
+                             int* rows_out);
+int sketch_rows_choice(msp_dtype a_t, int64_t m, int64_t n, int64_t lda, int64_t s, int32_t gamma);
 // Y[:, j] = M X[:, j] for an FP64 row-major M (ld = cols) with few rows: the same
 // matrix-core product, its reduction range cut into segments of at least min_seg columns
 // until about 2048 wavefronts run (scratch of at least gemm_split_doubles(rows, k)
@@ -339,6 +370,42 @@ hipError_t l2x_step(hipStream_t st, const L2xArgs& a, int par, int first);
 hipError_t l2x_publish(hipStream_t st, const L2xArgs& a, int par);
 
 // ---------------------------------------------------------------------------------
+// Inner iterations with an explicit operator H (+ sigma I) and preconditioner Minv by
+// direct products, two kernels per step (k_l2f.hip): the level-3 solves of the general
+// path. The state after l2_init (y = 0, r_0, z_0 = Minv r_0, p_0 = z_0, S.rz, S.done,
+// S.bnorm, S.iters = 0) is the input: r[0] = that r, p[0] = that p; r[1] and p[1] alternate
+// with them by step parity. The solution accumulates in y.
+// ---------------------------------------------------------------------------------
+constexpr int kL2fMaxK = 16;
+constexpr int kL2fRows = 8;
+struct L2fArgs {
+  int s, k, nb;
+  const double* H;
+  const double* Minv;
+  double sigma;
+  FcgState S;
+  double *y, *z, *q;
+  double *r[2], *p[2];
+  double *rz[2];
+  double* alpha;
+  double* ppart;   // [nb][k]     <p, q> partials
+  double* dpart;   // [nb][k][3]  <z, r_new>, <z, r_old>, |r_new|^2 partials
+  int32_t *done[2], *iters[2];
+  int32_t* brk;
+  double tol;
+  int max_iter;
+  int32_t* mirror;  // [2] host-mapped: active columns, largest iteration count
+};
+int l2f_blocks(int64_t s);
+// carves p[1], rz, alpha, the partials and the int state; the caller sets the rest
+L2fArgs l2f_carve(WsCarver& w, int64_t s, int64_t k);
+// step t: decision on the previous step (fresh = 1 for t = 0: the l2_init state), p_t,
+// q_t = (H + sigma I) p_t and <p_t, q_t> partials; publishes the host mirror
+hipError_t l2f_op(hipStream_t st, const L2fArgs& a, int t, int fresh);
+// step t: alpha_t, y, r_{t+1}, z_{t+1} = Minv r_{t+1} and the dot partials
+hipError_t l2f_prec(hipStream_t st, const L2fArgs& a, int t);
+
+// ---------------------------------------------------------------------------------
 // The preconditioner handle
 // ---------------------------------------------------------------------------------
 struct msp_precond {
@@ -351,6 +418,7 @@ struct msp_precond {
   msp_dtype y_t;
   int64_t ldy;
   double lam, lam0, lt;
+  double trace_a = 0.0, trace_nys = 0.0;  // lam0 estimated: tr A and tr(W^+ C^T C)
   double shift_rel;
   // device data carved from the nystrom workspace
   double* Wm;         // PSD: W = S C (symmetrised)

@@ -73,14 +73,20 @@ def test_nystrom_validation():
     h = ctypes.c_void_p()
     dummy = ctypes.c_void_p(256)
     # lam + lam0 must be > 0
-    assert L.msp_nystrom(None, 0, 100, 100, 16, 8, dummy, dummy, dummy, 0, 16, 0.0, 0.0, 64, 8, 3, dummy,
-                         1 << 30, ctypes.byref(h)) == 1
+    assert L.msp_nystrom(None, 0, 100, 100, 16, 8, dummy, dummy, dummy, 0, 16, None, 0, 0, 0.0, 0.0, 64, 8, 3,
+                         dummy, 1 << 30, ctypes.byref(h)) == 1
     # NaN lambda
-    assert L.msp_nystrom(None, 0, 100, 100, 16, 8, dummy, dummy, dummy, 0, 16, float("nan"), 0.0, 64, 8, 3, dummy,
-                         1 << 30, ctypes.byref(h)) == 5
+    assert L.msp_nystrom(None, 0, 100, 100, 16, 8, dummy, dummy, dummy, 0, 16, None, 0, 0, float("nan"), 0.0, 64, 8,
+                         3, dummy, 1 << 30, ctypes.byref(h)) == 5
     # PSD needs a square system
-    assert L.msp_nystrom(None, 0, 90, 100, 16, 8, dummy, dummy, dummy, 0, 16, 1.0, 0.0, 64, 8, 3, dummy,
+    assert L.msp_nystrom(None, 0, 90, 100, 16, 8, dummy, dummy, dummy, 0, 16, None, 0, 0, 1.0, 0.0, 64, 8, 3, dummy,
                          1 << 30, ctypes.byref(h)) == 1
+    # the lam0 estimator (lambda0 < 0) needs A, and only PSD handles have it
+    assert L.msp_nystrom(None, 0, 100, 100, 16, 8, dummy, dummy, dummy, 0, 16, None, 0, 0, 1.0, -1.0, 64, 8, 3,
+                         dummy, 1 << 30, ctypes.byref(h)) == 1
+    assert b"needs A" in L.msp_last_error()
+    assert L.msp_nystrom(None, 1, 100, 100, 16, 8, dummy, dummy, dummy, 0, 16, dummy, 0, 100, 1.0, -1.0, 64, 8, 3,
+                         dummy, 1 << 30, ctypes.byref(h)) == 7
 
 
 def test_solve_rejects_null_handle():

@@ -8,7 +8,9 @@ Every system must report a relative residual <= 1e-8. Three sampled systems (the
 the largest and one in between) are regenerated on the host and checked one by one: the
 residuals of X and of dB = (A + lam I)^{-1} (2 X) recomputed on the host (<= 1e-8), their
 distance to dense FP64 solves on the F32 matrix within what that residual allows
-(|x - x*| <= |r| / lam, since A is PSD), and dlam = -<dB, X>.
+(|x - x*| <= |r| / lam, since A is PSD), and dlam = -<dB, X>. The same three systems (their F32
+matrices held in FP64) then go through the FP64 batched path in one launch to a relative
+residual of 1e-11, and each column of X must lie within 1e-7 |x*| of the dense FP64 solution.
 """
 import numpy as np
 import pytest
@@ -85,5 +87,30 @@ def test_full_size_batched_forward_and_adjoint():
             assert np.linalg.norm(db[q] - want[q]) <= 1.01 * bound + 1e-10 * np.linalg.norm(want[q]), (j, q)
         # dlam = -<dB, X> over the block
         assert dlams[j] == pytest.approx(-float(np.sum(db * x)), rel=1e-9)
-    for P, *_ in systems:
+    # FP64 parity of x itself: the three sampled systems (their F32 matrices held exactly in
+    # FP64, sketched with the same seeds) through the FP64 batched path in one launch,
+    # driven to a relative residual of 1e-11; every column within 1e-7 |x*| of the dense
+    # FP64 solution
+    picks = [int(order[0]), int(order[count // 2]), int(order[-1])]
+    say(f"case batched x parity at tol 1e-11 (FP64 path): systems {picks}")
+    sub = []
+    for j in picks:
+        P32, A32, _, Bt = systems[j]
+        A64 = A32.double()
+        rows, signs, Y = msp.sketch(A64, P32.s, w.gamma, w.seed_s + 97 * j)
+        sub.append((msp.Precond("psd", rows, signs, Y, w.lam, P32.lam0, P32.phi, w.phi_gamma,
+                                w.seed_s + 97 * j + 8), A64, None, Bt))
+    # 1e-11: the FP64 residual of these systems bottoms out near 1e-12 (eps |A| |x| / |b|)
+    Xt, tinfos = msp.solve_batched(sub, tol=1e-11)
+    for idx, j in enumerate(picks):
+        say(tinfos[idx])
+        assert tinfos[idx]["status"] == "MSP_OK", (j, tinfos[idx])
+        n = int(sizes[j])
+        a, b = W.batched_rbf_system(j, n, float(ls[j]), dim, nrhs, w.config_id)
+        xs = dense.solve_psd(a.astype(np.float64), b.T, w.lam).T
+        x = Xt[idx].cpu().numpy()
+        err = max(np.linalg.norm(x[q] - xs[q]) / np.linalg.norm(xs[q]) for q in range(nrhs))
+        say(f"system {j} n={n}: max_q |x - x*| / |x*| = {err:.3e}")
+        assert err <= 1e-7
+    for P, *_ in systems + sub:
         P.close()

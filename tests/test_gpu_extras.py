@@ -208,3 +208,83 @@ def test_effective_dimension_matches_oracle():
     assert est == pytest.approx(est_o, rel=1e-9)
     d = dense.effective_dimension(eigs, lam)
     assert abs(est - d) < 4 * math.sqrt(2.0 * np.sum((eigs / (eigs + lam)) ** 2) / N)
+
+
+def test_gaussian_probes_match_oracle_generator():
+    # the integer stream is the same on both sides; the Box-Muller transform (log, sqrt,
+    # cos in FP64) agrees to a few ulp
+    from oracle import rng
+    say("case gaussian probes n=3001 N=17")
+    n, N, seed = 3001, 17, 424242
+    G = msp.gaussian_probes(n, N, seed).cpu().numpy()
+    want = rng.gaussian_probes(seed, n, N)
+    assert np.all(np.abs(G - want) <= 1e-14 * np.maximum(1.0, np.abs(want)))
+
+
+def test_schatten_generates_probes_from_a_seed():
+    # G = NULL: the driver draws the probes itself; the same estimate as passing them in
+    say("case schatten-1 with generated probes n=200 N=16")
+    n, s, N, seed = 200, 32, 16, 77
+    a, sig, _ = W.schatten_psd(n, config_id=201)
+    lam0 = omsp.paper_lambda0(sig ** 2, s // 2)
+    A = torch.from_numpy(a).to(DEV)
+    rows, signs, Y = msp.sketch(A, s, 8, 9)
+    P = msp.Precond("general", rows, signs, Y, 1.0, lam0, 4 * s, 8, 10)
+    u_lo, u_hi = trace.default_range(1.0, n, eps_q=1e-2)
+    kw = dict(p=1.0, h=2.0, u_lo=u_lo, u_hi=u_hi, tol=1e-8, inner_tol=1e-10, level3_tol=1e-10)
+    est1, se1, _ = msp.schatten(P, A, None, nprobes=N, probe_seed=seed, **kw)
+    est2, se2, _ = msp.schatten(P, A, msp.gaussian_probes(n, N, seed), **kw)
+    assert est1 == est2 and se1 == se2
+
+
+def test_schatten_descending_nodes_match_oracle():
+    # u_lo NaN: nodes from u_hi down, the lower tail replaced by |g|^2 once its bound is
+    # below 1e-4 of the estimate; the same nodes, stop and estimate as the oracle's
+    say("case schatten-1 descending nodes n=200 N=16")
+    n, s, N, h = 200, 32, 16, 1.5
+    a, sig, _ = W.schatten_psd(n, config_id=203)
+    g = W.gaussian((N, n), 203)
+    lam0 = omsp.paper_lambda0(sig ** 2, s // 2)
+    A = torch.from_numpy(a).to(DEV)
+    rows, signs, Y = msp.sketch(A, s, 8, 27)
+    P = msp.Precond("general", rows, signs, Y, 1.0, lam0, 4 * s, 8, 28)
+    u_hi = trace.upper_end(1.0, 1.0)
+    est, se, info = msp.schatten(P, A, torch.from_numpy(g).to(DEV), p=1.0, h=h, u_hi=u_hi, tol=1e-10,
+                                 inner_tol=1e-12, level3_tol=1e-12)
+    assert info["code"] == "MSP_OK", info
+    ridge = lambda t, G: np.linalg.solve(a.T @ a + t * np.eye(n), G)
+    est_o, se_o, _, used, bound = trace.schatten_descending(a, g.T, 1.0, h, u_hi, ridge)
+    say(est, se, est_o, se_o, info["trace_nodes"], used, bound)
+    assert info["trace_nodes"] == used
+    assert est == pytest.approx(est_o, rel=1e-6)
+    assert se == pytest.approx(se_o, rel=1e-4)
+    exact = dense.schatten_p(sig, 1.0)
+    assert abs(est - exact) < 4 * math.sqrt(2.0 * np.sum(sig ** 2) / N) + 2e-4 * exact
+
+
+def test_orlicz_matches_oracle():
+    # g(s) = s + 0.5 s^1.5: both Schatten sums from one descent, then the root of
+    # sum_q c_q r^{-p_q} S_q = 1, against the oracle on the same probes
+    from scipy.optimize import brentq
+    say("case orlicz n=200 N=16")
+    n, s, N, h = 200, 32, 16, 1.5
+    a, sig, _ = W.schatten_psd(n, config_id=204)
+    g = W.gaussian((N, n), 204)
+    lam0 = omsp.paper_lambda0(sig ** 2, s // 2)
+    A = torch.from_numpy(a).to(DEV)
+    rows, signs, Y = msp.sketch(A, s, 8, 37)
+    P = msp.Precond("general", rows, signs, Y, 1.0, lam0, 4 * s, 8, 38)
+    coefs, powers = [1.0, 0.5], [1.0, 1.5]
+    u_hi = trace.upper_end(1.0, 1.5)
+    r, se, sums, info = msp.orlicz(P, A, torch.from_numpy(g).to(DEV), coefs, powers, h=h, u_hi=u_hi, tol=1e-10,
+                                   inner_tol=1e-12, level3_tol=1e-12)
+    assert info["code"] == "MSP_OK", info
+    ridge = lambda t, G: np.linalg.solve(a.T @ a + t * np.eye(n), G)
+    r_o, se_o, sums_o, used = trace.orlicz_estimate(a, g.T, coefs, powers, h, u_hi, ridge)
+    say(r, se, sums, r_o, se_o, list(sums_o), info["trace_nodes"], used)
+    assert info["trace_nodes"] == used
+    assert r == pytest.approx(r_o, rel=1e-6)
+    assert np.allclose(sums, sums_o, rtol=1e-6)
+    assert se == pytest.approx(se_o, rel=1e-4)
+    want = brentq(lambda x: float(np.sum(sig / x + 0.5 * (sig / x) ** 1.5)) - 1.0, 1e-3, 1e6, xtol=1e-14)
+    assert abs(r - want) < 4 * se + 2e-4 * want

@@ -185,12 +185,45 @@ def test_general_graph_replayed_level3_steps_match_eager():
         assert info["level3_iters"] == out[0][1]["level3_iters"]
 
 
-@pytest.mark.parametrize("form", [1, 2])
-def test_refinement_stops_on_a_stall(form):
-    # kappa(A) ~ 1e6 (so kappa(A)^4 is far beyond FP64) with an FP32 copy inside MSP: the
+@pytest.mark.parametrize("n,s,nrhs", [(400, 32, 1), (1300, 300, 9), (1300, 300, 16)])
+def test_two_kernel_level3_steps_match_the_generic_step(n, s, nrhs):
+    # the level-3 solves as two kernels per step (direct FP64 row products over the formed
+    # A~^T A~ and M3^{-1}) against the generic step kernels: the same iteration, so both
+    # converge to the same solution with level-3 counts that differ only by rounding;
+    # s = 300 spans two reduction chunks and ends in a partial block of rows
+    say(f"case two-kernel level-3 steps n={n} s={s} nrhs={nrhs}")
+    a, sv, _, _ = W.general_outlier(n, 12, config_id=109, big=(1e2, 1e4))
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    bm = W.gaussian((nrhs, n), 109)
+    A, P = _gen(a, 0.0, lam0, s)
+    B = torch.from_numpy(bm if nrhs > 1 else bm[0]).to(DEV)
+    got = {}
+    for l3k in (2, 0, 2):
+        X, info = msp.solve(P, A, B, tol=1e-10, inner_tol=1e-12, level3_tol=1e-12, level3_kernels=l3k)
+        say(l3k, info)
+        assert info["status"] == "MSP_OK", info
+        x = X.cpu().numpy().reshape(nrhs, n)
+        for j in range(nrhs):
+            assert np.linalg.norm(a @ x[j] - bm[j]) <= 1e-10 * np.linalg.norm(bm[j])
+        if l3k in got:  # deterministic: the repeated two-kernel solve gives the same bits
+            assert np.array_equal(x, got[l3k][0])
+        got[l3k] = (x, info)
+    x2, i2 = got[2]
+    x0, i0 = got[0]
+    xs = np.linalg.solve(a, bm.T).T
+    for j in range(nrhs):
+        assert np.linalg.norm(x2[j] - xs[j]) <= 1e-7 * np.linalg.norm(xs[j])
+    assert abs(i2["level3_iters"] - i0["level3_iters"]) <= 0.05 * i0["level3_iters"] + 4
+    assert abs(i2["outer_iters"] - i0["outer_iters"]) <= 2
+
+
+def test_refinement_stops_on_a_stall():
+    # kappa(A) ~ 1e6 (so kappa(A)^4 is far beyond FP64) with an FP32 copy inside MSP and the
+    # one-level form, whose explicit level-2 matrix B^T B loses the small directions: the
     # refinement either converges or stops with the best iterate within a few steps (a
-    # stall is two steps that fail to halve the residual; one tightening of the inner
-    # tolerance for the multi-level forms, none for the one-level form)
+    # stall is two steps that fail to halve the residual; the one-level form has no inner
+    # level to tighten, so it stops at the first stall)
+    form = 2
     say(f"case general refinement stall n=512 level2_form={form}")
     n, s = 512, 64
     a, sv, _, _ = W.general_outlier(n, 16, config_id=108)
@@ -200,17 +233,22 @@ def test_refinement_stops_on_a_stall(form):
     A32 = A.float()
     rows, signs, Y = msp.sketch(A32, s, 8, 41)
     P = msp.Precond("general", rows, signs, Y, 0.0, lam0, 4 * s, 8, 43)
-    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), A_lo=A32, refine=1, tol=1e-12, level2_form=form,
+    tol = 1e-11
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), A_lo=A32, refine=1, tol=tol, level2_form=form,
                         max_outer=20000, max_refine=30)
     say(info)
     assert info["code"] in ("MSP_OK", "MSP_ERR_NO_CONVERGENCE"), info
     assert info["refine_steps"] <= 12, info
     x = X.cpu().numpy()
-    host = np.linalg.norm(b - a @ x) / np.linalg.norm(b)
+    bn = np.linalg.norm(b)
+    host = np.linalg.norm(b - a @ x) / bn
+    # the two FP64 residuals differ by rounding: n eps (|A| |x| + |b|) relative to |b|
+    floor = n * np.finfo(np.float64).eps * np.linalg.norm(np.abs(a) @ np.abs(x) + np.abs(b)) / bn
+    say(f"host {host:.3e} library {info['rel_residual_max']:.3e} rounding floor {floor:.1e}")
     assert np.isfinite(host) and host < 1.0
-    assert abs(info["rel_residual_max"] - host) <= 1e-8 * host + 1e-15
+    assert abs(info["rel_residual_max"] - host) <= 1e-8 * host + floor
     if info["code"] == "MSP_OK":
-        assert host <= 1e-12
+        assert host <= tol + floor
 
 
 def test_refinement_level1_budget_across_steps():

@@ -3,8 +3,9 @@ one right-hand side), in the launch configuration the benchmark times.
 
 At this size the oracle checks sampled outputs one by one (rows of Y = A S^T), the whole
 integer sketch bit for bit, the s x s factors, the FP64 residual of the returned solution
-recomputed on the host from the same matrix, and the level-1 iteration count of the
-oracle's own two-level solve on the same sketches.
+recomputed on the host from the same matrix, the level-1 iteration count of the oracle's
+own two-level solve on the same sketches, and the solution itself against the oracle's
+dense x* (stored in tests/golden by make_rbf_xstar.py) at a relative residual of 1e-12.
 """
 import json
 import os
@@ -96,4 +97,38 @@ def test_full_size_solve_residual_and_iterations(rbf):
     # ||(A + lam I)^{-1}|| <= 1/lam
     xo = res.x
     assert np.linalg.norm(x - xo) <= 2 * w.tol * np.linalg.norm(b) / w.lam
+    xs = _xstar(rbf)
+    say(f"at tol {w.tol}: |x - x*| / |x*| = {np.linalg.norm(x - xs) / np.linalg.norm(xs):.3e}")
+    P.close()
+
+
+def _xstar(rbf):
+    """x* = (A + lam I)^{-1} b of the oracle's dense solve, stored by
+    tests/golden/make_rbf_xstar.py, checked against the regenerated matrix."""
+    w, lam0, a, b, A = rbf
+    xs = np.load(os.path.join(GOLDEN, f"rbf_gp_n{w.n}_xstar.npy"))
+    assert xs.shape == (w.n,)
+    assert dense.rel_residual_psd(a, xs, b, w.lam) <= 1e-12
+    return xs
+
+
+def test_full_size_solution_matches_the_oracle_x(rbf):
+    # the FP64 path of the timed configuration driven to a relative residual of 1e-12
+    # (kappa(A + lam I) ~ 7e4, so 1e-8 alone does not bound the forward error by 1e-7):
+    # x within 1e-7 |x*| of the oracle's dense solution
+    w, lam0, a, b, A = rbf
+    xs = _xstar(rbf)
+    say(f"case full-size x parity n={w.n} tol=1e-12")
+    rows, signs, Y = msp.sketch(A, w.s, w.gamma, w.seed_s)
+    P = msp.Precond("psd", rows, signs, Y, w.lam, lam0, w.phi, w.phi_gamma, w.seed_phi)
+    X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), tol=1e-12, inner_tol=1e-10)
+    say(info)
+    # at 1e-12 the recomputed FP64 residual is near its rounding floor (eps |A| |x| / |b| ~ 3e-12
+    # at worst): a stop just above the target still has to meet the x bound below
+    assert info["status"] == "MSP_OK" or (info["status"] == "MSP_ERR_NO_CONVERGENCE"
+                                          and info["rel_residual_max"] <= 3e-12), info
+    x = X.cpu().numpy()
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    say(f"|x - x*| / |x*| = {err:.3e}, host residual {dense.rel_residual_psd(a, x, b, w.lam):.3e}")
+    assert err <= 1e-7
     P.close()

@@ -320,3 +320,48 @@ def test_graph_replayed_inner_steps_match_eager():
         assert np.array_equal(x, runs[0][0])
         assert info["outer_iters"] == runs[0][1]["outer_iters"]
         assert info["inner_iters"] == runs[0][1]["inner_iters"]
+
+
+@pytest.mark.parametrize("case", ["outlier", "rbf", "bf16"])
+def test_lambda0_estimator_matches_oracle(case):
+    # lambda0 < 0: the GPU estimates lam0 = (2/l) max(tr A - tr(W^+ C^T C), 0) from the
+    # handle's sketch and A's diagonal; the oracle's estimator on the same sketch
+    say(f"case lambda0 estimator {case}")
+    if case == "outlier":
+        n, s, lam = 1024, 64, 1e-3
+        a, eigs, _ = W.psd_outlier(n, 32, config_id=0)
+    else:
+        n, s, lam = 2048, 128, 1e-2
+        a = W.rbf_matrix(W.rbf_points(n, 8, 11))
+    A = torch.from_numpy(a).to(DEV)
+    A_sk = A.to(torch.bfloat16) if case == "bf16" else A
+    rows, signs, Y = msp.sketch(A_sk, s, 8, 31)
+    P = msp.Precond("psd", rows, signs, Y, lam, None, 4 * s, 8, 32, A=A_sk)
+    a_sk = A_sk.double().cpu().numpy()
+    r_o, s_o = rng.sketch_indices(31, n, s, 8)
+    c = osk.right_sketch(a_sk, r_o, s_o, s)
+    w = osk.left_sketch(r_o, s_o, s, c)
+    want = omsp.lambda0_estimate(a_sk, c, w, s // 2)
+    scale = 2.0 / (s // 2) * float(np.trace(a_sk))
+    tol = (1e-9 if case != "bf16" else 1e-5) * scale  # BF16: the FP32 sketch's rounding
+    say(f"gpu lam0 {P.lam0:.12e} oracle {want:.12e}")
+    assert abs(P.lam0 - want) <= tol
+    if case == "outlier":
+        b = W.gaussian(n, 0)
+        X, info = msp.solve(P, A, torch.from_numpy(b).to(DEV), tol=1e-10, inner_tol=1e-12)
+        assert info["status"] == "MSP_OK", info
+        assert dense.rel_residual_psd(a, X.cpu().numpy(), b, lam) <= 1e-10
+
+
+def test_lambda0_estimator_low_rank_needs_lambda():
+    # rank(A) <= s: the estimate is 0; with lam = 0 there is no regulariser left
+    say("case lambda0 estimator low rank")
+    n, r, s = 300, 20, 32
+    g = np.random.default_rng(3).standard_normal((n, r))
+    A = torch.from_numpy(g @ g.T).to(DEV)
+    rows, signs, Y = msp.sketch(A, s, 8, 5)
+    P = msp.Precond("psd", rows, signs, Y, 1e-2, None, 4 * s, 8, 6, A=A)
+    assert P.lam0 == 0.0
+    with pytest.raises(msp.MspError) as e:
+        msp.Precond("psd", rows, signs, Y, 0.0, None, 4 * s, 8, 6, A=A)
+    assert e.value.status == "MSP_ERR_INVALID_ARG"

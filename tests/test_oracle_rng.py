@@ -60,3 +60,28 @@ def test_gamma_equal_s_is_a_permutation():
 def test_invalid_gamma():
     with pytest.raises(ValueError):
         rng.sketch_indices(1, 10, 4, 5)
+
+
+def test_probe_uniforms_are_the_counter_stream():
+    # the vectorised draw equals the plain definition, element by element
+    seed, n, N = 987654321, 7, 3
+    U1, U2 = rng.probe_uniforms(seed, n, N)
+    for j in range(N):
+        key = rng.stream_output(seed ^ rng.PROBE_DOMAIN, j + 1)
+        for i in range(n):
+            u1 = rng.stream_output(key, 2 * i + 1)
+            u2 = rng.stream_output(key, 2 * i + 2)
+            assert U1[j, i] == ((u1 >> 11) + 1) * 2.0 ** -53
+            assert U2[j, i] == (u2 >> 11) * 2.0 ** -53
+    assert U1.min() > 0.0 and U1.max() <= 1.0 and U2.min() >= 0.0 and U2.max() < 1.0
+
+
+def test_gaussian_probes_are_standard_normal():
+    # moments and the Kolmogorov-Smirnov distance of 200 000 draws against N(0, 1)
+    from scipy import stats
+    g = rng.gaussian_probes(2405, 2000, 100).ravel()
+    assert abs(g.mean()) < 5 / np.sqrt(g.size)
+    assert abs(g.var() - 1.0) < 5 * np.sqrt(2.0 / g.size)
+    assert stats.kstest(g, "norm").pvalue > 1e-3
+    # distinct seeds and the sketch domain give different draws
+    assert not np.array_equal(rng.gaussian_probes(1, 50, 2), rng.gaussian_probes(2, 50, 2))
