@@ -11,12 +11,12 @@
  *   - Every call enqueues its device work on `stream` (hipStream_t passed as void*);
  *     calls that fill [host] outputs synchronise the stream before returning.
  *   - The caller owns all device memory, including the workspaces whose sizes the
- *     *_workspace queries return; the library never allocates device memory. On the
- *     host, msp_nystrom allocates one 4 KiB page of pinned, device-mapped memory per
- *     handle (the mirror through which solves read convergence flags), solves with
- *     profile != 0 create HIP events (kept in the handle), and solves with use_graph != 0
- *     create a capture stream and graphs (freed at return); msp_precond_destroy frees
- *     the rest.
+ *     *_workspace queries return; the library never allocates device memory, apart
+ *     from the fixed static scratch of msp_sketch_noalloc. On the host, msp_nystrom
+ *     allocates one 4 KiB page of pinned, device-mapped memory per handle (the mirror
+ *     through which solves read convergence flags), solves with profile != 0 create HIP
+ *     events (kept in the handle), and solves with use_graph != 0 create a capture stream
+ *     and graphs (freed at return); msp_precond_destroy frees the rest.
  *   - Errors: every call returns an msp_status; no call throws or aborts.
  *     Arguments are validated before any device work is enqueued. msp_last_error()
  *     returns a thread-local message describing the last failure.
@@ -94,6 +94,24 @@ msp_status msp_sketch_autotune(void* stream, const void* A, msp_dtype a_t, int64
                                int64_t s, int32_t gamma, uint64_t seed, int32_t* S_rows, int8_t* S_signs,
                                void* Y, msp_dtype y_t, int64_t ldy, void* ws, size_t ws_bytes,
                                int32_t* rows_per_block /*host*/);
+
+/* ---------------------------------------------------------------------------------
+ * msp_sketch_noalloc -- msp_sketch without a workspace, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation. Same arguments, kernels, results (bit for bit) and asynchrony as msp_sketch,
+ * minus ws / ws_bytes; calls no allocating routine and no memset.
+ *
+ * The sketch's scratch (bucket lists and sort counts, msp_sketch_workspace bytes) lives in
+ * a static device array of MSP_NOALLOC_SCRATCH_BYTES that each GPU the library runs on
+ * holds until the process ends; its device address is looked up on the first call on
+ * each device. A sketch whose msp_sketch_workspace exceeds that size returns
+ * MSP_ERR_WORKSPACE before any device work. Every call on one GPU shares the array, so
+ * calls that overlap on one GPU (different streams or threads without ordering) race.
+ * ------------------------------------------------------------------------------ */
+#define MSP_NOALLOC_SCRATCH_BYTES (16u << 20)
+msp_status msp_sketch_noalloc(void* stream, const void* A, msp_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                              int64_t s, int32_t gamma, uint64_t seed, int32_t* S_rows, int8_t* S_signs, void* Y,
+                              msp_dtype y_t, int64_t ldy);
 
 /* ---------------------------------------------------------------------------------
  * msp_nystrom -- the Nystrom factor and the inner-level preconditioners.

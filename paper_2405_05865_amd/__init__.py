@@ -19,7 +19,7 @@ import torch
 from . import _binding as B
 from ._binding import MspError, SolveInfo, SolveOpts  # noqa: F401
 
-__all__ = ["sketch", "Precond", "nystrom", "solve", "solve_batched", "solve_batched_backward", "solve_backward", "schatten", "effective_dimension", "gaussian_probes",
+__all__ = ["sketch", "sketch_noalloc", "Precond", "nystrom", "solve", "solve_batched", "solve_batched_backward", "solve_backward", "schatten", "effective_dimension", "gaussian_probes",
            "MSPSolve", "msp_solve", "library", "MspError", "SolveOpts"]
 
 _DT = {torch.float64: B.MSP_F64, torch.float32: B.MSP_F32, torch.bfloat16: B.MSP_BF16}
@@ -136,6 +136,35 @@ def sketch(A: torch.Tensor, s: int, gamma: int, seed: int, y_dtype: torch.dtype 
     B.check(L.msp_sketch(_stream(A.device), A.data_ptr(), _code(A), m, n, A.stride(0), s, gamma,
                          ctypes.c_uint64(seed & (2 ** 64 - 1)), rows.data_ptr(), signs.data_ptr(), Y.data_ptr(),
                          _code(Y), Y.stride(0), ws.data_ptr(), ws.numel()))
+    return rows, signs, Y
+
+
+def sketch_noalloc(A: torch.Tensor, s: int, gamma: int, seed: int, out=None, y_dtype: torch.dtype | None = None):
+    """msp_sketch_noalloc: the same S and Y = A S^T as sketch(), with the library's static
+    device scratch instead of a workspace. ``out`` = (S_rows, S_signs, Y) preallocated by
+    the caller (then nothing is allocated here either); returns that triple."""
+    L = library()
+    _rowmajor(A, "A")
+    m, n = A.shape
+    if out is None:
+        if y_dtype is None:
+            y_dtype = torch.float64 if A.dtype == torch.float64 else torch.float32
+        out = (torch.empty((n, gamma), dtype=torch.int32, device=A.device),
+               torch.empty((n, gamma), dtype=torch.int8, device=A.device),
+               torch.empty((m, s), dtype=y_dtype, device=A.device))
+    rows, signs, Y = out
+    if rows.dtype != torch.int32 or signs.dtype != torch.int8 or tuple(rows.shape) != (n, gamma) \
+            or tuple(signs.shape) != (n, gamma) or not rows.is_contiguous() or not signs.is_contiguous():
+        raise ValueError("S_rows / S_signs must be contiguous int32 / int8 tensors of shape (n, gamma)")
+    _rowmajor(Y, "Y")
+    if Y.shape[0] != m or Y.shape[1] != s:
+        raise ValueError(f"Y must be ({m}, {s})")
+    for t in (rows, signs, Y):
+        if t.device != A.device:
+            raise ValueError("outputs must live on A's device")
+    B.check(L.msp_sketch_noalloc(_stream(A.device), A.data_ptr(), _code(A), m, n, A.stride(0), s, gamma,
+                                 ctypes.c_uint64(seed & (2 ** 64 - 1)), rows.data_ptr(), signs.data_ptr(),
+                                 Y.data_ptr(), _code(Y), Y.stride(0)))
     return rows, signs, Y
 
 

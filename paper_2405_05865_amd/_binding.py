@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmsp.so")
 MSP_F64, MSP_F32, MSP_BF16 = 0, 1, 2
 MSP_SYM_PSD, MSP_GENERAL = 0, 1
 MSP_TRACE_SCHATTEN_P, MSP_TRACE_EFFDIM = 0, 1
+NOALLOC_SCRATCH_BYTES = 16 << 20  # MSP_NOALLOC_SCRATCH_BYTES of include/msp.h
 
 STATUS = {
     0: "MSP_OK",
@@ -34,7 +35,7 @@ EXPORTS = (
     "msp_solve_batched_workspace", "msp_solve_batched", "msp_solve_batched_backward_workspace",
     "msp_solve_batched_backward", "msp_solve_backward",
     "msp_schatten_workspace", "msp_schatten", "msp_orlicz", "msp_gaussian_probes", "msp_left_sketch_workspace", "msp_left_sketch",
-    "msp_lstsq_workspace", "msp_lstsq", "msp_last_error", "msp_version",
+    "msp_lstsq_workspace", "msp_lstsq", "msp_sketch_noalloc", "msp_last_error", "msp_version",
 )
 
 
@@ -155,6 +156,7 @@ def load(path: str | None = None):
                              ctypes.c_size_t]
     L.msp_sketch_autotune.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, I32, U64, P, P, P, ctypes.c_int, I64, P,
                                       ctypes.c_size_t, ctypes.POINTER(I32)]
+    L.msp_sketch_noalloc.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, I32, U64, P, P, P, ctypes.c_int, I64]
     L.msp_nystrom_workspace.argtypes = [ctypes.c_int, I64, I64, I64, I64, I32, SZ]
     L.msp_nystrom.argtypes = [P, ctypes.c_int, I64, I64, I64, I32, P, P, P, ctypes.c_int, I64, P, ctypes.c_int, I64,
                               D, D, I64, I32, U64, P, ctypes.c_size_t, ctypes.POINTER(P)]

@@ -134,3 +134,15 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_noalloc_scratch_size_and_oversized_request():
+    # the binding's copy of MSP_NOALLOC_SCRATCH_BYTES matches the header, and a sketch whose
+    # scratch exceeds it is rejected on the host before any device work
+    m = re.search(r"#define MSP_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", open(HDR).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == B.NOALLOC_SCRATCH_BYTES
+    L = msp.library()
+    n = 1 << 22
+    code = L.msp_sketch_noalloc(None, None, B.MSP_F32, n, n, n, 2048, 8, 1, None, None, None, B.MSP_F32, 2048)
+    assert B.STATUS[code] == "MSP_ERR_WORKSPACE"
+    assert b"static scratch" in L.msp_last_error()
