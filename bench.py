@@ -181,6 +181,8 @@ def main():
                     help="cap the level-1 iterations (counter runs over a few sweeps only)")
     ap.add_argument("--level3-tol", type=float, default=1e-10,
                     help="general workload: relative residual target of the level-3 solves")
+    ap.add_argument("--max-refine", type=int, default=None,
+                    help="batched: FP64 refinement step cap (library default 30; BF16 sweeps at lam = 1e-2 need more)")
     ap.add_argument("--level3-kernels", type=int, default=2, choices=[0, 2],
                     help="general: kernels per level-3 step (2: fused pair, 0: generic step)")
     ap.add_argument("--refine-inner-tol", type=float, default=1e-4,
@@ -694,7 +696,7 @@ def bench_batched(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         Xs, infos = msp.solve_batched([(P, q["A"], q["A_lo"], q["B"]) for P, q in zip(Ps, systems)], tol=w.tol,
-                                      refine=1, profile=1)
+                                      refine=1, profile=1, max_refine=args.max_refine)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         for P in Ps:
@@ -737,10 +739,11 @@ def bench_batched(args):
         sys_args = [(P, q["A"], q["A_lo"], q["B"]) for P, q in zip(Ps, systems)]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        Xs, finfos = msp.solve_batched(sys_args, tol=w.tol, refine=1)
+        Xs, finfos = msp.solve_batched(sys_args, tol=w.tol, refine=1, max_refine=args.max_refine)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        dBs, dls, _, binfos = msp.solve_batched_backward(sys_args, Xs, [2.0 * X for X in Xs], tol=w.tol, refine=1)
+        dBs, dls, _, binfos = msp.solve_batched_backward(sys_args, Xs, [2.0 * X for X in Xs], tol=w.tol, refine=1,
+                                                         max_refine=args.max_refine)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         for P in Ps:
@@ -792,7 +795,8 @@ def bench_batched(args):
         "config": {"workload": f"batched_rbf_{count}", "count": count, "nrhs": nrhs, "n_range": [512, 8192],
                    "sum_n2": float(np.sum(sizes.astype(np.float64) ** 2)), "s": "min(256, n/2)", "gamma": w.gamma,
                    "phi": "min(4s, n)", "lambda": w.lam, "lambda0_source": args.lambda0, "tol": w.tol,
-                   "matrix": "f32", "sweeps": args.lo, "refinement": "fp64 krylov"},
+                   "matrix": "f32", "sweeps": args.lo, "refinement": "fp64 krylov",
+                   "max_refine": args.max_refine},
         "setup_ms_per_step": round(1e3 * setup_t / args.steps, 2),
         "solve_ms_per_step": round(1e3 * solve_t / args.steps, 2),
         "a_sweep_bytes_per_step": a_bytes,

@@ -439,6 +439,27 @@ msp_status msp_orlicz(void* stream, msp_precond* P, const void* A_hi, msp_dtype 
                       double* sums /*host*/, msp_solve_info* info /*host*/);
 
 /* ---------------------------------------------------------------------------------
+ * msp_kyfan -- the Ky Fan k-norm ||A||_(k) = sum_{i<=k} sigma_i(A) (Section 3.2 names Ky Fan
+ * norms beside the Orlicz norms). A sum of the top k singular values needs the top of the
+ * spectrum itself, which ridge solves (A^T A + t I)^{-1} do not isolate, so it is taken from
+ * the top singular subspace: Z_0 = the b >= k Gaussian vectors msp_gaussian_probes draws from
+ * seed, Q_0 = orth(Z_0), Q_i = orth(A^T A Q_{i-1}) for i = 1..q, and the Rayleigh-Ritz values of
+ * A on Q_q (square roots of the eigenvalues of (A Q_q)^T (A Q_q)); orth(Z) = Z V Lambda^{-1/2}
+ * from the eigenpairs of Z^T Z, dropping directions with eigenvalue <= 1e-13 of the largest.
+ * Ritz values interlace, so the estimate is at most ||A||_(k) and converges to it; with
+ * rank(A) <= b one step is exact. 2q + 1 block products with A and q with A^T, FP64
+ * arithmetic; the b x b eigenproblems by cyclic Jacobi rotations in one workgroup.
+ *   A        m x n, F64 or F32, ld lda >= n
+ *   k, b, q  1 <= k <= b <= min(64, m, n), 0 <= q
+ *   estimate [host] out; sigma [host] out, may be NULL: the b Ritz values, decreasing
+ * Synchronises the stream before returning.
+ * ------------------------------------------------------------------------------ */
+msp_status msp_kyfan_workspace(int64_t m, int64_t n, int64_t b, size_t* bytes /*host*/);
+msp_status msp_kyfan(void* stream, const void* A, msp_dtype a_t, int64_t m, int64_t n, int64_t lda, int64_t k,
+                     int64_t b, int32_t q, uint64_t seed, void* ws, size_t ws_bytes, double* estimate /*host*/,
+                     double* sigma /*host*/);
+
+/* ---------------------------------------------------------------------------------
  * msp_gaussian_probes -- the Gaussian probe vectors of Hutchinson's estimator (Section
  * 3.2 draws them; the paper fixes no generator): Box-Muller (1958) over the counter-based
  * SplitMix64 stream of msp_sketch. Probe j has key k_j = fmix((seed ^ 0xD1B54A32D192ED03)

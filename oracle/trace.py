@@ -200,3 +200,38 @@ def orlicz_estimate(a, probes, coefs, powers, h, u_hi, ridge_solve, eps_q=1e-4, 
     dphi = float(np.sum(-powers * coefs * r ** (-powers - 1.0) * sums))
     se = float(vals.std(ddof=1) / math.sqrt(N) / abs(dphi)) if N > 1 else float("nan")
     return r, se, sums, used
+
+
+# ---------------------------------------------------------------------------------
+# Ky Fan norms (Section 3.2 names them beside the Orlicz norms)
+# ---------------------------------------------------------------------------------
+# ||A||_(k) = sum_{i<=k} sigma_i(A) needs the top of the spectrum itself, which ridge solves
+# (A^T A + t I)^{-1} do not isolate (every function of sigma they reach is smooth in log sigma
+# with a transition width that does not shrink). It is taken from the top singular subspace:
+# randomized subspace iteration on A^T A from b >= k Gaussian vectors, q steps, each
+# orthonormalised, then the Rayleigh-Ritz values of A on that subspace. Ritz values interlace
+# (each is at most the singular value of the same rank), so the estimate never exceeds
+# ||A||_(k) and converges to it; with rank(A) <= b one step is exact.
+def orthonormal_columns(z: np.ndarray, drop: float = 1e-13) -> np.ndarray:
+    """An orthonormal basis of range(z) (n x b) as z V Lambda^{-1/2} from the eigenpairs of
+    z^T z; directions with eigenvalue <= drop * max are left out (zero columns)."""
+    g = z.T @ z
+    lam, v = np.linalg.eigh(0.5 * (g + g.T))
+    keep = lam > drop * lam.max()
+    scale = np.zeros_like(lam)
+    scale[keep] = 1.0 / np.sqrt(lam[keep])
+    return (z @ v) * scale[None, :]
+
+
+def kyfan_subspace(a: np.ndarray, k: int, b: int, q: int, omega: np.ndarray):
+    """The Ky Fan k-norm estimate from q steps of subspace iteration started at omega
+    (n x b). Returns (estimate, the b Ritz singular values in decreasing order)."""
+    if not (1 <= k <= b):
+        raise ValueError("1 <= k <= b")
+    qm = orthonormal_columns(np.asarray(omega, dtype=np.float64))
+    for _ in range(q):
+        qm = orthonormal_columns(a.T @ (a @ qm))
+    t = a @ qm
+    lam = np.linalg.eigvalsh(t.T @ t)
+    sig = np.sqrt(np.clip(lam, 0.0, None))[::-1]
+    return float(sig[:k].sum()), sig

@@ -19,7 +19,7 @@ import torch
 from . import _binding as B
 from ._binding import MspError, SolveInfo, SolveOpts  # noqa: F401
 
-__all__ = ["sketch", "sketch_noalloc", "Precond", "nystrom", "solve", "solve_batched", "solve_batched_backward", "solve_backward", "schatten", "effective_dimension", "gaussian_probes",
+__all__ = ["sketch", "sketch_noalloc", "Precond", "nystrom", "solve", "solve_batched", "solve_batched_backward", "solve_backward", "schatten", "orlicz", "kyfan", "effective_dimension", "gaussian_probes",
            "MSPSolve", "msp_solve", "library", "MspError", "SolveOpts"]
 
 _DT = {torch.float64: B.MSP_F64, torch.float32: B.MSP_F32, torch.bfloat16: B.MSP_BF16}
@@ -482,6 +482,28 @@ def orlicz(P: Precond, A_hi, probes, coefs, powers, A_lo=None, h: float = 1.5, u
     d = info.as_dict()
     d["code"] = B.STATUS.get(code, code)
     return est.value, se.value, list(s_arr), d
+
+
+def kyfan(A: torch.Tensor, k: int, b: int | None = None, q: int = 10, seed: int = 0):
+    """Ky Fan k-norm sum_{i<=k} sigma_i(A) (msp_kyfan): b >= k vectors (default min(2k, 64)),
+    q steps of subspace iteration. Returns (estimate, the b Ritz values as a list)."""
+    L = library()
+    _rowmajor(A, "A")
+    if A.dtype not in (torch.float64, torch.float32):
+        raise ValueError("A must be float64 or float32")
+    if not A.is_cuda:
+        raise ValueError("A must be on the GPU")
+    m, n = A.shape
+    b = int(b) if b is not None else min(2 * int(k), 64, m, n)
+    need = B.size_out()
+    B.check(L.msp_kyfan_workspace(m, n, b, ctypes.byref(need)))
+    ws = _workspace(need.value, A.device)
+    est = ctypes.c_double()
+    sig = (ctypes.c_double * b)()
+    B.check(L.msp_kyfan(_stream(A.device), A.data_ptr(), _code(A), m, n, A.stride(0), int(k), b, int(q),
+                        ctypes.c_uint64(seed & (2 ** 64 - 1)), ws.data_ptr(), ws.numel(), ctypes.byref(est),
+                        ctypes.cast(sig, ctypes.c_void_p)))
+    return est.value, list(sig)
 
 
 def effective_dimension(P: Precond, A_hi, probes, lam: float, **opts):

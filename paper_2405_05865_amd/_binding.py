@@ -34,7 +34,8 @@ EXPORTS = (
     "msp_precond_set_lambda", "msp_precond_factors", "msp_solve_opts_default", "msp_solve_workspace", "msp_solve",
     "msp_solve_batched_workspace", "msp_solve_batched", "msp_solve_batched_backward_workspace",
     "msp_solve_batched_backward", "msp_solve_backward",
-    "msp_schatten_workspace", "msp_schatten", "msp_orlicz", "msp_gaussian_probes", "msp_left_sketch_workspace", "msp_left_sketch",
+    "msp_schatten_workspace", "msp_schatten", "msp_orlicz", "msp_kyfan_workspace", "msp_kyfan",
+    "msp_gaussian_probes", "msp_left_sketch_workspace", "msp_left_sketch",
     "msp_lstsq_workspace", "msp_lstsq", "msp_sketch_noalloc", "msp_last_error", "msp_version",
 )
 
@@ -187,6 +188,9 @@ def load(path: str | None = None):
     L.msp_orlicz.argtypes = [P, P, P, ctypes.c_int, P, ctypes.c_int, I64, P, P, I64, P, I64, I64, U64, D, D, D,
                              ctypes.POINTER(SolveOpts), P, ctypes.c_size_t, ctypes.POINTER(D), ctypes.POINTER(D), P,
                              ctypes.POINTER(SolveInfo)]
+    L.msp_kyfan_workspace.argtypes = [I64, I64, I64, SZ]
+    L.msp_kyfan.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, I64, I32, U64, P, ctypes.c_size_t,
+                            ctypes.POINTER(D), P]
     L.msp_gaussian_probes.argtypes = [P, I64, I64, U64, P, I64]
     L.msp_left_sketch_workspace.argtypes = [I64, I64, I32, SZ]
     L.msp_left_sketch.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, I32, U64, P, P, P, I64, P, ctypes.c_size_t]

@@ -990,6 +990,7 @@ struct Batch {
         __syncthreads();
         if (!any_active(R, c.k)) break;
         if (restarts >= MAX_RESTARTS || it >= c.P.max_refine) {
+          // capped after a failed confirmation: rel holds the recomputed residual
           if (w < c.k && lane == 0 && R->done[w] == 0) R->done[w] = 3;
           __syncthreads();
           break;
@@ -999,7 +1000,10 @@ struct Batch {
         continue;
       }
       if (it >= c.P.max_refine) {
-        if (w < c.k && lane == 0 && R->done[w] == 0) R->done[w] = 3;
+        if (w < c.k && lane == 0 && R->done[w] == 0) {
+          R->done[w] = 3;  // capped: report the recurrence residual it stopped at
+          R->rel[w] = R->bn[w] > 0.0 ? R->rn[w] / R->bn[w] : 0.0;
+        }
         __syncthreads();
         break;
       }
@@ -1025,7 +1029,10 @@ struct Batch {
           R->rn[w] = rn;
           if (brk || !(rn == rn)) R->done[w] = 2;
           else if (rn <= c.P.tol * R->bn[w]) R->done[w] = 1;
-          else if (itj >= c.P.max_refine) R->done[w] = 3;
+          else if (itj >= c.P.max_refine) {
+            R->done[w] = 3;
+            R->rel[w] = R->bn[w] > 0.0 ? rn / R->bn[w] : 0.0;
+          }
         }
       }
       ++it;

@@ -1,31 +1,38 @@
 // Inner flexible-PCG steps on a formed operator in two kernels per step: the level-3 solves
 // of Algorithm 5 with the s x s A~^T A~ (+ sigma I) and the s x s preconditioner M3^{-1},
-// for blocks of up to kL2fMaxK columns. Step t of the recurrence
+// for blocks of up to kL2fMaxK columns and s <= kL2fMaxS. Step t of the recurrence
 //   q_t = (H + sigma I) p_t,  alpha_t = <r_t, z_t> / <p_t, q_t>,  y += alpha_t p_t,
 //   r_{t+1} = r_t - alpha_t q_t,  z_{t+1} = Minv r_{t+1},
 //   beta_{t+1} = <z_{t+1}, r_{t+1} - r_t> / <r_t, z_t>,  p_{t+1} = z_{t+1} + beta_{t+1} p_t
 // runs as
 //   k_l2f_op    the decision on |r_t| and beta_t from the previous step's partials (every
-//               block sums them in the same order), p_t = z_t + beta_t p_{t-1} for the
-//               block's rows, q_t = (H + sigma I) p_t for the block's rows (each block forms
-//               the whole p_t it needs on the fly, staged in LDS by chunks), <p_t, q_t> partials;
-//   k_l2f_prec  alpha_t from those partials (again in every block), r_{t+1} formed on the fly
-//               the same way, y and r for the block's rows, z_{t+1} = Minv r_{t+1} for the
-//               block's rows, and the partials of <z, r_{t+1}>, <z, r_t> and |r_{t+1}|^2.
-// The same iteration as the six-kernel step (flexible PCG, Polak-Ribiere beta, the same
-// stop and breakdown rules), with the matrix products as plain FP64 row dots instead of
-// matrix-core block products: only the summation order differs. p and r alternate between
-// two buffers by step parity (a block reads the whole previous vector while others write
-// their rows of the next one); the per-column state is double-buffered the same way.
+//               block sums them in the same order), p_t = z_t + beta_t p_{t-1}, q_t for the
+//               block's rows and the <p_t, q_t> partials;
+//   k_l2f_prec  alpha_t from those partials (again in every block), y and r_{t+1} for the
+//               block's rows, z_{t+1} = Minv r_{t+1} for them and the partials of
+//               <z, r_{t+1}>, <z, r_t> and |r_{t+1}|^2.
+// The same iteration as the generic step (flexible PCG, Polak-Ribiere beta, the same stop and
+// breakdown rules) with the matrix products as plain FP64 row dots: only the summation order
+// differs. Both kernels are bound by latency, not bandwidth (the s x s operands stay in the
+// caches between steps), so each makes as few dependent round trips as it can: a block of
+// eight wavefronts owns eight rows (one each); the vector it multiplies (p_t, resp. r_{t+1},
+// formed on the fly from the two vectors that define it) is staged whole into LDS for eight
+// columns at a time, every thread issuing its loads in batches before storing any; the
+// partial sums of the previous kernel are reduced by whole wavefronts. p and r alternate
+// between two buffers by step parity (a block reads the whole previous vector while others
+// write their rows of the next one); the per-column state is double-buffered the same way.
 #include "msp_internal.h"
+
+#include <mutex>
 
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int NT = 256;
-constexpr int RB = kL2fRows;   // rows of the product per block
-constexpr int CH = 256;        // reduction chunk staged in LDS
-constexpr int KM = kL2fMaxK;   // columns handled per launch
+constexpr int NWV = kL2fRows;     // wavefronts per block, one row each
+constexpr int NT = NWV * WAVE;
+constexpr int KG = 8;             // columns per staging pass
+constexpr int KM = kL2fMaxK;      // columns per launch
+constexpr int BATCH = 8;          // staged elements per thread per batch of loads
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -33,72 +40,83 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// rows r0 .. r0 + RB of out = M x, x[j][c] = u[j][c] + coef_j * v[j][c] formed on the fly
-// (v may be null), for the live columns. Wavefront w takes rows r0 + 2w and r0 + 2w + 1;
-// lane l takes the reduction indices l + 64 i of each chunk. acc[2][KM] returned per lane
-// (not yet reduced over the wavefront).
-__device__ __forceinline__ void rows_product(const double* __restrict__ M, int s, int k, int r0,
-                                             const double* __restrict__ u, const double* __restrict__ v,
-                                             const double* coef, const int* live, double (*xs)[CH],
-                                             double (&acc)[2][KM]) {
-  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
-  const int rA = r0 + 2 * w, rB = rA + 1;
+// sum over b < nb of part[b * stride + e], by one wavefront in a fixed order (valid in
+// every lane)
+__device__ __forceinline__ double wave_parts(const double* part, int nb, int64_t stride, int e) {
+  const int lane = threadIdx.x % WAVE;
+  double t = 0.0;
+  for (int b = lane; b < nb; b += WAVE) t += part[(int64_t)b * stride + e];
+  return wave_sum(t);
+}
+
+// xs[jj * s + c] = u[j][c] + coef[j] v[j][c] (v null: u[j][c]) for the kg columns
+// j = j0 + jj, zero for finished columns; every thread issues BATCH loads of each vector
+// before storing any
+__device__ __forceinline__ void stage(const double* __restrict__ u, const double* __restrict__ v,
+                                      const double* coef, const int* live, int s, int j0, int kg, double* xs) {
+  const int total = kg * s;
+  for (int base = 0; base < total; base += NT * BATCH) {
+    double uv[BATCH], vv[BATCH];
 #pragma unroll
-  for (int j = 0; j < KM; ++j) acc[0][j] = acc[1][j] = 0.0;
-  for (int c0 = 0; c0 < s; c0 += CH) {
-    for (int idx = tid; idx < CH * k; idx += NT) {
-      const int j = idx / CH, cc = idx % CH, c = c0 + cc;
-      double x = 0.0;
-      if (c < s && live[j]) {
-        x = u[(int64_t)j * s + c];
-        if (v) x = fma(coef[j], v[(int64_t)j * s + c], x);
-      }
-      xs[j][cc] = x;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < CH / WAVE; ++i) {
-      const int cc = lane + WAVE * i, c = c0 + cc;
-      if (c < s) {
-        const double hA = rA < s ? M[(int64_t)rA * s + c] : 0.0;
-        const double hB = rB < s ? M[(int64_t)rB * s + c] : 0.0;
-#pragma unroll
-        for (int j = 0; j < KM; ++j) {
-          if (j < k) {
-            const double x = xs[j][cc];
-            acc[0][j] = fma(hA, x, acc[0][j]);
-            acc[1][j] = fma(hB, x, acc[1][j]);
-          }
+    for (int q = 0; q < BATCH; ++q) {
+      const int idx = base + q * NT + (int)threadIdx.x;
+      uv[q] = 0.0;
+      vv[q] = 0.0;
+      if (idx < total) {
+        const int jj = idx / s, c = idx - jj * s;
+        if (live[j0 + jj]) {
+          uv[q] = u[(int64_t)(j0 + jj) * s + c];
+          if (v) vv[q] = v[(int64_t)(j0 + jj) * s + c];
         }
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int idx = base + q * NT + (int)threadIdx.x;
+      if (idx < total) {
+        const int jj = idx / s;
+        xs[idx] = v ? fma(coef[j0 + jj], vv[q], uv[q]) : uv[q];
+      }
+    }
+  }
+}
+
+// acc[jj] = sum_c M[row][c] xs[jj * s + c] over this lane's columns c = lane + 64 i
+__device__ __forceinline__ void row_dots(const double* __restrict__ M, int s, int row, int kg, const double* xs,
+                                         double (&acc)[KG]) {
+  const int lane = threadIdx.x % WAVE;
+#pragma unroll
+  for (int jj = 0; jj < KG; ++jj) acc[jj] = 0.0;
+  if (row >= s) return;
+  const double* mr = M + (int64_t)row * s;
+#pragma unroll 8
+  for (int c = lane; c < s; c += WAVE) {
+    const double h = mr[c];
+#pragma unroll
+    for (int jj = 0; jj < KG; ++jj)
+      if (jj < kg) acc[jj] = fma(h, xs[jj * s + c], acc[jj]);
   }
 }
 
 __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
-  __shared__ double xs[KM][CH];
+  extern __shared__ double xs[];  // KG * s doubles
   __shared__ double beta_s[KM];
   __shared__ int live_s[KM];
-  __shared__ double red[4][2][KM];
+  __shared__ double red[NWV][KM];
   const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
   const int par = t & 1, nxt = par ^ 1;
   const int s = a.s, k = a.k;
-  // ---- decision on |r_t| and beta_t (the same in every block) ----
-  if (tid < k) {
-    const int j = tid;
+  // ---- decision on |r_t| and beta_t (the same in every block): wavefront w takes the
+  // columns w, w + NWV ----
+  for (int j = w; j < k; j += NWV) {
     int dj = fresh ? a.S.done[j] : a.done[par][j];
     int it = fresh ? a.S.iters[j] : a.iters[par][j];
     double rz = fresh ? a.S.rz[j] : a.rz[par][j];
     double beta = 0.0;
-    if (!fresh && dj == 0) {
-      double zr = 0.0, zro = 0.0, rr = 0.0;
-      for (int b = 0; b < a.nb; ++b) {
-        const double* d = a.dpart + ((int64_t)b * k + j) * 3;
-        zr += d[0];
-        zro += d[1];
-        rr += d[2];
-      }
+    if (!fresh && dj == 0) {  // uniform in the wavefront
+      const double zr = wave_parts(a.dpart, a.nb, (int64_t)k * 3, j * 3 + 0);
+      const double zro = wave_parts(a.dpart, a.nb, (int64_t)k * 3, j * 3 + 1);
+      const double rr = wave_parts(a.dpart, a.nb, (int64_t)k * 3, j * 3 + 2);
       ++it;
       const double rn = sqrt(rr);
       if (a.brk[j] || !(rn == rn)) dj = 2;
@@ -114,167 +132,174 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
           dj = 2;
         }
       }
-      if (blockIdx.x == 0) a.S.rnorm[j] = rn;
-    }
-    live_s[j] = dj == 0;
-    beta_s[j] = beta;
-    if (blockIdx.x == 0) {
-      a.done[nxt][j] = dj;
-      a.iters[nxt][j] = it;
-      a.rz[nxt][j] = rz;
-    }
-  }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    if (tid == 0) {
-      int cnt = 0, mx = 0;
-      for (int j = 0; j < k; ++j) {
-        cnt += live_s[j];
-        mx = max(mx, a.iters[nxt][j]);
-      }
-      if (a.mirror) {
-        __hip_atomic_store(a.mirror, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(a.mirror + 1, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
-    }
-  }
-  int any = 0;
-  for (int j = 0; j < k; ++j) any |= live_s[j];
-  if (!any) return;  // uniform in the block
-  const double* pc = a.p[par];
-  double* pn = a.p[nxt];
-  const int r0 = blockIdx.x * RB;
-  // p_t for the block's own rows (the previous direction for the first step: p = z)
-  for (int idx = tid; idx < RB * k; idx += NT) {
-    const int j = idx / RB, row = r0 + idx % RB;
-    if (row < s && live_s[j]) pn[(int64_t)j * s + row] = fresh ? pc[(int64_t)j * s + row]
-                                                                : fma(beta_s[j], pc[(int64_t)j * s + row],
-                                                                      a.z[(int64_t)j * s + row]);
-  }
-  double acc[2][KM];
-  if (fresh)
-    rows_product(a.H, s, k, r0, pc, nullptr, beta_s, live_s, xs, acc);
-  else
-    rows_product(a.H, s, k, r0, a.z, pc, beta_s, live_s, xs, acc);
-  // q rows and their <p, q> contributions
-#pragma unroll
-  for (int j = 0; j < KM; ++j) {
-    if (j >= k) continue;
-    const double qa = wave_sum(acc[0][j]), qb = wave_sum(acc[1][j]);
-    double pa = 0.0, pb = 0.0;
-    if (lane == 0 && live_s[j]) {
-      const int rA = r0 + 2 * w, rB = rA + 1;
-      if (rA < s) {
-        const double pv = fresh ? pc[(int64_t)j * s + rA] : fma(beta_s[j], pc[(int64_t)j * s + rA], a.z[(int64_t)j * s + rA]);
-        const double qv = fma(a.sigma, pv, qa);
-        a.q[(int64_t)j * s + rA] = qv;
-        pa = pv * qv;
-      }
-      if (rB < s) {
-        const double pv = fresh ? pc[(int64_t)j * s + rB] : fma(beta_s[j], pc[(int64_t)j * s + rB], a.z[(int64_t)j * s + rB]);
-        const double qv = fma(a.sigma, pv, qb);
-        a.q[(int64_t)j * s + rB] = qv;
-        pb = pv * qv;
-      }
+      if (blockIdx.x == 0 && lane == 0) a.S.rnorm[j] = rn;
     }
     if (lane == 0) {
-      red[w][0][j] = pa;
-      red[w][1][j] = pb;
+      live_s[j] = dj == 0;
+      beta_s[j] = beta;
+      if (blockIdx.x == 0) {
+        a.done[nxt][j] = dj;
+        a.iters[nxt][j] = it;
+        a.rz[nxt][j] = rz;
+      }
     }
   }
   __syncthreads();
+  if (blockIdx.x == 0 && tid == 0 && a.mirror) {
+    int cnt = 0, mx = 0;
+    for (int j = 0; j < k; ++j) {
+      cnt += live_s[j];
+      mx = max(mx, a.iters[nxt][j]);
+    }
+    __hip_atomic_store(a.mirror, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(a.mirror + 1, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  const double* pc = a.p[par];
+  double* pn = a.p[nxt];
+  const int row = blockIdx.x * NWV + w;
+  for (int j0 = 0; j0 < k; j0 += KG) {
+    const int kg = min(KG, k - j0);
+    int any = 0;
+    for (int jj = 0; jj < kg; ++jj) any |= live_s[j0 + jj];
+    if (!any) {  // uniform in the block
+      if (tid < kg)
+        for (int ww = 0; ww < NWV; ++ww) red[ww][j0 + tid] = 0.0;
+      continue;
+    }
+    // p_t = z_t + beta_t p_{t-1} (p_0 = z_0, held in p[0]) for every row, staged
+    if (fresh)
+      stage(pc, nullptr, beta_s, live_s, s, j0, kg, xs);
+    else
+      stage(a.z, pc, beta_s, live_s, s, j0, kg, xs);
+    __syncthreads();
+    double acc[KG];
+    row_dots(a.H, s, row, kg, xs, acc);
+    // lane jj finishes column j0 + jj of the wavefront's row: p_t, q_t and <p_t, q_t>
+    double mine = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < KG; ++jj) {
+      const double qs = wave_sum(acc[jj]);
+      if (lane == jj) mine = qs;
+    }
+    if (lane < kg) {
+      const int j = j0 + lane;
+      double pq = 0.0;
+      if (row < s && live_s[j]) {
+        const double pv = xs[lane * s + row];
+        const double qv = fma(a.sigma, pv, mine);
+        pn[(int64_t)j * s + row] = pv;
+        a.q[(int64_t)j * s + row] = qv;
+        pq = pv * qv;
+      }
+      red[w][j] = pq;
+    }
+    __syncthreads();  // xs is restaged by the next pass; red is complete
+  }
   if (tid < k) {
-    const int j = tid;
     double t2 = 0.0;
-    for (int ww = 0; ww < 4; ++ww) t2 += red[ww][0][j] + red[ww][1][j];
-    a.ppart[(int64_t)blockIdx.x * k + j] = t2;
+    for (int ww = 0; ww < NWV; ++ww) t2 += red[ww][tid];
+    a.ppart[(int64_t)blockIdx.x * k + tid] = t2;
   }
 }
 
 __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
-  __shared__ double xs[KM][CH];
+  extern __shared__ double xs[];  // KG * s doubles
   __shared__ double alpha_s[KM];
   __shared__ int live_s[KM];
-  __shared__ double red[4][2][3][KM];
+  __shared__ double red[NWV][KM][3];
   const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
   const int par = t & 1, nxt = par ^ 1;
   const int s = a.s, k = a.k;
   // alpha_t = <r_t, z_t> / <p_t, q_t> (the same in every block)
-  if (tid < k) {
-    const int j = tid;
+  for (int j = w; j < k; j += NWV) {
     const int dj = a.done[nxt][j];
     double al = 0.0;
-    if (dj == 0) {
-      double pq = 0.0;
-      for (int b = 0; b < a.nb; ++b) pq += a.ppart[(int64_t)b * k + j];
+    if (dj == 0) {  // uniform in the wavefront
+      const double pq = wave_parts(a.ppart, a.nb, k, j);
       const bool brk = !(pq > 0.0);
       al = brk ? 0.0 : a.rz[nxt][j] / pq;
-      if (blockIdx.x == 0) {
+      if (blockIdx.x == 0 && lane == 0) {
         a.brk[j] = brk ? 1 : 0;
         a.alpha[j] = al;
       }
     }
-    live_s[j] = dj == 0;
-    alpha_s[j] = -al;  // r_{t+1} = r_t + (-alpha) q_t
+    if (lane == 0) {
+      live_s[j] = dj == 0;
+      alpha_s[j] = -al;  // r_{t+1} = r_t + (-alpha) q_t
+    }
   }
   __syncthreads();
-  int any = 0;
-  for (int j = 0; j < k; ++j) any |= live_s[j];
-  if (!any) return;
   const double* rc = a.r[par];
   double* rn = a.r[nxt];
   const double* pn = a.p[nxt];
-  const int r0 = blockIdx.x * RB;
-  // y and r_{t+1} for the block's own rows
-  for (int idx = tid; idx < RB * k; idx += NT) {
-    const int j = idx / RB, row = r0 + idx % RB;
-    if (row < s && live_s[j]) {
-      const int64_t o = (int64_t)j * s + row;
-      a.y[o] = fma(-alpha_s[j], pn[o], a.y[o]);
-      rn[o] = fma(alpha_s[j], a.q[o], rc[o]);
+  const int row = blockIdx.x * NWV + w;
+  for (int j0 = 0; j0 < k; j0 += KG) {
+    const int kg = min(KG, k - j0);
+    int any = 0;
+    for (int jj = 0; jj < kg; ++jj) any |= live_s[j0 + jj];
+    if (!any) {
+      if (tid < kg)
+        for (int ww = 0; ww < NWV; ++ww)
+          for (int e = 0; e < 3; ++e) red[ww][j0 + tid][e] = 0.0;
+      continue;
     }
-  }
-  double acc[2][KM];
-  rows_product(a.Minv, s, k, r0, rc, a.q, alpha_s, live_s, xs, acc);
+    stage(rc, a.q, alpha_s, live_s, s, j0, kg, xs);  // r_{t+1}
+    __syncthreads();
+    double acc[KG];
+    row_dots(a.Minv, s, row, kg, xs, acc);
+    double mine = 0.0;
 #pragma unroll
-  for (int j = 0; j < KM; ++j) {
-    if (j >= k) continue;
-    const double za = wave_sum(acc[0][j]), zb = wave_sum(acc[1][j]);
-    double d[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    if (lane == 0 && live_s[j]) {
-      const int rows[2] = {r0 + 2 * w, r0 + 2 * w + 1};
-      const double zz[2] = {za, zb};
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int row = rows[h];
-        if (row >= s) continue;
+    for (int jj = 0; jj < KG; ++jj) {
+      const double zs = wave_sum(acc[jj]);
+      if (lane == jj) mine = zs;
+    }
+    if (lane < kg) {
+      const int j = j0 + lane;
+      double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+      if (row < s && live_s[j]) {
         const int64_t o = (int64_t)j * s + row;
-        const double rnew = fma(alpha_s[j], a.q[o], rc[o]);
-        a.z[o] = zz[h];
-        d[h][0] = zz[h] * rnew;
-        d[h][1] = zz[h] * rc[o];
-        d[h][2] = rnew * rnew;
+        const double rnew = xs[lane * s + row];
+        const double rold = rc[o];
+        a.y[o] = fma(-alpha_s[j], pn[o], a.y[o]);
+        rn[o] = rnew;
+        a.z[o] = mine;
+        d0 = mine * rnew;
+        d1 = mine * rold;
+        d2 = rnew * rnew;
       }
+      red[w][j][0] = d0;
+      red[w][j][1] = d1;
+      red[w][j][2] = d2;
     }
-    if (lane == 0) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int e = 0; e < 3; ++e) red[w][h][e][j] = d[h][e];
-    }
+    __syncthreads();
   }
-  __syncthreads();
   if (tid < 3 * k) {
     const int j = tid / 3, e = tid % 3;
     double t2 = 0.0;
-    for (int ww = 0; ww < 4; ++ww) t2 += red[ww][0][e][j] + red[ww][1][e][j];
+    for (int ww = 0; ww < NWV; ++ww) t2 += red[ww][j][e];
     a.dpart[((int64_t)blockIdx.x * k + j) * 3 + e] = t2;
   }
 }
 
+size_t lds_bytes(int s) { return (size_t)KG * (size_t)s * sizeof(double); }
+
+std::once_flag g_lds_once;
+hipError_t g_lds_err = hipSuccess;
+
+// the staging array exceeds the default 64 KiB of dynamic LDS for s > 1024
+hipError_t allow_lds() {
+  std::call_once(g_lds_once, [] {
+    const int bytes = (int)lds_bytes(kL2fMaxS);
+    g_lds_err = hipFuncSetAttribute((const void*)k_l2f_op, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (g_lds_err == hipSuccess)
+      g_lds_err = hipFuncSetAttribute((const void*)k_l2f_prec, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  });
+  return g_lds_err;
+}
+
 }  // namespace
 
-int l2f_blocks(int64_t s) { return (int)((s + RB - 1) / RB); }
+int l2f_blocks(int64_t s) { return (int)((s + NWV - 1) / NWV); }
 
 L2fArgs l2f_carve(WsCarver& w, int64_t s, int64_t k) {
   L2fArgs a{};
@@ -296,11 +321,17 @@ L2fArgs l2f_carve(WsCarver& w, int64_t s, int64_t k) {
 }
 
 hipError_t l2f_op(hipStream_t st, const L2fArgs& a, int t, int fresh) {
-  hipLaunchKernelGGL(k_l2f_op, dim3((unsigned)a.nb), dim3(NT), 0, st, a, t, fresh);
+  if (a.s < 1 || a.s > kL2fMaxS || a.k < 1 || a.k > kL2fMaxK) return hipErrorInvalidValue;
+  hipError_t e = allow_lds();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_l2f_op, dim3((unsigned)a.nb), dim3(NT), lds_bytes(a.s), st, a, t, fresh);
   return hipGetLastError();
 }
 
 hipError_t l2f_prec(hipStream_t st, const L2fArgs& a, int t) {
-  hipLaunchKernelGGL(k_l2f_prec, dim3((unsigned)a.nb), dim3(NT), 0, st, a, t);
+  if (a.s < 1 || a.s > kL2fMaxS || a.k < 1 || a.k > kL2fMaxK) return hipErrorInvalidValue;
+  hipError_t e = allow_lds();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_l2f_prec, dim3((unsigned)a.nb), dim3(NT), lds_bytes(a.s), st, a, t);
   return hipGetLastError();
 }

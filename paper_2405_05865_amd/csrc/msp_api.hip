@@ -596,7 +596,7 @@ size_t solve_layout(WsCarver& w, const msp_precond* P, int64_t k, SolveCtx* c, i
     G2 = w.take<double>(s * s);
   }
   // the general level 3 as two kernels per step (level2_form 1, at most kL2fMaxK columns)
-  const bool use_f = form == 1 && P->structure == MSP_GENERAL && l3k == 2 && k <= kL2fMaxK;
+  const bool use_f = form == 1 && P->structure == MSP_GENERAL && l3k == 2 && k <= kL2fMaxK && s <= kL2fMaxS;
   L2fArgs F{};
   if (use_f) F = l2f_carve(w, s, k);
   // the lower-triangle level-1 sweep (PSD, one right-hand side)

@@ -372,11 +372,12 @@ hipError_t l2x_publish(hipStream_t st, const L2xArgs& a, int par);
 // ---------------------------------------------------------------------------------
 // Inner iterations with an explicit operator H (+ sigma I) and preconditioner Minv by
 // direct products, two kernels per step (k_l2f.hip): the level-3 solves of the general
-// path. The state after l2_init (y = 0, r_0, z_0 = Minv r_0, p_0 = z_0, S.rz, S.done,
+// path (s <= kL2fMaxS). The state after l2_init (y = 0, r_0, z_0 = Minv r_0, p_0 = z_0, S.rz, S.done,
 // S.bnorm, S.iters = 0) is the input: r[0] = that r, p[0] = that p; r[1] and p[1] alternate
 // with them by step parity. The solution accumulates in y.
 // ---------------------------------------------------------------------------------
 constexpr int kL2fMaxK = 16;
+constexpr int kL2fMaxS = 2048;
 constexpr int kL2fRows = 8;
 struct L2fArgs {
   int s, k, nb;

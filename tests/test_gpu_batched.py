@@ -105,6 +105,42 @@ def test_batched_low_precision_refined(lo, hi):
         assert info["refine_steps"] >= 1
 
 
+def test_batched_bf16_sweeps_at_the_workload_lambda():
+    # the BF16 sweep variant of the batched GP workload at its own lam = 1e-2 (RBF kernels in
+    # 4 dimensions, the F32 matrix is the problem): BF16 rounding moves A by far more than
+    # lam, so the refinement runs Krylov steps around the BF16 solves; every system must still
+    # reach a relative residual of 1e-8 on the F32 matrix, and x is compared with the dense
+    # FP64 solution of that matrix
+    sizes = [300, 96, 513, 200]
+    k = 4
+    say("case batched bf16 sweeps lam=1e-2")
+    syss, args, Bs = [], [], []
+    for i, n in enumerate(sizes):
+        sy = _system(n, 650 + i, lam=1e-2, dtype=np.float32, lengthscale=0.5 + 0.5 * i)
+        A_hi = _padded(sy["a"], torch.float32, pad=(8 if i % 2 else 0))
+        A_lo = torch.empty_strided(A_hi.shape, A_hi.stride(), dtype=torch.bfloat16, device=DEV)
+        A_lo.copy_(A_hi)
+        P = _build(sy, torch.from_numpy(sy["a"]).to(DEV))
+        Bm = W.gaussian((k, n), 650 + i)
+        syss.append(sy)
+        Bs.append(Bm)
+        args.append((P, A_hi, A_lo, torch.from_numpy(Bm).to(DEV)))
+    # the Krylov refinement takes tens of steps here (30 is the default cap)
+    Xs, infos = msp.solve_batched(args, tol=1e-8, refine=1, max_refine=300)
+    for sy, Bm, X, info in zip(syss, Bs, Xs, infos):
+        say(sy["n"], info)
+        assert info["status"] == "MSP_OK", info
+        x = X.cpu().numpy()
+        xs = dense.solve_psd(sy["a64"], Bm.T, sy["lam"]).T
+        err = max(np.linalg.norm(x[j] - xs[j]) / np.linalg.norm(xs[j]) for j in range(k))
+        say(f"n={sy['n']}: max_j |x - x*| / |x*| = {err:.3e}")
+        for j in range(k):
+            rel = dense.rel_residual_psd(sy["a64"], x[j], Bm[j], sy["lam"])
+            assert rel <= 1e-8 * (1 + 1e-6)
+            # A + lam I >= lam I: the forward error the residual allows
+            assert np.linalg.norm(x[j] - xs[j]) <= 1.01 * rel * np.linalg.norm(Bm[j]) / sy["lam"] + 1e-10 * np.linalg.norm(xs[j])
+
+
 def test_batched_deterministic_and_chunks_of_16():
     sizes = [150, 77, 260]
     k = 20  # two launches: 16 + 4 right-hand sides

@@ -288,3 +288,48 @@ def test_orlicz_matches_oracle():
     assert se == pytest.approx(se_o, rel=1e-4)
     want = brentq(lambda x: float(np.sum(sig / x + 0.5 * (sig / x) ** 1.5)) - 1.0, 1e-3, 1e6, xtol=1e-14)
     assert abs(r - want) < 4 * se + 2e-4 * want
+
+
+def _kyfan_matrix(m, n, sig, seed):
+    rng_ = np.random.default_rng(seed)
+    u, _ = np.linalg.qr(rng_.standard_normal((m, n)))
+    v, _ = np.linalg.qr(rng_.standard_normal((n, n)))
+    return (u * sig) @ v.T
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_kyfan_matches_oracle_subspace(dt):
+    # the same Gaussian start block (the probe generator) on both sides: the GPU's Ritz
+    # values against the oracle's subspace iteration on the same (rounded) matrix, and the
+    # estimate against the singular values (sigma_{b+1} / sigma_k = 1/3: converged)
+    from oracle import rng
+    say(f"case ky fan m=300 n=240 k=6 b=12 q=12 {dt}")
+    m, n, k, b, q, seed = 300, 240, 6, 12, 12, 99
+    sig = np.concatenate([np.linspace(10.0, 6.0, 8), np.linspace(2.0, 0.1, n - 8)])
+    a = _kyfan_matrix(m, n, sig, 401)
+    A = torch.from_numpy(a).to(DEV).to(dt).contiguous()
+    est, ritz = msp.kyfan(A, k, b, q, seed)
+    a_used = A.double().cpu().numpy()
+    omega = rng.gaussian_probes(seed, n, b).T
+    est_o, ritz_o = trace.kyfan_subspace(a_used, k, b, q, omega)
+    say(est, est_o, ritz[:4], ritz_o[:4])
+    assert np.allclose(ritz, ritz_o, rtol=1e-9, atol=1e-12 * ritz_o[0])
+    assert est == pytest.approx(est_o, rel=1e-10)
+    sv = np.linalg.svd(a_used, compute_uv=False)
+    assert est <= sv[:k].sum() * (1 + 1e-12)
+    assert est >= sv[:k].sum() * (1 - 1e-9)
+
+
+def test_kyfan_exact_at_low_rank():
+    # rank(A) = 9 <= b = 16: one step of the iteration spans range(A^T)
+    say("case ky fan low rank")
+    m, n, r = 200, 150, 9
+    g = np.random.default_rng(402)
+    a = g.standard_normal((m, r)) @ g.standard_normal((r, n))
+    sv = np.linalg.svd(a, compute_uv=False)
+    A = torch.from_numpy(a).to(DEV)
+    for k in (1, 5, 9):
+        est, ritz = msp.kyfan(A, k, 16, 1, 7)
+        assert est == pytest.approx(float(sv[:k].sum()), rel=1e-10)
+    assert np.allclose(ritz[:r], sv[:r], rtol=1e-10)
+    assert max(ritz[r:]) <= 1e-7 * sv[0]

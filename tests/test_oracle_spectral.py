@@ -1,4 +1,5 @@
-"""Pins of the oracle's descending-node Schatten estimator and the Orlicz norm (Section 3.2)."""
+"""Pins of the oracle's descending-node Schatten estimator, the Orlicz norm and the Ky Fan norm
+(Section 3.2)."""
 import math
 
 import numpy as np
@@ -117,3 +118,72 @@ def test_orlicz_estimate_within_statistical_error():
     r, se, _, _ = trace.orlicz_estimate(a, g, coefs, powers, 1.0, u_hi, ridge)
     want = brentq(lambda r: float(np.sum(sig / r + (sig / r) ** 1.5)) - 1.0, 1e-3, 1e6, xtol=1e-14)
     assert abs(r - want) <= 4.0 * se
+
+
+# ---- Ky Fan norms by subspace iteration ----------------------------------------------
+def _general(sig, seed, m=None):
+    n = len(sig)
+    m = m or n
+    rng = np.random.default_rng(seed)
+    u, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    v, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return (u * sig) @ v.T
+
+
+def test_kyfan_exact_at_rank_within_the_block():
+    # rank(A) <= b: the first step's subspace holds range(A^T), so the Ritz values are the
+    # singular values
+    n, r, b = 120, 10, 16
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal((n, r)) @ rng.standard_normal((r, n))
+    sig = np.linalg.svd(a, compute_uv=False)
+    om = rng.standard_normal((n, b))
+    for k in (1, 4, 10):
+        est, ritz = trace.kyfan_subspace(a, k, b, 1, om)
+        assert est == pytest.approx(float(sig[:k].sum()), rel=1e-11)
+    assert np.allclose(ritz[:r], sig[:r], rtol=1e-11)
+
+
+def test_kyfan_ritz_values_interlace():
+    # every Ritz value is at most the singular value of the same rank, for any subspace
+    sig = np.geomspace(1.0, 1e-3, 80)
+    a = _general(sig, 12, m=100)
+    om = np.random.default_rng(13).standard_normal((80, 12))
+    for q in (0, 1, 3):
+        _, ritz = trace.kyfan_subspace(a, 5, 12, q, om)
+        assert np.all(ritz <= sig[:12] * (1 + 1e-12))
+
+
+def test_kyfan_converges_with_a_gap():
+    # sigma_{b+1} / sigma_k = 1/2: the top-k Ritz values converge like (1/2)^{2q}
+    sig = np.concatenate([np.linspace(10.0, 6.0, 8), np.linspace(2.0, 0.1, 92)])
+    a = _general(sig, 14)
+    om = np.random.default_rng(15).standard_normal((100, 10))
+    want = float(sig[:6].sum())
+    errs = [want - trace.kyfan_subspace(a, 6, 10, q, om)[0] for q in (2, 6, 12)]
+    assert errs[0] > 0 and errs[2] >= -1e-12 * want
+    assert errs[2] < 1e-10 * want and errs[1] < errs[0]
+
+
+def test_kyfan_one_vector_is_the_power_method():
+    # k = b = 1: the estimate is |A x_q| for the normalised power iterate x_q on A^T A
+    sig = np.linspace(3.0, 0.5, 50)
+    a = _general(sig, 16)
+    x = np.random.default_rng(17).standard_normal(50)
+    q = 7
+    y = x / np.linalg.norm(x)
+    for _ in range(q):
+        y = a.T @ (a @ y)
+        y /= np.linalg.norm(y)
+    est, _ = trace.kyfan_subspace(a, 1, 1, q, x[:, None])
+    assert est == pytest.approx(float(np.linalg.norm(a @ y)), rel=1e-13)
+
+
+def test_orthonormal_columns_drops_a_dependent_direction():
+    rng = np.random.default_rng(18)
+    z = rng.standard_normal((40, 5))
+    z[:, 4] = z[:, 0] + z[:, 1]
+    qm = trace.orthonormal_columns(z)
+    g = qm.T @ qm
+    assert np.count_nonzero(np.abs(np.diag(g)) > 0.5) == 4
+    assert np.allclose(g[np.ix_(np.diag(g) > 0.5, np.diag(g) > 0.5)], np.eye(4), atol=1e-12)
