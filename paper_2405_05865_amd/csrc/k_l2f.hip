@@ -15,7 +15,9 @@
 // breakdown rules) with the matrix products as plain FP64 row dots: only the summation order
 // differs. Both kernels are bound by latency, not bandwidth (the s x s operands stay in the
 // caches between steps), so each makes as few dependent round trips as it can: a block of
-// eight wavefronts owns eight rows (one each); the vector it multiplies (p_t, resp. r_{t+1},
+// eight wavefronts owns eight rows, one each (four rows per wavefront, a quarter of the blocks
+// and of the bytes staged, measured slower at s = 2048: 79 against 66 us per step); the vector
+// it multiplies (p_t, resp. r_{t+1},
 // formed on the fly from the two vectors that define it) is staged whole into LDS for eight
 // columns at a time, every thread issuing its loads in batches before storing any; the
 // partial sums of the previous kernel are reduced by whole wavefronts. p and r alternate
@@ -28,11 +30,11 @@
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int NWV = kL2fRows;     // wavefronts per block, one row each
+constexpr int NWV = kL2fRows;     // wavefronts per block
 constexpr int NT = NWV * WAVE;
 constexpr int KG = 8;             // columns per staging pass
 constexpr int KM = kL2fMaxK;      // columns per launch
-constexpr int BATCH = 8;          // staged elements per thread per batch of loads
+constexpr int BATCH = 16;         // staged elements per thread per batch of loads
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -81,23 +83,36 @@ __device__ __forceinline__ void stage(const double* __restrict__ u, const double
   }
 }
 
-// acc[jj] = sum_c M[row][c] xs[jj * s + c] over this lane's columns c = lane + 64 i
-__device__ __forceinline__ void row_dots(const double* __restrict__ M, int s, int row, int kg, const double* xs,
-                                         double (&acc)[KG]) {
+// acc[i][jj] = sum_c M[row_i][c] xs[jj * s + c] over this lane's columns c = lane + 64 m,
+// rows row_i = row0 + NWV i
+template <int RPW>
+__device__ __forceinline__ void row_dots(const double* __restrict__ M, int s, int row0, int kg, const double* xs,
+                                         double (&acc)[RPW][KG]) {
   const int lane = threadIdx.x % WAVE;
 #pragma unroll
-  for (int jj = 0; jj < KG; ++jj) acc[jj] = 0.0;
-  if (row >= s) return;
-  const double* mr = M + (int64_t)row * s;
-#pragma unroll 8
-  for (int c = lane; c < s; c += WAVE) {
-    const double h = mr[c];
+  for (int i = 0; i < RPW; ++i)
 #pragma unroll
-    for (int jj = 0; jj < KG; ++jj)
-      if (jj < kg) acc[jj] = fma(h, xs[jj * s + c], acc[jj]);
+    for (int jj = 0; jj < KG; ++jj) acc[i][jj] = 0.0;
+#pragma unroll 16
+  for (int c = lane; c < s; c += WAVE) {
+    double h[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int row = row0 + NWV * i;
+      h[i] = row < s ? M[(int64_t)row * s + c] : 0.0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < KG; ++jj) {
+      if (jj < kg) {
+        const double x = xs[jj * s + c];
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) acc[i][jj] = fma(h[i], x, acc[i][jj]);
+      }
+    }
   }
 }
 
+template <int RPW>
 __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
   extern __shared__ double xs[];  // KG * s doubles
   __shared__ double beta_s[KM];
@@ -156,7 +171,7 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
   }
   const double* pc = a.p[par];
   double* pn = a.p[nxt];
-  const int row = blockIdx.x * NWV + w;
+  const int row0 = blockIdx.x * NWV * RPW + w;
   for (int j0 = 0; j0 < k; j0 += KG) {
     const int kg = min(KG, k - j0);
     int any = 0;
@@ -172,27 +187,31 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
     else
       stage(a.z, pc, beta_s, live_s, s, j0, kg, xs);
     __syncthreads();
-    double acc[KG];
-    row_dots(a.H, s, row, kg, xs, acc);
-    // lane jj finishes column j0 + jj of the wavefront's row: p_t, q_t and <p_t, q_t>
-    double mine = 0.0;
+    double acc[RPW][KG];
+    row_dots<RPW>(a.H, s, row0, kg, xs, acc);
+    // lane jj finishes column j0 + jj of the wavefront's rows: p_t, q_t and <p_t, q_t>
+    double pq = 0.0;
 #pragma unroll
-    for (int jj = 0; jj < KG; ++jj) {
-      const double qs = wave_sum(acc[jj]);
-      if (lane == jj) mine = qs;
-    }
-    if (lane < kg) {
-      const int j = j0 + lane;
-      double pq = 0.0;
-      if (row < s && live_s[j]) {
-        const double pv = xs[lane * s + row];
-        const double qv = fma(a.sigma, pv, mine);
-        pn[(int64_t)j * s + row] = pv;
-        a.q[(int64_t)j * s + row] = qv;
-        pq = pv * qv;
+    for (int i = 0; i < RPW; ++i) {
+      const int row = row0 + NWV * i;
+      double mine = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < KG; ++jj) {
+        const double qs = wave_sum(acc[i][jj]);
+        if (lane == jj) mine = qs;
       }
-      red[w][j] = pq;
+      if (lane < kg) {
+        const int j = j0 + lane;
+        if (row < s && live_s[j]) {
+          const double pv = xs[lane * s + row];
+          const double qv = fma(a.sigma, pv, mine);
+          pn[(int64_t)j * s + row] = pv;
+          a.q[(int64_t)j * s + row] = qv;
+          pq = fma(pv, qv, pq);
+        }
+      }
     }
+    if (lane < kg) red[w][j0 + lane] = pq;
     __syncthreads();  // xs is restaged by the next pass; red is complete
   }
   if (tid < k) {
@@ -202,6 +221,7 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
   }
 }
 
+template <int RPW>
 __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
   extern __shared__ double xs[];  // KG * s doubles
   __shared__ double alpha_s[KM];
@@ -232,7 +252,7 @@ __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
   const double* rc = a.r[par];
   double* rn = a.r[nxt];
   const double* pn = a.p[nxt];
-  const int row = blockIdx.x * NWV + w;
+  const int row0 = blockIdx.x * NWV * RPW + w;
   for (int j0 = 0; j0 < k; j0 += KG) {
     const int kg = min(KG, k - j0);
     int any = 0;
@@ -245,28 +265,35 @@ __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
     }
     stage(rc, a.q, alpha_s, live_s, s, j0, kg, xs);  // r_{t+1}
     __syncthreads();
-    double acc[KG];
-    row_dots(a.Minv, s, row, kg, xs, acc);
-    double mine = 0.0;
+    double acc[RPW][KG];
+    row_dots<RPW>(a.Minv, s, row0, kg, xs, acc);
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
 #pragma unroll
-    for (int jj = 0; jj < KG; ++jj) {
-      const double zs = wave_sum(acc[jj]);
-      if (lane == jj) mine = zs;
+    for (int i = 0; i < RPW; ++i) {
+      const int row = row0 + NWV * i;
+      double mine = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < KG; ++jj) {
+        const double zs = wave_sum(acc[i][jj]);
+        if (lane == jj) mine = zs;
+      }
+      if (lane < kg) {
+        const int j = j0 + lane;
+        if (row < s && live_s[j]) {
+          const int64_t o = (int64_t)j * s + row;
+          const double rnew = xs[lane * s + row];
+          const double rold = rc[o];
+          a.y[o] = fma(-alpha_s[j], pn[o], a.y[o]);
+          rn[o] = rnew;
+          a.z[o] = mine;
+          d0 = fma(mine, rnew, d0);
+          d1 = fma(mine, rold, d1);
+          d2 = fma(rnew, rnew, d2);
+        }
+      }
     }
     if (lane < kg) {
       const int j = j0 + lane;
-      double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-      if (row < s && live_s[j]) {
-        const int64_t o = (int64_t)j * s + row;
-        const double rnew = xs[lane * s + row];
-        const double rold = rc[o];
-        a.y[o] = fma(-alpha_s[j], pn[o], a.y[o]);
-        rn[o] = rnew;
-        a.z[o] = mine;
-        d0 = mine * rnew;
-        d1 = mine * rold;
-        d2 = rnew * rnew;
-      }
       red[w][j][0] = d0;
       red[w][j][1] = d1;
       red[w][j][2] = d2;
@@ -283,6 +310,9 @@ __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
 
 size_t lds_bytes(int s) { return (size_t)KG * (size_t)s * sizeof(double); }
 
+// rows per wavefront: the kernels are written for RPW rows, one measured fastest
+constexpr int kRowsPerWave = 1;
+
 std::once_flag g_lds_once;
 hipError_t g_lds_err = hipSuccess;
 
@@ -290,16 +320,19 @@ hipError_t g_lds_err = hipSuccess;
 hipError_t allow_lds() {
   std::call_once(g_lds_once, [] {
     const int bytes = (int)lds_bytes(kL2fMaxS);
-    g_lds_err = hipFuncSetAttribute((const void*)k_l2f_op, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (g_lds_err == hipSuccess)
-      g_lds_err = hipFuncSetAttribute((const void*)k_l2f_prec, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void* fns[] = {(const void*)k_l2f_op<kRowsPerWave>, (const void*)k_l2f_prec<kRowsPerWave>};
+    for (const void* f : fns)
+      if (g_lds_err == hipSuccess) g_lds_err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   });
   return g_lds_err;
 }
 
 }  // namespace
 
-int l2f_blocks(int64_t s) { return (int)((s + NWV - 1) / NWV); }
+int l2f_blocks(int64_t s) {
+  const int rb = NWV * kRowsPerWave;
+  return (int)((s + rb - 1) / rb);
+}
 
 L2fArgs l2f_carve(WsCarver& w, int64_t s, int64_t k) {
   L2fArgs a{};
@@ -321,17 +354,19 @@ L2fArgs l2f_carve(WsCarver& w, int64_t s, int64_t k) {
 }
 
 hipError_t l2f_op(hipStream_t st, const L2fArgs& a, int t, int fresh) {
-  if (a.s < 1 || a.s > kL2fMaxS || a.k < 1 || a.k > kL2fMaxK) return hipErrorInvalidValue;
+  if (a.s < 1 || a.s > kL2fMaxS || a.k < 1 || a.k > kL2fMaxK || a.nb != l2f_blocks(a.s)) return hipErrorInvalidValue;
   hipError_t e = allow_lds();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_l2f_op, dim3((unsigned)a.nb), dim3(NT), lds_bytes(a.s), st, a, t, fresh);
+  const size_t lds = lds_bytes(a.s);
+  hipLaunchKernelGGL(k_l2f_op<kRowsPerWave>, dim3((unsigned)a.nb), dim3(NT), lds, st, a, t, fresh);
   return hipGetLastError();
 }
 
 hipError_t l2f_prec(hipStream_t st, const L2fArgs& a, int t) {
-  if (a.s < 1 || a.s > kL2fMaxS || a.k < 1 || a.k > kL2fMaxK) return hipErrorInvalidValue;
+  if (a.s < 1 || a.s > kL2fMaxS || a.k < 1 || a.k > kL2fMaxK || a.nb != l2f_blocks(a.s)) return hipErrorInvalidValue;
   hipError_t e = allow_lds();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_l2f_prec, dim3((unsigned)a.nb), dim3(NT), lds_bytes(a.s), st, a, t);
+  const size_t lds = lds_bytes(a.s);
+  hipLaunchKernelGGL(k_l2f_prec<kRowsPerWave>, dim3((unsigned)a.nb), dim3(NT), lds, st, a, t);
   return hipGetLastError();
 }

@@ -92,6 +92,48 @@ __device__ __forceinline__ void rows_pass(const L2xArgs& a, int row0, const doub
   }
 }
 
+// With one row per wavefront (s <= 512) the wavefront's rows of Minv and G are loaded into
+// registers at the start of a kernel, so their latency overlaps the vector loads and block
+// sums instead of following them; the pass then reads only r from LDS.
+template <int CPL>
+struct RowRegs {
+  double m[CPL], g[CPL];
+};
+
+template <int CPL>
+__device__ __forceinline__ void load_rows(const L2xArgs& a, int row0, RowRegs<CPL>& R) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int s = a.s, i = row0 + w;
+#pragma unroll
+  for (int c4 = 0; c4 < CPL; ++c4) {
+    const int c = lane + c4 * WAVE;
+    const bool in = i < s && c < s;
+    R.m[c4] = in ? a.Minv[(int64_t)i * s + c] : 0.0;
+    R.g[c4] = in ? a.G[(int64_t)i * s + c] : 0.0;
+  }
+}
+
+template <int CPL>
+__device__ __forceinline__ void rows_pass_regs(const L2xArgs& a, int row0, const double* rs, const RowRegs<CPL>& R,
+                                               double* zo, double* go) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int i = row0 + w;
+  if (i >= a.s) return;
+  double tz = 0.0, tg = 0.0;
+#pragma unroll
+  for (int c4 = 0; c4 < CPL; ++c4) {
+    const double rv = rs[lane + c4 * WAVE];  // zero beyond s
+    tz = fma(R.m[c4], rv, tz);
+    tg = fma(R.g[c4], rv, tg);
+  }
+  tz = wave_sum(tz);
+  tg = wave_sum(tg);
+  if (lane == 0) {
+    zo[i] = tz;
+    go[i] = tg;
+  }
+}
+
 // first step's inputs: |b| from r_0 (written by the right-hand-side kernel), the
 // decision (parent done or b = 0), z_0 and g_0
 template <int CPL, int RPW>
@@ -101,6 +143,8 @@ __global__ void __launch_bounds__(NT) k_l2x_start(L2xArgs a) {
   __shared__ double sh[2 * NW];
   const int tid = threadIdx.x, s = a.s;
   const int row0 = blockIdx.x * NW * RPW;
+  RowRegs<CPL> R;
+  if constexpr (RPW == 1) load_rows<CPL>(a, row0, R);
   int cnt = 0;
   {
     const int j = blockIdx.y;
@@ -131,7 +175,10 @@ __global__ void __launch_bounds__(NT) k_l2x_start(L2xArgs a) {
         if (e < CPL * WAVE) rs[e] = rv[q];
       }
       __syncthreads();
-      rows_pass<CPL, RPW>(a, row0, rs, a.z[0] + o, a.g[0] + o);
+      if constexpr (RPW == 1)
+        rows_pass_regs<CPL>(a, row0, rs, R, a.z[0] + o, a.g[0] + o);
+      else
+        rows_pass<CPL, RPW>(a, row0, rs, a.z[0] + o, a.g[0] + o);
     }
   }
   if (gridDim.y == 1 && blockIdx.x == 0 && tid == 0 && a.mirror) {
@@ -155,6 +202,8 @@ __global__ void __launch_bounds__(NT) k_l2x_step(L2xArgs a, int par, int first) 
   const bool publish = gridDim.y == 1 && lead && a.mirror;
   const int j = blockIdx.y;
   const int64_t o = (int64_t)j * s;
+  RowRegs<CPL> R;
+  if constexpr (RPW == 1) load_rows<CPL>(a, row0, R);
   const int dcur = a.done[cur][j];
   if (dcur != 0) {  // carry the finished column's state to the next parity
     const int itc = a.it[cur][j];
@@ -171,7 +220,7 @@ __global__ void __launch_bounds__(NT) k_l2x_step(L2xArgs a, int par, int first) 
     return;  // uniform in the block
   }
   {
-    double zv[EPT], rv[EPT], pv[EPT], uv[EPT];
+    double zv[EPT], rv[EPT], pv[EPT], uv[EPT], gv[EPT];
     double zr = 0.0, zu = 0.0;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -181,6 +230,7 @@ __global__ void __launch_bounds__(NT) k_l2x_step(L2xArgs a, int par, int first) 
       rv[q] = in ? a.r[cur][o + e] : 0.0;
       pv[q] = (in && !first) ? a.p[cur][o + e] : 0.0;
       uv[q] = (in && !first) ? a.u[cur][o + e] : 0.0;
+      gv[q] = in ? a.g[cur][o + e] : 0.0;
       zr = fma(zv[q], rv[q], zr);
       zu = fma(zv[q], uv[q], zu);
     }
@@ -193,10 +243,8 @@ __global__ void __launch_bounds__(NT) k_l2x_step(L2xArgs a, int par, int first) 
     double pq = 0.0;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      const int e = tid + q * NT;
-      const double gv = (e < s) ? a.g[cur][o + e] : 0.0;
       pv[q] = fma(beta, pv[q], zv[q]);
-      uv[q] = fma(beta, uv[q], gv);
+      uv[q] = fma(beta, uv[q], gv[q]);
       pq = fma(pv[q], uv[q], pq);
     }
     pq = block_sum1(pq, sh);
@@ -242,7 +290,10 @@ __global__ void __launch_bounds__(NT) k_l2x_step(L2xArgs a, int par, int first) 
         if (e < CPL * WAVE) rs[e] = rv[q];
       }
       __syncthreads();
-      rows_pass<CPL, RPW>(a, row0, rs, a.z[nxt] + o, a.g[nxt] + o);
+      if constexpr (RPW == 1)
+        rows_pass_regs<CPL>(a, row0, rs, R, a.z[nxt] + o, a.g[nxt] + o);
+      else
+        rows_pass<CPL, RPW>(a, row0, rs, a.z[nxt] + o, a.g[nxt] + o);
     }
   }
 }

@@ -217,6 +217,46 @@ def test_two_kernel_level3_steps_match_the_generic_step(n, s, nrhs):
     assert abs(i2["outer_iters"] - i0["outer_iters"]) <= 2
 
 
+@pytest.mark.parametrize("n,s", [(1100, 1025), (2100, 2048)])
+def test_two_kernel_level3_steps_at_large_s(n, s):
+    # the two-kernel level-3 step at s = 1025 (ragged, two reduction passes per 64 lanes) and
+    # s = 2048 (the largest, 128 KiB of staged vector), against the generic step on 8
+    # right-hand sides; phi = n keeps the matrix small
+    say(f"case two-kernel level-3 steps n={n} s={s} k=8")
+    nrhs = 8
+    # a milder spread (singular values 1 .. 100) keeps the full solves to seconds
+    a, sv, _, _ = W.general_outlier(n, 64, config_id=110, big=(1e1, 1e2))
+    lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
+    bm = W.gaussian((nrhs, n), 110)
+    A = torch.from_numpy(a).to(DEV)
+    rows, signs, Y = msp.sketch(A, s, 8, 41)
+    P = msp.Precond("general", rows, signs, Y, 0.0, lam0, n, 8, 43)
+    B = torch.from_numpy(bm).to(DEV)
+    xs = {}
+    # the first three level-1 steps of both forms: the same iteration, so the same inner and
+    # level-3 counts up to rounding
+    part = {}
+    for l3k in (2, 0):
+        X, info = msp.solve(P, A, B, tol=1e-6, inner_tol=1e-10, level3_tol=1e-10, level3_kernels=l3k, max_outer=3)
+        say("three steps", l3k, info)
+        part[l3k] = info
+    assert abs(part[2]["level3_iters"] - part[0]["level3_iters"]) <= 0.02 * part[0]["level3_iters"] + 4
+    assert abs(part[2]["inner_iters"] - part[0]["inner_iters"]) <= 2
+    for l3k in (2, 0):
+        X, info = msp.solve(P, A, B, tol=1e-6, inner_tol=1e-10, level3_tol=1e-10, level3_kernels=l3k)
+        say(l3k, info)
+        assert info["status"] == "MSP_OK", info
+        x = X.cpu().numpy()
+        for j in range(nrhs):
+            assert np.linalg.norm(a @ x[j] - bm[j]) <= 1e-6 * (1 + 1e-6) * np.linalg.norm(bm[j])
+        xs[l3k] = (x, info)
+    # both residuals are at most 1e-6 |b|, so the solutions differ by at most 2e-6 |b| / sigma_min
+    for j in range(nrhs):
+        assert np.linalg.norm(xs[2][0][j] - xs[0][0][j]) <= 2.02e-6 * np.linalg.norm(bm[j]) / sv.min()
+    assert abs(xs[2][1]["outer_iters"] - xs[0][1]["outer_iters"]) <= 2
+    assert xs[2][1]["level3_iters"] > 0
+
+
 def test_refinement_stops_on_a_stall():
     # kappa(A) ~ 1e6 (so kappa(A)^4 is far beyond FP64) with an FP32 copy inside MSP and the
     # one-level form, whose explicit level-2 matrix B^T B loses the small directions: the
