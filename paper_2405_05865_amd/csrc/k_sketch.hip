@@ -215,12 +215,12 @@ template <int R>
 struct TileCol<double, R> {
   static constexpr int LDR = R + 2;  // doubles per column, 16-byte pad
   template <class TC>
-  static __device__ __forceinline__ void add(const double* col, bool neg, TC* acc) {
+  static __device__ __forceinline__ void add(const double* col, TC sgn, TC* acc) {
 #pragma unroll
     for (int q = 0; q < R / 2; ++q) {
       const double2 v = *reinterpret_cast<const double2*>(col + 2 * q);
-      acc[2 * q] += neg ? -v.x : v.x;
-      acc[2 * q + 1] += neg ? -v.y : v.y;
+      acc[2 * q] = fma(sgn, v.x, acc[2 * q]);
+      acc[2 * q + 1] = fma(sgn, v.y, acc[2 * q + 1]);
     }
   }
 };
@@ -228,14 +228,14 @@ template <int R>
 struct TileCol<float, R> {
   static constexpr int LDR = R + 4;
   template <class TC>
-  static __device__ __forceinline__ void add(const float* col, bool neg, TC* acc) {
+  static __device__ __forceinline__ void add(const float* col, TC sgn, TC* acc) {
 #pragma unroll
     for (int q = 0; q < R / 4; ++q) {
       const float4 v = *reinterpret_cast<const float4*>(col + 4 * q);
-      acc[4 * q] += neg ? -v.x : v.x;
-      acc[4 * q + 1] += neg ? -v.y : v.y;
-      acc[4 * q + 2] += neg ? -v.z : v.z;
-      acc[4 * q + 3] += neg ? -v.w : v.w;
+      acc[4 * q] = fmaf(sgn, v.x, acc[4 * q]);
+      acc[4 * q + 1] = fmaf(sgn, v.y, acc[4 * q + 1]);
+      acc[4 * q + 2] = fmaf(sgn, v.z, acc[4 * q + 2]);
+      acc[4 * q + 3] = fmaf(sgn, v.w, acc[4 * q + 3]);
     }
   }
 };
@@ -243,7 +243,7 @@ template <int R>
 struct TileCol<__hip_bfloat16, R> {
   static constexpr int LDR = R + 8;
   template <class TC>
-  static __device__ __forceinline__ void add(const __hip_bfloat16* col, bool neg, TC* acc) {
+  static __device__ __forceinline__ void add(const __hip_bfloat16* col, TC sgn, TC* acc) {
 #pragma unroll
     for (int q = 0; q < R / 8; ++q) {
       const uint4 v = *reinterpret_cast<const uint4*>(col + 8 * q);
@@ -251,8 +251,8 @@ struct TileCol<__hip_bfloat16, R> {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float lo = __uint_as_float(w[i] << 16), hi = __uint_as_float(w[i] & 0xFFFF0000u);
-        acc[8 * q + 2 * i] += neg ? -lo : lo;
-        acc[8 * q + 2 * i + 1] += neg ? -hi : hi;
+        acc[8 * q + 2 * i] = fmaf(sgn, lo, acc[8 * q + 2 * i]);
+        acc[8 * q + 2 * i + 1] = fmaf(sgn, hi, acc[8 * q + 2 * i + 1]);
       }
     }
   }
@@ -345,7 +345,8 @@ __global__ void __launch_bounds__(256) k_sketch_tiles(const TA* __restrict__ A, 
         const int p1 = off[buf][j + 1];
         for (int p = off[buf][j]; p < p1; ++p) {
           const int32_t e = ent[buf][p];
-          TileCol<TA, R>::add(&tile[buf][(e >> 1) * LDR], (e & 1) != 0, acc[b]);
+          // the entry's sign as a factor: fma(-1, v, a) rounds exactly as a - v
+          TileCol<TA, R>::add(&tile[buf][(e >> 1) * LDR], (e & 1) ? TC(-1) : TC(1), acc[b]);
         }
       }
     }

@@ -1165,8 +1165,6 @@ msp_status gen_level3(SolveCtx& c, const double* rhs, double* out, double sigma,
     f.sigma = sigma;
     f.S = c.L3.S;
     f.y = c.L3.x;
-    f.z = c.L3.z;
-    f.q = c.L3.q;
     f.r[0] = c.L3.r;
     f.r[1] = c.L3.ro;
     f.p[0] = c.L3.p;

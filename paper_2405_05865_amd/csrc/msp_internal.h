@@ -374,30 +374,36 @@ hipError_t l2x_publish(hipStream_t st, const L2xArgs& a, int par);
 // direct products, two kernels per step (k_l2f.hip): the level-3 solves of the general
 // path (s <= kL2fMaxS). The state after l2_init (y = 0, r_0, z_0 = Minv r_0, p_0 = z_0, S.rz, S.done,
 // S.bnorm, S.iters = 0) is the input: r[0] = that r, p[0] = that p; r[1] and p[1] alternate
-// with them by step parity. The solution accumulates in y.
+// with them by step parity. The solution accumulates in y; z and q exist only as the sums of
+// their column-segment partials.
 // ---------------------------------------------------------------------------------
 constexpr int kL2fMaxK = 16;
 constexpr int kL2fMaxS = 2048;
-constexpr int kL2fRows = 8;
+constexpr int kL2fRows = 8;     // wavefronts per block
+constexpr int kL2fSegW = 512;   // operator columns per block
 struct L2fArgs {
   int s, k, nb;
+  int nseg, rpw;   // column segments of kL2fSegW; rows per wavefront (l2f_shape)
   const double* H;
   const double* Minv;
   double sigma;
   FcgState S;
-  double *y, *z, *q;
+  double* y;
   double *r[2], *p[2];
   double *rz[2];
   double* alpha;
   double* ppart;   // [nb][k]     <p, q> partials
   double* dpart;   // [nb][k][3]  <z, r_new>, <z, r_old>, |r_new|^2 partials
+  double* qpart;   // [nseg][k][s] (H + sigma I) p by column segment (sigma p in segment 0)
+  double* zpart;   // [nseg][k][s] Minv r by column segment
   int32_t *done[2], *iters[2];
   int32_t* brk;
   double tol;
   int max_iter;
   int32_t* mirror;  // [2] host-mapped: active columns, largest iteration count
 };
-int l2f_blocks(int64_t s);
+// the launch shape for s: column segments, rows per wavefront, blocks (row blocks x segments)
+void l2f_shape(int64_t s, int* nseg, int* rpw, int* nb);
 // carves p[1], rz, alpha, the partials and the int state; the caller sets the rest
 L2fArgs l2f_carve(WsCarver& w, int64_t s, int64_t k);
 // step t: decision on the previous step (fresh = 1 for t = 0: the l2_init state), p_t,
