@@ -217,13 +217,13 @@ def test_two_kernel_level3_steps_match_the_generic_step(n, s, nrhs):
     assert abs(i2["outer_iters"] - i0["outer_iters"]) <= 2
 
 
-@pytest.mark.parametrize("n,s", [(1100, 1025), (2100, 2048)])
-def test_two_kernel_level3_steps_at_large_s(n, s):
-    # the two-kernel level-3 step at s = 1025 (ragged, two reduction passes per 64 lanes) and
-    # s = 2048 (the largest, 128 KiB of staged vector), against the generic step on 8
-    # right-hand sides; phi = n keeps the matrix small
-    say(f"case two-kernel level-3 steps n={n} s={s} k=8")
-    nrhs = 8
+@pytest.mark.parametrize("n,s,nrhs", [(1100, 1025, 8), (2100, 2048, 8), (1700, 1600, 12)])
+def test_two_kernel_level3_steps_at_large_s(n, s, nrhs):
+    # the two-kernel level-3 step over several 512-column segments: s = 1025 (three segments,
+    # the last one column wide, one row per wavefront), s = 2048 (four segments, four rows per
+    # wavefront) and s = 1600 with 12 right-hand sides (four segments, two rows per wavefront,
+    # two passes of 8 and 4 columns), against the generic step; phi = n keeps the matrix small
+    say(f"case two-kernel level-3 steps n={n} s={s} k={nrhs}")
     # a milder spread (singular values 1 .. 100) keeps the full solves to seconds
     a, sv, _, _ = W.general_outlier(n, 64, config_id=110, big=(1e1, 1e2))
     lam0 = omsp.paper_lambda0(np.sort(sv)[::-1] ** 2, s // 2)
