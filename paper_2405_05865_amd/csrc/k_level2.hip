@@ -800,7 +800,7 @@ hipError_t l2_reduce_to(hipStream_t st, const L2Step& a, double* out, const int3
 }
 
 // one step after l2_op(p): update, decision + preconditioner, new direction
-hipError_t l2_step(hipStream_t st, const L2Step& a) {
+hipError_t l2_step(hipStream_t st, const L2Step& a, bool publish) {
   if (a.nbC == 0 && a.k >= kUpdateColMinK)
     hipLaunchKernelGGL(k_l2_update_m, dim3((unsigned)a.k), dim3(256), 0, st, make_args(a));
   else
@@ -809,6 +809,7 @@ hipError_t l2_step(hipStream_t st, const L2Step& a) {
   hipError_t e = prec_launch(st, a, 1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_l2_dir, dim3((unsigned)a.k), dim3(256), 0, st, make_args(a), 0);
-  if (a.k > kDirFenceMaxK) hipLaunchKernelGGL(k_l2_publish, dim3(1), dim3(256), 0, st, make_args(a));
+  if (a.k > kDirFenceMaxK && publish)
+    hipLaunchKernelGGL(k_l2_publish, dim3(1), dim3(256), 0, st, make_args(a));
   return hipGetLastError();
 }

@@ -791,7 +791,7 @@ msp_status l2_graph(SolveCtx& c, const L2Step& a, const double* M, int P, hipGra
   hipError_t e = hipSuccess;
   for (int i = 0; i < P && e == hipSuccess; ++i) {
     e = l2_op_matrix(c.graphs.cap, M, c.s, a.p, c.k, a.S.done, a.wp, a.pqw, a.gscratch, a.gscratch_n);
-    if (e == hipSuccess) e = l2_step(c.graphs.cap, a);
+    if (e == hipSuccess) e = l2_step(c.graphs.cap, a, i + 1 == P);  // the host reads after the graph
   }
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c.graphs.cap, &g);
@@ -839,7 +839,8 @@ msp_status run_l2(SolveCtx& c, const L2Step& a_in, const double* W, int slotid, 
       else
         MSP_CHECK_HIP(l2_op(c.st, P->Y, P->y_t, rows, c.s, P->ldy, a.p, c.s, c.k, a.S.done, a.part, a.pqpart, W,
                             a.wp, a.pqw, false));
-      MSP_CHECK_HIP(l2_step(c.st, a));
+      // the host mirror is read after the chunk: only its last step publishes it
+      MSP_CHECK_HIP(l2_step(c.st, a, i + 1 == chunk || issued + 1 >= cap));
     }
     TRY(sync(c));
     if (*slot(c, slotid) == 0 || issued >= cap) break;

@@ -333,7 +333,9 @@ hipError_t l2_init(hipStream_t st, const L2Step& a);
 // the first kernel of l2_init alone: y = 0, r = rhs (0 where parent_done)
 hipError_t l2_rhs(hipStream_t st, const L2Step& a);
 // one step after l2_op(p): alpha, y/r update, convergence decision, z = Minv r, p = z + beta p
-hipError_t l2_step(hipStream_t st, const L2Step& a);
+// publish = false skips the host mirror of the active count for more than 16 columns (the
+// caller publishes with the last step before it reads the mirror)
+hipError_t l2_step(hipStream_t st, const L2Step& a, bool publish = true);
 // out[j][c] = sum of the group partials of the last rhs-mode l2_op (Y^T v), s x k
 hipError_t l2_reduce_to(hipStream_t st, const L2Step& a, double* out, const int32_t* skip);
 
