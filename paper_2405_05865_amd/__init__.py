@@ -119,9 +119,12 @@ def _opts(**kw) -> SolveOpts:
 # -----------------------------------------------------------------------------------
 # msp_sketch
 # -----------------------------------------------------------------------------------
-def sketch(A: torch.Tensor, s: int, gamma: int, seed: int, y_dtype: torch.dtype | None = None):
+def sketch(A: torch.Tensor, s: int, gamma: int, seed: int, y_dtype: torch.dtype | None = None,
+           autotune: bool = False):
     """S (Definition 2.1) and Y = A S^T. Returns (S_rows int32 [n, gamma],
-    S_signs int8 [n, gamma], Y [m, s])."""
+    S_signs int8 [n, gamma], Y [m, s]). autotune=True calls msp_sketch_autotune: the rows of
+    A per block of the sketch kernel are timed on this matrix and the fastest is kept for
+    this shape (returned as a fourth value)."""
     L = library()
     _rowmajor(A, "A")
     m, n = A.shape
@@ -133,6 +136,13 @@ def sketch(A: torch.Tensor, s: int, gamma: int, seed: int, y_dtype: torch.dtype 
     need = B.size_out()
     B.check(L.msp_sketch_workspace(m, n, s, gamma, ctypes.byref(need)))
     ws = _workspace(need.value, A.device)
+    if autotune:
+        chosen = ctypes.c_int32(0)
+        B.check(L.msp_sketch_autotune(_stream(A.device), A.data_ptr(), _code(A), m, n, A.stride(0), s, gamma,
+                                      ctypes.c_uint64(seed & (2 ** 64 - 1)), rows.data_ptr(), signs.data_ptr(),
+                                      Y.data_ptr(), _code(Y), Y.stride(0), ws.data_ptr(), ws.numel(),
+                                      ctypes.byref(chosen)))
+        return rows, signs, Y, chosen.value
     B.check(L.msp_sketch(_stream(A.device), A.data_ptr(), _code(A), m, n, A.stride(0), s, gamma,
                          ctypes.c_uint64(seed & (2 ** 64 - 1)), rows.data_ptr(), signs.data_ptr(), Y.data_ptr(),
                          _code(Y), Y.stride(0), ws.data_ptr(), ws.numel()))

@@ -53,3 +53,31 @@ def test_autotuned_block_sweep(tmp_path, monkeypatch):
     assert rec["kernel"] == "block_sweep" and rec["rows"] == n and rec["cols"] == n and rec["k"] == k
     assert rec["nseg"] == i1["sweep_segments"] and rec["ms"] > 0
     P.close()
+
+
+@pytest.mark.parametrize("dt,n,s", [(torch.float64, 4096, 256), (torch.float32, 3000, 300)])
+def test_autotuned_sketch_rows_per_block(tmp_path, monkeypatch, dt, n, s):
+    # msp_sketch_autotune times every admissible number of rows of A per block on the
+    # caller's matrix and keeps the fastest for the shape; the rows per block change only the
+    # work split, not the order of any sum, so Y is the same bits as the built-in choice's,
+    # and a second call takes the cached choice without timing again
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("MSP_TUNE_CACHE", str(cache))
+    say(f"case sketch autotune n={n} s={s} {dt}")
+    g = torch.Generator(device=DEV)
+    g.manual_seed(402)
+    A = torch.randn((n, n), dtype=dt, device=DEV, generator=g)
+    r0, g0, Y0 = msp.sketch(A, s, 8, 31)
+    r1, g1, Y1, R = msp.sketch(A, s, 8, 31, autotune=True)
+    say("rows per block", R)
+    assert R in (2, 4, 8, 16, 32)
+    assert torch.equal(r0, r1) and torch.equal(g0, g1)
+    assert torch.equal(Y0, Y1)
+    _, _, Y2, R2 = msp.sketch(A, s, 8, 31, autotune=True)
+    _, _, Y3 = msp.sketch(A, s, 8, 31)
+    assert R2 == R and torch.equal(Y2, Y0) and torch.equal(Y3, Y0)
+    lines = [json.loads(l) for l in cache.read_text().splitlines() if l.strip()]
+    assert len(lines) == 1, lines
+    rec = lines[0]
+    assert rec["kernel"] == "sketch_apply" and rec["n"] == n and rec["s"] == s and rec["gamma"] == 8
+    assert rec["rows_per_block"] == R and rec["ms"] > 0
