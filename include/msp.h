@@ -61,7 +61,7 @@ typedef struct msp_precond msp_precond;
  *
  * Definition 2.1 (sparse embedding matrix): S in R^{s x n}; column i of S holds
  * +-1/sqrt(gamma) in gamma distinct rows chosen uniformly without replacement, with
- * independent signs. Algorithm 1 line 3 (PSD) and Algorithm 3 line 4 (general) form
+ * independent signs. Algorithm 1 (PSD) and Algorithm 3 (general) form
  * Y = A S^T (the paper's C, resp. A-tilde), one pass over A.
  *
  * The index draw is counter-based SplitMix64: column key k_i = fmix(seed + (i+1)G),
@@ -116,11 +116,11 @@ msp_status msp_sketch_noalloc(void* stream, const void* A, msp_dtype a_t, int64_
 /* ---------------------------------------------------------------------------------
  * msp_nystrom -- the Nystrom factor and the inner-level preconditioners.
  *
- * MSP_SYM_PSD (Algorithm 1 lines 3-4; Section 4): lam~ = lam + lam0, W = S C
+ * MSP_SYM_PSD (Algorithm 1; Section 4): lam~ = lam + lam0, W = S C
  *   (symmetrised), C~ = Phi C with Phi a second sparse embedding (phi rows,
  *   phi_gamma nonzeros per column, seed phi_seed), M2 = C~^T C~ + lam~ W, and the
  *   explicit inverse M2^{-1} that Algorithm 1 precomputes.
- * MSP_GENERAL (Algorithm 3 lines 2-6; Section 5): A^ = Phi A~ (Phi over the m rows),
+ * MSP_GENERAL (Algorithm 3; Section 5): A^ = Phi A~ (Phi over the m rows),
  *   M3a = A^^T A^, M3b = M3a + lam~ I and their explicit inverses.
  * Every inverse is of (M + mu I), mu = 1e-12 tr(M)/s, by Gauss-Jordan elimination
  * without pivoting (valid for SPD M: each pivot is a positive Schur-complement
@@ -165,8 +165,8 @@ msp_status msp_precond_factors(void* stream, const msp_precond* P, double* W, do
 msp_status msp_precond_set_lambda(void* stream, msp_precond* P, double lambda);
 
 /* ---------------------------------------------------------------------------------
- * msp_solve -- the preconditioned iteration (Algorithm 1 line 5 with Algorithm 2;
- * Algorithm 3 line 7 with Algorithms 4-5).
+ * msp_solve -- the preconditioned iteration (the level-1 iteration of Algorithm 1 with Algorithm 2;
+ * that of Algorithm 3 with Algorithms 4-5).
  *
  * Level 1 is flexible PCG (Polak-Ribiere beta) on (A + lam I) (PSD) or A^T A + lam I
  * (general); with an exact preconditioner it coincides with Algorithm 6 (Section 6).

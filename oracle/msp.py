@@ -108,15 +108,15 @@ class PsdMsp:
         self.lam = float(lam)
         self.lam0 = float(lam0)
         self.opts = opts or MspOptions()
-        # Algorithm 1, line 2: sparse embedding S (Definition 2.1)
+        # Algorithm 1: sparse embedding S (Definition 2.1)
         self.s_rows, self.s_signs = rng.sketch_indices(seed_s, self.n, s, gamma)
         self.s = s
-        # line 3: lam~ = lam + lam0, C = A S^T, W = S C
+        # then lam~ = lam + lam0, C = A S^T, W = S C
         self.lt = self.lam + self.lam0
         self.c = sketch.right_sketch(a, self.s_rows, self.s_signs, s)
         w = sketch.left_sketch(self.s_rows, self.s_signs, s, self.c)
         self.w = 0.5 * (w + w.T)
-        # line 4: C~ = Phi C, M2 = C~^T C~ + lam~ W, and its inverse
+        # then C~ = Phi C, M2 = C~^T C~ + lam~ W, and its inverse
         self.phi_rows, self.phi_signs = rng.sketch_indices(seed_phi, self.n, phi, phi_gamma)
         self.ct = sketch.left_sketch(self.phi_rows, self.phi_signs, phi, self.c)
         m2 = self.ct.T @ self.ct + self.lt * self.w
@@ -143,7 +143,7 @@ class PsdMsp:
         return self.a @ x + self.lam * x
 
     def solve(self, b) -> KrylovResult:
-        """Algorithm 1, line 5: level-1 iteration on (A + lam I) x = b with SolveM1."""
+        """Algorithm 1, the level-1 iteration on (A + lam I) x = b with SolveM1."""
         b = np.asarray(b, dtype=np.float64)
         self.info = SolveInfo()
         res = fcg(self.op1, b, self.solve_m1, self.opts.tol, self.opts.max_outer,
@@ -173,16 +173,16 @@ class GeneralMsp:
         self.lam = float(lam)
         self.lam0 = float(lam0)
         self.opts = opts or MspOptions()
-        # Algorithm 3, line 2: lam~
+        # Algorithm 3: lam~
         self.lt = self.lam + self.lam0
-        # line 3: S (s x n)
+        # then S (s x n)
         self.s_rows, self.s_signs = rng.sketch_indices(seed_s, self.n, s, gamma)
         self.s = s
-        # line 4: A~ = A S^T (m x s), A^ = Phi A~ (phi x s), Phi over the m rows
+        # then A~ = A S^T (m x s), A^ = Phi A~ (phi x s), Phi over the m rows
         self.at = sketch.right_sketch(a, self.s_rows, self.s_signs, s)
         self.phi_rows, self.phi_signs = rng.sketch_indices(seed_phi, self.m, phi, phi_gamma)
         self.ah = sketch.left_sketch(self.phi_rows, self.phi_signs, phi, self.at)
-        # lines 5-6: M3a = A^^T A^, M3b = M3a + lam~ I and their inverses
+        # then M3a = A^^T A^, M3b = M3a + lam~ I and their inverses
         m3a = self.ah.T @ self.ah
         self.m3a = 0.5 * (m3a + m3a.T)
         self.m3b = self.m3a + self.lt * np.eye(s)
@@ -209,7 +209,7 @@ class GeneralMsp:
         return (u.x - v.x) / self.lt
 
     def op2(self, y):
-        """A~^T A A^T A~ y + lam~ A~^T A~ y (Algorithm 4, line 2)."""
+        """A~^T A A^T A~ y + lam~ A~^T A~ y (the operator of Algorithm 4)."""
         t = self.at @ y
         return self.at.T @ (self.a @ (self.a.T @ t)) + self.lt * (self.at.T @ t)
 
@@ -225,7 +225,7 @@ class GeneralMsp:
         return self.a.T @ (self.a @ x) + self.lam * x
 
     def solve_normal(self, c) -> KrylovResult:
-        """Algorithm 3, line 7: level-1 iteration on (A^T A + lam I) x = c."""
+        """Algorithm 3, the level-1 iteration on (A^T A + lam I) x = c."""
         c = np.asarray(c, dtype=np.float64)
         self.info = SolveInfo()
         res = fcg(self.op1, c, self.solve_m1, self.opts.tol, self.opts.max_outer,

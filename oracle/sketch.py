@@ -23,14 +23,14 @@ def dense_embedding(rows, signs, s) -> np.ndarray:
 
 
 def right_sketch(a: np.ndarray, rows: np.ndarray, signs: np.ndarray, s: int) -> np.ndarray:
-    """C = A S^T (Algorithm 1, line 3; Algorithm 3, line 4 names it A-tilde):
+    """C = A S^T (Algorithm 1; Algorithm 3 names it A-tilde):
     column j of C sums sign/sqrt(gamma) * A[:, i] over the columns i that S maps to j."""
     S = embedding_matrix(rows, signs, s)
     return np.asarray((S @ a.T).T)
 
 
 def left_sketch(rows: np.ndarray, signs: np.ndarray, s: int, x: np.ndarray) -> np.ndarray:
-    """S X for a tall X (n x k): W = S C (Algorithm 1, line 3), C~ = Phi C (line 4),
-    A^ = Phi A~ (Algorithm 3, line 4)."""
+    """S X for a tall X (n x k): W = S C and C~ = Phi C (Algorithm 1),
+    A^ = Phi A~ (Algorithm 3)."""
     S = embedding_matrix(rows, signs, s)
     return np.asarray(S @ x)

@@ -786,7 +786,7 @@ struct Batch {
     y_z(c);
   }
 
-  // ---- level 1 (Algorithm 1 line 5): (A_lo + lam I) x = rhs, x -> zh ---------------
+  // ---- level 1 (the level-1 iteration of Algorithm 1): (A_lo + lam I) x = rhs, x -> zh ---------------
   // skip (shared, may be null): columns not to solve. With confirm, convergence is
   // checked on rhs - (A_hi + lam I) x recomputed in FP64; restarts from it otherwise.
   static __device__ void level1(Ctx& c, const double* rhs, int64_t ldr, double tol, const int* skip, bool confirm) {

@@ -1,5 +1,5 @@
 // Small dense FP64 work on s x s matrices: the Gram products C~^T C~ and A^^T A^
-// (Algorithm 1 line 4, Algorithm 3 line 5), symmetric combinations, and the explicit
+// (Algorithms 1 and 3), symmetric combinations, and the explicit
 // SPD inverses M2^{-1}, M3a^{-1}, M3b^{-1} the algorithms precompute.
 //
 // The inverse is computed by block Gauss-Jordan sweeps without pivoting. For SPD M

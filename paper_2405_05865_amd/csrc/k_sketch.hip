@@ -1,5 +1,5 @@
 // Sparse embedding (Definition 2.1): index draw, bucket lists, and the two sparse
-// products of the method: Y = A S^T (Algorithm 1 line 3, Algorithm 3 line 4) and
+// products of the method: Y = A S^T (Algorithms 1 and 3) and
 // row gathers S X / Phi X on a tall X (W = S C, C~ = Phi C, A^ = Phi A~).
 #include "msp_internal.h"
 

@@ -357,13 +357,13 @@ extern "C" msp_status msp_nystrom(void* stream, msp_structure structure, int64_t
   };
   const double sphi = 1.0 / std::sqrt((double)phi_gamma);
   if (structure == MSP_SYM_PSD) {
-    // Algorithm 1 line 3: W = S C (bucket lists of S, then a row gather of C)
+    // Algorithm 1: W = S C (bucket lists of S, then a row gather of C)
     SketchWs sk = carve_sketch(w, n, s, gamma);
     if (!w.ok()) return fail(msp_fail(MSP_ERR_WORKSPACE, "workspace overflow"));
     hipError_t e = build_buckets(st, S_rows, S_signs, n, s, gamma, sk.b, sk.scratch);
     if (e == hipSuccess) e = launch_gather_rows(st, Y, y_t, ldy, s, s, sk.b, 1.0 / std::sqrt((double)gamma), o.Wm, s);
     if (e == hipSuccess) e = launch_symmetrize(st, s, o.Wm);
-    // line 4: C~ = Phi C, then C~^T C~
+    // Algorithm 1: C~ = Phi C, then C~^T C~
     if (e == hipSuccess) e = launch_sketch_gen(st, phi_seed, n, phi, phi_gamma, o.phi_rows, o.phi_signs);
     if (e == hipSuccess) e = build_buckets(st, o.phi_rows, o.phi_signs, n, phi, phi_gamma, o.sk_Phi.b, o.sk_Phi.scratch);
     if (e == hipSuccess) e = launch_gather_rows(st, Y, y_t, ldy, s, phi, o.sk_Phi.b, sphi, o.small, s);
@@ -374,7 +374,7 @@ extern "C" msp_status msp_nystrom(void* stream, msp_structure structure, int64_t
       if (r != MSP_OK) return fail(r);
     }
   } else {
-    // Algorithm 3 lines 4-5: A^ = Phi A~ over the m rows, M3a = A^^T A^
+    // Algorithm 3: A^ = Phi A~ over the m rows, M3a = A^^T A^
     hipError_t e = launch_sketch_gen(st, phi_seed, m, phi, phi_gamma, o.phi_rows, o.phi_signs);
     if (e == hipSuccess) e = build_buckets(st, o.phi_rows, o.phi_signs, m, phi, phi_gamma, o.sk_Phi.b, o.sk_Phi.scratch);
     if (e == hipSuccess) e = launch_gather_rows(st, Y, y_t, ldy, s, phi, o.sk_Phi.b, sphi, o.small, s);
@@ -1113,7 +1113,7 @@ msp_status psd_solve_m1(SolveCtx& c, const double* r, double* z) {
   return MSP_OK;
 }
 
-// Algorithm 1 line 5: level-1 FCG on (A_sw + lam I) X = B, confirmed on A_cf. X -> L1.x
+// The level-1 iteration of Algorithm 1: FCG on (A_sw + lam I) X = B, confirmed on A_cf. X -> L1.x
 msp_status psd_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int max_outer) {
   Level& L = c.L1;
   const int64_t n = c.n, k = c.k;
@@ -1188,7 +1188,7 @@ msp_status gen_solve_m2(SolveCtx& c, const double* r, double* z, const int32_t* 
   return MSP_OK;
 }
 
-// q2 = A~^T A A^T A~ p2 + lam~ A~^T A~ p2   (Algorithm 4, line 2)
+// q2 = A~^T A A^T A~ p2 + lam~ A~^T A~ p2   (the operator of Algorithm 4)
 msp_status gen_op2(SolveCtx& c, const double* p2, double* q2, const int32_t* skip) {
   const msp_precond* P = c.P;
   const int64_t m = c.m, n = c.n, s = c.s, k = c.k;
@@ -1269,7 +1269,7 @@ msp_status gen_op1(SolveCtx& c, const double* p, double* q, double* t, const int
   return MSP_OK;
 }
 
-// Algorithm 3 line 7. normal == 0: A x = B (B m x k) with the stop on |B - A x|;
+// The level-1 iteration of Algorithm 3. normal == 0: A x = B (B m x k) with the stop on |B - A x|;
 // normal != 0: (A^T A + lam I) x = B (B n x k). X -> L1.x
 msp_status gen_core(SolveCtx& c, const double* B, int64_t ldb, double tol, int max_outer, bool normal) {
   Level& L = c.L1;

@@ -1,4 +1,4 @@
-"""Pins of the sparse embedding products (Definition 2.1, Algorithm 1 line 3)."""
+"""Pins of the sparse embedding products (Definition 2.1, Algorithm 1)."""
 import numpy as np
 import pytest
 
