@@ -217,12 +217,13 @@ def test_two_kernel_level3_steps_match_the_generic_step(n, s, nrhs):
     assert abs(i2["outer_iters"] - i0["outer_iters"]) <= 2
 
 
-@pytest.mark.parametrize("n,s,nrhs", [(1100, 1025, 8), (2100, 2048, 8), (1700, 1600, 12)])
+@pytest.mark.parametrize("n,s,nrhs", [(1100, 1025, 8), (2100, 2048, 8), (1700, 1600, 12), (700, 513, 16)])
 def test_two_kernel_level3_steps_at_large_s(n, s, nrhs):
     # the two-kernel level-3 step over several 512-column segments: s = 1025 (three segments,
     # the last one column wide, one row per wavefront), s = 2048 (four segments, four rows per
-    # wavefront) and s = 1600 with 12 right-hand sides (four segments, two rows per wavefront,
-    # two passes of 8 and 4 columns), against the generic step; phi = n keeps the matrix small
+    # wavefront), s = 1600 with 12 right-hand sides (four segments, two rows per wavefront,
+    # two passes of 8 and 4 columns) and s = 513 with 16 (a one-column second segment, two
+    # full passes), against the generic step; phi = n keeps the matrix small
     say(f"case two-kernel level-3 steps n={n} s={s} k={nrhs}")
     # a milder spread (singular values 1 .. 100) keeps the full solves to seconds
     a, sv, _, _ = W.general_outlier(n, 64, config_id=110, big=(1e1, 1e2))
