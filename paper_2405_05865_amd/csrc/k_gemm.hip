@@ -268,10 +268,14 @@ __global__ void __launch_bounds__(WAVE) k_gemm_sum(const double* __restrict__ pa
 // segments of the reduction range: double until the launch has about 8 wavefronts per CU
 // (measured at n = 32768, 16 RHS: 2048 wavefronts stream faster than 8192 once every step
 // reads whole cache lines), each segment keeps >= min_seg columns and the partials fit the
-// scratch
+// scratch. Products of cache-resident matrices (the s x s operators of the inner levels,
+// min_seg = kSegSmall) stop at about 4 wavefronts per CU: at s = 1024 and 512 columns fewer,
+// longer segments write and re-read fewer partials (a Schatten-1 block run 6% faster than
+// with 2048 wavefronts; 512 and 256 were slower)
 int gemm_segments(int64_t rows, int64_t cols, int k, int64_t waves, size_t scratch_doubles, int min_seg) {
+  const int64_t target = min_seg <= kSegSmall ? 1024 : 2048;
   int nseg = 1;
-  while (waves * nseg < 2048 && nseg < 64 && cols / (2 * nseg) >= min_seg &&
+  while (waves * nseg < target && nseg < 64 && cols / (2 * nseg) >= min_seg &&
          (size_t)(2 * nseg) * (size_t)k * (size_t)rows <= scratch_doubles)
     nseg *= 2;
   return nseg;
