@@ -23,8 +23,8 @@
 // where they read them (every reader of an element forms it with the same expression, so
 // every copy has the same bits). The dots are linear in q and z and are taken on the partials.
 // Within a kernel every global load that does not wait on the per-column scalars is issued
-// first; the wavefront's rpw x 8 row dots are finished by one halving butterfly (31
-// exchanges for 32 values instead of six per value). At s = 2048 and 8 columns, four rows
+// first; the wavefront's rpw x 8 row dots are finished by one halving butterfly (32
+// exchanges for 32 values instead of 192). At s = 2048 and 8 columns, four rows
 // per wavefront (256 blocks, one per CU) measured fastest: more blocks with fewer rows each
 // stage the vector more often and run in several rounds.
 // p and r alternate between two buffers by step parity (a block reads the previous vector
