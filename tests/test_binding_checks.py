@@ -71,3 +71,12 @@ def test_batched_checks_every_system():
         msp.solve_batched([(_psd(), bad, None, _vec(64, 2)), (_psd(), good, None, _vec(64, 2))])
     with pytest.raises(ValueError, match="shape"):
         msp.solve_batched_backward([(_psd(), bad, None)], [_vec(64, 2)], [_vec(64, 2)])
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_sketch_checks_the_matrix(autotune):
+    # a host matrix or a column-major view never reaches msp_sketch / msp_sketch_autotune
+    with pytest.raises(ValueError, match="CUDA|HIP"):
+        msp.sketch(torch.zeros((64, 64), dtype=torch.float64), 8, 4, 1, autotune=autotune)
+    with pytest.raises(ValueError, match="row-major"):
+        msp.sketch(torch.zeros((64, 64), dtype=torch.float64).t(), 8, 4, 1, autotune=autotune)
