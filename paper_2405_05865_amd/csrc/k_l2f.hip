@@ -16,9 +16,9 @@
 // differs. Both kernels are bound by latency, not bandwidth (the s x s operands stay in the
 // caches between steps), so the work is cut for short dependent chains in many blocks: a block
 // of eight wavefronts takes rpw rows per wavefront and one segment of kL2fSegW operator
-// columns. It stages only its segment of the vector it multiplies (formed on the fly from the
-// vectors that define it), so the LDS per block and the LDS reads per row are those of
-// s = kL2fSegW at any s. The products are left as one partial per column segment: q_t and
+// columns (kL2fSegWSmall when s <= kL2fSegW, for more blocks on the small operators). It
+// stages only its segment of the vector it multiplies (formed on the fly from the vectors
+// that define it), so the LDS per block and the LDS reads per row do not grow with s. The products are left as one partial per column segment: q_t and
 // z_{t+1} exist only as the fixed-order sums of their nseg partials, which the consumers form
 // where they read them (every reader of an element forms it with the same expression, so
 // every copy has the same bits). The dots are linear in q and z and are taken on the partials.
@@ -38,12 +38,17 @@ constexpr int NWV = kL2fRows;     // wavefronts per block
 constexpr int NT = NWV * WAVE;
 constexpr int KG = 8;             // columns per staging pass
 constexpr int KM = kL2fMaxK;      // columns per launch
-constexpr int SEGW = kL2fSegW;    // operator columns per block
-constexpr int MAXSEG = (kL2fMaxS + SEGW - 1) / SEGW;
-constexpr int SPT = KG * SEGW / NT;  // staged elements per thread
+// operator columns per block: kL2fSegW, or kL2fSegWSmall for s <= kL2fSegW (more blocks
+// for the small operators); at most MAXSEG segments either way
+constexpr int MAXSEG = (kL2fMaxS + kL2fSegW - 1) / kL2fSegW;
+static_assert((kL2fSegW + kL2fSegWSmall - 1) / kL2fSegWSmall <= MAXSEG, "segment counts");
 
-static_assert(KG * SEGW % NT == 0, "the staging pass is whole per thread");
-static_assert(SEGW % WAVE == 0, "segment columns are whole per lane");
+template <int SW>
+struct Seg {
+  static constexpr int SPT = KG * SW / NT;  // staged elements per thread
+  static_assert(KG * SW % NT == 0, "the staging pass is whole per thread");
+  static_assert(SW % WAVE == 0, "segment columns are whole per lane");
+};
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -93,14 +98,14 @@ __device__ __forceinline__ double seg_sum(const double* __restrict__ part, int64
 // the loads of one staging pass, issued before anything that waits on them: u at the
 // segment's elements (j0 + jj, c0 + cc) of this thread and, with want_part, the sum of the
 // NS partials there; zero outside the kg columns and the segment
-template <int NS>
+template <int NS, int SW>
 __device__ __forceinline__ void load_seg(const double* __restrict__ u, const double* __restrict__ part, bool want_part,
-                                         int64_t sk, int j0, int kg, int c0, int cw, int s, double (&uv)[SPT],
-                                         double (&gv)[SPT]) {
+                                         int64_t sk, int j0, int kg, int c0, int cw, int s,
+                                         double (&uv)[Seg<SW>::SPT], double (&gv)[Seg<SW>::SPT]) {
 #pragma unroll
-  for (int q = 0; q < SPT; ++q) {
+  for (int q = 0; q < Seg<SW>::SPT; ++q) {
     const int idx = (int)threadIdx.x + q * NT;
-    const int jj = idx / SEGW, cc = idx % SEGW;
+    const int jj = idx / SW, cc = idx % SW;
     uv[q] = 0.0;
     gv[q] = 0.0;
     if (jj < kg && cc < cw) {
@@ -112,12 +117,12 @@ __device__ __forceinline__ void load_seg(const double* __restrict__ u, const dou
 }
 
 // h[m][i] = M[row_i][c0 + lane + 64 m] (zero outside the matrix), rows row_i = row0 + NWV i
-template <int RPW>
+template <int RPW, int SW>
 __device__ __forceinline__ void load_rows(const double* __restrict__ M, int s, int row0, int c0, int cw,
-                                          double (&h)[SEGW / WAVE][RPW]) {
+                                          double (&h)[SW / WAVE][RPW]) {
   const int lane = threadIdx.x % WAVE;
 #pragma unroll
-  for (int m = 0; m < SEGW / WAVE; ++m) {
+  for (int m = 0; m < SW / WAVE; ++m) {
     const int cc = lane + WAVE * m;
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
@@ -129,8 +134,8 @@ __device__ __forceinline__ void load_rows(const double* __restrict__ M, int s, i
 
 // acc[i][jj] = sum over the segment's columns of h[.][i] xs[jj][.] (xs is zero outside the
 // live columns and the segment)
-template <int RPW>
-__device__ __forceinline__ void row_dots(const double (&h)[SEGW / WAVE][RPW], const double* xs,
+template <int RPW, int SW>
+__device__ __forceinline__ void row_dots(const double (&h)[SW / WAVE][RPW], const double* xs,
                                          double (&acc)[RPW][KG]) {
   const int lane = threadIdx.x % WAVE;
 #pragma unroll
@@ -138,10 +143,10 @@ __device__ __forceinline__ void row_dots(const double (&h)[SEGW / WAVE][RPW], co
 #pragma unroll
     for (int jj = 0; jj < KG; ++jj) acc[i][jj] = 0.0;
 #pragma unroll
-  for (int m = 0; m < SEGW / WAVE; ++m) {
+  for (int m = 0; m < SW / WAVE; ++m) {
 #pragma unroll
     for (int jj = 0; jj < KG; ++jj) {
-      const double x = xs[jj * SEGW + lane + WAVE * m];
+      const double x = xs[jj * SW + lane + WAVE * m];
 #pragma unroll
       for (int i = 0; i < RPW; ++i) acc[i][jj] = fma(h[m][i], x, acc[i][jj]);
     }
@@ -187,11 +192,11 @@ __device__ __forceinline__ double scatter_sums(double (&v)[NV]) {
 // for the per-column scalars, forms the staged vector and the own-row values, and takes the
 // row products from registers and LDS. Thread tid < KG * RB keeps the own-row element
 // (column j0 + tid / RB, row rbase + tid % RB).
-template <int RPW, int NS>
+template <int RPW, int NS, int SW>
 __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
   constexpr int RB = NWV * RPW;
   static_assert(KG * RB <= NT, "one own-row element per thread");
-  __shared__ double xs[KG * SEGW];
+  __shared__ double xs[KG * SW];
   __shared__ double own[KG][RB];  // p_t at the block's rows
   __shared__ double beta_s[KM];
   __shared__ int live_s[KM];
@@ -203,7 +208,7 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
   const double* pc = a.p[par];
   double* pn = a.p[nxt];
   const int sg = blockIdx.x % NS, rb = blockIdx.x / NS;
-  const int c0 = sg * SEGW, cw = min(SEGW, s - c0);
+  const int c0 = sg * SW, cw = min(SW, s - c0);
   const int rbase = rb * RB, row0 = rbase + w;
   const int ojj = tid / RB, orow = rbase + tid % RB;
   const int64_t sk = (int64_t)s * k;
@@ -211,8 +216,8 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
   for (int j0 = 0; j0 < k; j0 += KG) {
     const int kg = min(KG, k - j0);
     // p_{t-1} and z_t (p_0 alone when fresh) over the segment and at the own rows; H's rows
-    double uv[SPT], gv[SPT];
-    load_seg<NS>(pc, a.zpart, !fresh, sk, j0, kg, c0, cw, s, uv, gv);
+    double uv[Seg<SW>::SPT], gv[Seg<SW>::SPT];
+    load_seg<NS, SW>(pc, a.zpart, !fresh, sk, j0, kg, c0, cw, s, uv, gv);
     const bool oval = tid < KG * RB && ojj < kg && orow < s;
     const int64_t oo = (int64_t)(j0 + ojj) * s + orow;
     double ou = 0.0, og = 0.0;
@@ -220,8 +225,8 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
       ou = pc[oo];
       if (!fresh) og = seg_sum<NS>(a.zpart, sk, oo);
     }
-    double h[SEGW / WAVE][RPW];
-    load_rows<RPW>(a.H, s, row0, c0, cw, h);
+    double h[SW / WAVE][RPW];
+    load_rows<RPW, SW>(a.H, s, row0, c0, cw, h);
     if (j0 == 0) {
       // ---- decision on |r_t| and beta_t (the same in every block): wavefront w takes
       // the columns w, w + NWV ----
@@ -283,9 +288,9 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
     // p_t = z_t + beta_t p_{t-1} (p_0 when fresh): staged, and at the own rows (segment 0
     // stores it)
 #pragma unroll
-    for (int q = 0; q < SPT; ++q) {
+    for (int q = 0; q < Seg<SW>::SPT; ++q) {
       const int idx = tid + q * NT;
-      const int jj = idx / SEGW, cc = idx % SEGW;
+      const int jj = idx / SW, cc = idx % SW;
       const bool on = jj < kg && cc < cw && live_s[j0 + jj];
       xs[idx] = on ? (fresh ? uv[q] : fma(beta_s[j0 + jj], uv[q], gv[q])) : 0.0;
     }
@@ -301,7 +306,7 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
     double v[RPW * KG];
     {
       double acc[RPW][KG];
-      row_dots<RPW>(h, xs, acc);
+      row_dots<RPW, SW>(h, xs, acc);
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
@@ -332,11 +337,11 @@ __global__ void __launch_bounds__(NT) k_l2f_op(L2fArgs a, int t, int fresh) {
   }
 }
 
-template <int RPW, int NS>
+template <int RPW, int NS, int SW>
 __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
   constexpr int RB = NWV * RPW;
   static_assert(KG * RB <= NT, "one own-row element per thread");
-  __shared__ double xs[KG * SEGW];
+  __shared__ double xs[KG * SW];
   __shared__ double own[2][KG][RB];  // r_{t+1} and r_t at the block's rows
   __shared__ double alpha_s[KM];
   __shared__ int live_s[KM];
@@ -349,7 +354,7 @@ __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
   double* rn = a.r[nxt];
   const double* pn = a.p[nxt];
   const int sg = blockIdx.x % NS, rb = blockIdx.x / NS;
-  const int c0 = sg * SEGW, cw = min(SEGW, s - c0);
+  const int c0 = sg * SW, cw = min(SW, s - c0);
   const int rbase = rb * RB, row0 = rbase + w;
   const int ojj = tid / RB, orow = rbase + tid % RB;
   const int64_t sk = (int64_t)s * k;
@@ -358,8 +363,8 @@ __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
     const int kg = min(KG, k - j0);
     // r_t and q_t over the segment and at the own rows (with p_t and y there in segment 0);
     // Minv's rows
-    double uv[SPT], gv[SPT];
-    load_seg<NS>(rc, a.qpart, true, sk, j0, kg, c0, cw, s, uv, gv);
+    double uv[Seg<SW>::SPT], gv[Seg<SW>::SPT];
+    load_seg<NS, SW>(rc, a.qpart, true, sk, j0, kg, c0, cw, s, uv, gv);
     const bool oval = tid < KG * RB && ojj < kg && orow < s;
     const int64_t oo = (int64_t)(j0 + ojj) * s + orow;
     double ou = 0.0, og = 0.0, op = 0.0, oy = 0.0;
@@ -371,8 +376,8 @@ __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
         oy = a.y[oo];
       }
     }
-    double h[SEGW / WAVE][RPW];
-    load_rows<RPW>(a.Minv, s, row0, c0, cw, h);
+    double h[SW / WAVE][RPW];
+    load_rows<RPW, SW>(a.Minv, s, row0, c0, cw, h);
     if (j0 == 0) {
       // alpha_t = <r_t, z_t> / <p_t, q_t> (the same in every block)
       for (int j = w; j < k; j += NWV) {
@@ -408,9 +413,9 @@ __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
     // r_{t+1} = r_t - alpha_t q_t: staged, and at the own rows (segment 0 stores it and
     // y += alpha_t p_t)
 #pragma unroll
-    for (int q = 0; q < SPT; ++q) {
+    for (int q = 0; q < Seg<SW>::SPT; ++q) {
       const int idx = tid + q * NT;
-      const int jj = idx / SEGW, cc = idx % SEGW;
+      const int jj = idx / SW, cc = idx % SW;
       const bool on = jj < kg && cc < cw && live_s[j0 + jj];
       xs[idx] = on ? fma(alpha_s[j0 + jj], gv[q], uv[q]) : 0.0;
     }
@@ -431,7 +436,7 @@ __global__ void __launch_bounds__(NT) k_l2f_prec(L2fArgs a, int t) {
     double v[RPW * KG];
     {
       double acc[RPW][KG];
-      row_dots<RPW>(h, xs, acc);
+      row_dots<RPW, SW>(h, xs, acc);
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
@@ -474,44 +479,49 @@ int pick_rpw(int64_t s, int nseg) {
   return 1;
 }
 
-template <int RPW, int NS>
+template <int RPW, int NS, int SW>
 hipError_t launch_pair(hipStream_t st, const L2fArgs& a, int t, int fresh, bool op) {
   if (op)
-    hipLaunchKernelGGL((k_l2f_op<RPW, NS>), dim3((unsigned)a.nb), dim3(NT), 0, st, a, t, fresh);
+    hipLaunchKernelGGL((k_l2f_op<RPW, NS, SW>), dim3((unsigned)a.nb), dim3(NT), 0, st, a, t, fresh);
   else
-    hipLaunchKernelGGL((k_l2f_prec<RPW, NS>), dim3((unsigned)a.nb), dim3(NT), 0, st, a, t);
+    hipLaunchKernelGGL((k_l2f_prec<RPW, NS, SW>), dim3((unsigned)a.nb), dim3(NT), 0, st, a, t);
   return hipGetLastError();
 }
 
-template <int RPW>
+template <int RPW, int SW>
 hipError_t launch_ns(hipStream_t st, const L2fArgs& a, int t, int fresh, bool op) {
   static_assert(MAXSEG == 4, "one instantiation per segment count");
   switch (a.nseg) {
-    case 1: return launch_pair<RPW, 1>(st, a, t, fresh, op);
-    case 2: return launch_pair<RPW, 2>(st, a, t, fresh, op);
-    case 3: return launch_pair<RPW, 3>(st, a, t, fresh, op);
-    case 4: return launch_pair<RPW, 4>(st, a, t, fresh, op);
+    case 1: return launch_pair<RPW, 1, SW>(st, a, t, fresh, op);
+    case 2: return launch_pair<RPW, 2, SW>(st, a, t, fresh, op);
+    case 3: return launch_pair<RPW, 3, SW>(st, a, t, fresh, op);
+    case 4: return launch_pair<RPW, 4, SW>(st, a, t, fresh, op);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch(hipStream_t st, const L2fArgs& a, int t, int fresh, bool op) {
-  int nseg = 0, rpw = 0, nb = 0;
+  int nseg = 0, rpw = 0, nb = 0, segw = 0;
   if (a.s < 1 || a.s > kL2fMaxS || a.k < 1 || a.k > kL2fMaxK) return hipErrorInvalidValue;
-  l2f_shape(a.s, &nseg, &rpw, &nb);
-  if (a.nseg != nseg || a.rpw != rpw || a.nb != nb) return hipErrorInvalidValue;
+  l2f_shape(a.s, &nseg, &rpw, &nb, &segw);
+  if (a.nseg != nseg || a.rpw != rpw || a.nb != nb || a.segw != segw) return hipErrorInvalidValue;
+  if (a.segw == kL2fSegWSmall) {  // s <= kL2fSegW: one row per wavefront (pick_rpw)
+    if (a.rpw != 1) return hipErrorInvalidValue;
+    return launch_ns<1, kL2fSegWSmall>(st, a, t, fresh, op);
+  }
   switch (a.rpw) {
-    case 1: return launch_ns<1>(st, a, t, fresh, op);
-    case 2: return launch_ns<2>(st, a, t, fresh, op);
-    case 4: return launch_ns<4>(st, a, t, fresh, op);
+    case 1: return launch_ns<1, kL2fSegW>(st, a, t, fresh, op);
+    case 2: return launch_ns<2, kL2fSegW>(st, a, t, fresh, op);
+    case 4: return launch_ns<4, kL2fSegW>(st, a, t, fresh, op);
   }
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-void l2f_shape(int64_t s, int* nseg, int* rpw, int* nb) {
-  *nseg = (int)((s + SEGW - 1) / SEGW);
+void l2f_shape(int64_t s, int* nseg, int* rpw, int* nb, int* segw) {
+  *segw = s <= kL2fSegW ? kL2fSegWSmall : kL2fSegW;
+  *nseg = (int)((s + *segw - 1) / *segw);
   *rpw = pick_rpw(s, *nseg);
   *nb = (int)((s + NWV * *rpw - 1) / (NWV * *rpw)) * *nseg;
 }
@@ -520,7 +530,7 @@ L2fArgs l2f_carve(WsCarver& w, int64_t s, int64_t k) {
   L2fArgs a{};
   a.s = (int)s;
   a.k = (int)k;
-  l2f_shape(s, &a.nseg, &a.rpw, &a.nb);
+  l2f_shape(s, &a.nseg, &a.rpw, &a.nb, &a.segw);
   a.p[1] = w.take<double>(s * k);
   a.rz[0] = w.take<double>(k);
   a.rz[1] = w.take<double>(k);

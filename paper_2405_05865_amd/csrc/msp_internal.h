@@ -382,10 +382,11 @@ hipError_t l2x_publish(hipStream_t st, const L2xArgs& a, int par);
 constexpr int kL2fMaxK = 16;
 constexpr int kL2fMaxS = 2048;
 constexpr int kL2fRows = 8;     // wavefronts per block
-constexpr int kL2fSegW = 512;   // operator columns per block
+constexpr int kL2fSegW = 512;       // operator columns per block
+constexpr int kL2fSegWSmall = 128;  // the same for s <= kL2fSegW (more blocks)
 struct L2fArgs {
   int s, k, nb;
-  int nseg, rpw;   // column segments of kL2fSegW; rows per wavefront (l2f_shape)
+  int nseg, rpw, segw;  // column segments of segw columns; rows per wavefront (l2f_shape)
   const double* H;
   const double* Minv;
   double sigma;
@@ -404,8 +405,9 @@ struct L2fArgs {
   int max_iter;
   int32_t* mirror;  // [2] host-mapped: active columns, largest iteration count
 };
-// the launch shape for s: column segments, rows per wavefront, blocks (row blocks x segments)
-void l2f_shape(int64_t s, int* nseg, int* rpw, int* nb);
+// the launch shape for s: column segments, rows per wavefront, blocks (row blocks x
+// segments), segment width
+void l2f_shape(int64_t s, int* nseg, int* rpw, int* nb, int* segw);
 // carves p[1], rz, alpha, the partials and the int state; the caller sets the rest
 L2fArgs l2f_carve(WsCarver& w, int64_t s, int64_t k);
 // step t: decision on the previous step (fresh = 1 for t = 0: the l2_init state), p_t,
