@@ -187,3 +187,23 @@ def test_orthonormal_columns_drops_a_dependent_direction():
     g = qm.T @ qm
     assert np.count_nonzero(np.abs(np.diag(g)) > 0.5) == 4
     assert np.allclose(g[np.ix_(np.diag(g) > 0.5, np.diag(g) > 0.5)], np.eye(4), atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [0.5, 1.0, 1.5])
+def test_upper_end_leaves_at_most_eps_of_the_top_share(p):
+    # sigma^p = (sin(pi p / 2) / pi) * integral over u of e^{(p/2) u} sigma^2 / (sigma^2 + e^u):
+    # the part above u_hi, integrated directly, is at most eps_q sigma_max^p for every
+    # sigma <= sigma_max, and the whole integral is sigma^p
+    from scipy.integrate import quad
+    smax, eps = 3.0, 1e-4
+    u_hi = trace.upper_end(smax, p, eps_q=eps)
+    c = math.sin(math.pi * p / 2) / math.pi
+    f = lambda u, sig: c * math.exp(0.5 * p * u) * sig * sig / (sig * sig + math.exp(u))
+    for sig in (smax, 0.3 * smax, 1e-2 * smax):
+        tail, _ = quad(f, u_hi, u_hi + 400.0, args=(sig,), limit=400)
+        assert tail <= eps * smax ** p
+        whole = sum(quad(f, a, a + 10.0, args=(sig,), limit=200)[0] for a in np.arange(-200.0, u_hi + 400.0, 10.0))
+        assert whole == pytest.approx(sig ** p, rel=1e-7)
+    # tight to within the factor sin(pi p / 2) / (pi (1 - p / 2)) at sigma = sigma_max
+    tail, _ = quad(f, u_hi, u_hi + 400.0, args=(smax,), limit=400)
+    assert tail >= 0.5 * eps * smax ** p * c / (1 - p / 2)
