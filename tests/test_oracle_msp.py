@@ -317,3 +317,22 @@ def test_lambda0_estimate_against_the_paper_value_on_an_rbf_matrix():
     _, est = _est(a, s)
     paper = msp.paper_lambda0(eigs, s // 2)
     assert 2.0 / (s // 2) * eigs[s:].sum() <= est <= 3.0 * paper
+
+
+def test_spd_inverse_is_the_shifted_inverse():
+    # (M + mu I)^{-1} with mu = shift_rel tr(M) / d: against numpy's inverse of the shifted
+    # matrix, symmetric, and with shift_rel = 0 an exact inverse to kappa * eps
+    rng = np.random.default_rng(31)
+    q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    for spread in (1e2, 1e8):
+        ev = np.geomspace(1.0, spread, 40)
+        m = (q * ev) @ q.T
+        m = 0.5 * (m + m.T)
+        for shift_rel in (0.0, 1e-3):
+            mu = shift_rel * float(np.trace(m)) / 40
+            got = msp.spd_inverse(m, shift_rel)
+            want = np.linalg.inv(m + mu * np.eye(40))
+            assert np.array_equal(got, got.T)
+            kappa = (spread + mu) / (1.0 + mu)
+            assert np.linalg.norm(got - want) <= 100 * kappa * np.finfo(float).eps * np.linalg.norm(want)
+            assert np.linalg.norm(got @ (m + mu * np.eye(40)) - np.eye(40)) <= 100 * kappa * np.finfo(float).eps * 40

@@ -66,3 +66,15 @@ def test_embedding_preserves_norms_on_average():
         rows, signs = rng.sketch_indices(1000 + seed, 400, 40, 4)
         vals.append(np.linalg.norm(sketch.left_sketch(rows, signs, 40, x[:, None])) ** 2)
     assert abs(np.mean(vals) / (x @ x) - 1.0) < 0.05
+
+
+def test_embedding_matrix_entries_follow_the_draws():
+    # column i of S holds sign(i, g) / sqrt(gamma) at row rows(i, g) for the gamma draws, and
+    # nothing else (Definition 2.1); each column has unit norm since its rows are distinct
+    rows = np.array([[0, 3], [2, 1], [3, 0]])
+    signs = np.array([[1, -1], [-1, -1], [1, 1]], dtype=np.int8)
+    S = sketch.embedding_matrix(rows, signs, 4).toarray()
+    r = 1.0 / np.sqrt(2.0)
+    want = np.array([[r, 0, r], [0, -r, 0], [0, -r, 0], [-r, 0, r]])
+    assert np.array_equal(S, want)
+    assert np.allclose(np.linalg.norm(S, axis=0), 1.0)
